@@ -1,0 +1,372 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Nothing here compares the oracle with itself or with the GPU path: each check
+uses a hand-derived value, a closed form, a textbook invariant, an independent
+library routine (LAPACK SVD least squares, scikit-learn's OMP, torch autograd
+and torch.optim.Adam) or brute force.
+"""
+
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import (omp_fp64, clomp_fp64, ClompParams, lstsq_support,
+                    resid_norm_fp64, grad_fp64, adam_step_fp64,
+                    bruteforce_support, well_separated)
+from oracle.omp import ST_ZERO_Y, ST_K_CAPPED, ST_NAN, ST_EARLY_STOP
+from paper_2501_11592_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _parse_golden(name):
+    rows = []
+    for line in open(os.path.join(GOLDEN, name)):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        rows.append([f.strip() for f in line.split("|")])
+    return rows
+
+
+def _vec(s):
+    return np.array([float(v) for v in s.split()]) if s.strip() else np.zeros(0)
+
+
+def _mat_rows(s):
+    return np.array([[float(v) for v in r.split()] for r in s.split(";")])
+
+
+def gaussian_instance(seed, m, n, k):
+    """Noiseless k-sparse Gaussian instance in float64 (y computed in float64)."""
+    g = np.random.default_rng([99, seed, m, n, k])
+    A = g.standard_normal((m, n)) / math.sqrt(m)
+    supp = np.sort(g.choice(n, size=k, replace=False))
+    s = np.zeros(n)
+    s[supp] = g.standard_normal(k)
+    return A, A @ s, supp, s
+
+
+# ------------------------------------------------------------------ golden
+@pytest.mark.parametrize("row", _parse_golden("omp_worked_examples.txt"),
+                         ids=lambda r: r[0])
+def test_omp_worked_examples(row):
+    _, cols, y, k, supp, x, rn = row
+    A = _mat_rows(cols).T
+    y = _vec(y)
+    res = omp_fp64(A, y, int(k))
+    assert res.support == [int(v) for v in supp.split()]
+    np.testing.assert_allclose(res.x, _vec(x), rtol=0, atol=1e-14)
+    assert abs(res.resid_norm - float(rn)) < 1e-14
+    # CLOMP selects the same atoms here and refines to the same least squares
+    cres = clomp_fp64(A, y, int(k), ClompParams(inner_steps=64))
+    assert cres.support == res.support
+    np.testing.assert_allclose(cres.x, _vec(x), rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("row", _parse_golden("grad_worked_example.txt"),
+                         ids=lambda r: r[0])
+def test_grad_worked_example(row):
+    _, Arows, x, mask, y, loss, grad = row
+    l, g, _ = grad_fp64(_vec(x), _vec(mask), _mat_rows(Arows), _vec(y))
+    assert l == float(loss)
+    np.testing.assert_array_equal(g, _vec(grad))
+
+
+# ------------------------------------------------------------------ O6 / a7
+def test_lstsq_matches_svd_lstsq_and_normal_equations():
+    A, y, _, _ = gaussian_instance(1, 40, 100, 6)
+    y = y + np.random.default_rng(3).standard_normal(40) * 0.1
+    S = [5, 17, 3, 88, 41, 60, 12]
+    xq = lstsq_support(A, y, S)
+    xs = np.linalg.lstsq(A[:, S], y, rcond=None)[0]
+    np.testing.assert_allclose(xq, xs, rtol=1e-12, atol=1e-13)
+    r = y - A[:, S] @ xq
+    assert np.max(np.abs(A[:, S].T @ r)) < 1e-12 * np.linalg.norm(A[:, S]) * np.linalg.norm(y)
+    assert abs(resid_norm_fp64(A, y, S, xq) - math.sqrt(float(r @ r))) < 1e-15 * (1 + np.linalg.norm(y))
+    assert resid_norm_fp64(A, y, [], []) == pytest.approx(np.linalg.norm(y), rel=1e-15)
+
+
+# ------------------------------------------------------------------ O3 brute force
+def test_bruteforce_finds_planted_support():
+    A, y, supp, _ = gaussian_instance(2, 8, 14, 3)
+    best, r, table = bruteforce_support(A, y, 3)
+    assert best == list(supp) and r < 1e-12
+    assert len(table) == math.comb(14, 3)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_omp_never_beats_bruteforce_and_matches_on_recoverable(seed):
+    g = np.random.default_rng([5, seed])
+    m, n, k = 7, int(g.integers(10, 17)), int(g.integers(1, 4))
+    A, y, supp, _ = gaussian_instance(seed, m, n, k)
+    noisy = y + 0.3 * g.standard_normal(m)
+    for yy in (y, noisy):
+        best, rbf, _ = bruteforce_support(A, yy, k)
+        res = omp_fp64(A, yy, k)
+        assert res.resid_norm >= rbf - 1e-12
+        if yy is y and sorted(res.support) == list(supp):
+            assert sorted(res.support) == best
+
+
+# ------------------------------------------------------------------ O1 OMP
+def test_omp_exact_recovery_rate_and_accuracy():
+    recovered = 0
+    for seed in range(30):
+        A, y, supp, s = gaussian_instance(seed, 64, 256, 8)
+        res = omp_fp64(A, y, 8)
+        if sorted(res.support) == list(supp):
+            recovered += 1
+            assert np.max(np.abs(res.x - s)) < 1e-10
+    assert recovered >= 28          # OMP recovers m/k = 8 Gaussian instances w.h.p.
+
+
+def test_omp_residual_orthogonal_and_monotone():
+    A, y, _, _ = gaussian_instance(7, 50, 200, 10)
+    y = y + 0.05 * np.random.default_rng(1).standard_normal(50)
+    res = omp_fp64(A, y, 20)
+    hist = [np.linalg.norm(y)] + res.resid_hist
+    assert all(b <= a * (1 + 1e-14) for a, b in zip(hist, hist[1:]))
+    # invariant after the last step (every intermediate step re-solves from scratch)
+    for t in range(1, len(res.support) + 1):
+        S = res.support[:t]
+        xS = lstsq_support(A, y, S)
+        r = y - A[:, S] @ xS
+        assert np.max(np.abs(A[:, S].T @ r)) <= 1e-10 * np.linalg.norm(A[:, S]) * np.linalg.norm(y)
+
+
+def test_omp_full_support_zero_residual():
+    A, y, _, _ = gaussian_instance(11, 12, 30, 4)
+    y = y + np.random.default_rng(2).standard_normal(12)
+    res = omp_fp64(A, y, 12)
+    assert len(res.support) == 12 and res.resid_norm < 1e-12 * np.linalg.norm(y)
+
+
+def test_omp_matches_sklearn_on_well_separated():
+    from sklearn.linear_model import orthogonal_mp
+    checked = 0
+    for seed in range(20):
+        A, y, _, _ = gaussian_instance(seed, 64, 256, 8)
+        y = y + 0.01 * np.random.default_rng(seed).standard_normal(64)
+        ok, res = well_separated(A, y, 8, method="omp", delta=1e-3)
+        if not ok:
+            continue
+        checked += 1
+        coef = orthogonal_mp(A, y, n_nonzero_coefs=8)
+        assert sorted(np.flatnonzero(coef).tolist()) == sorted(res.support)
+        np.testing.assert_allclose(res.x, coef, rtol=0, atol=1e-10)
+    assert checked >= 10
+
+
+def test_omp_flags():
+    A, y, _, _ = gaussian_instance(3, 6, 20, 2)
+    r = omp_fp64(A, np.zeros(6), 3)
+    assert r.status & ST_ZERO_Y and r.support == [] and not r.x.any()
+    r = omp_fp64(A, y, 9)
+    assert r.status & ST_K_CAPPED and len(r.support) == 6
+    yn = y.copy()
+    yn[2] = np.nan
+    assert omp_fp64(A, yn, 2).status & ST_NAN
+    r = omp_fp64(A, y, 6, resid_tol=1e-9)
+    assert r.status & ST_EARLY_STOP and len(r.support) < 6
+    assert r.resid_norm <= 1e-9 * np.linalg.norm(y)
+
+
+# ------------------------------------------------------------------ O4 / O5
+def test_grad_central_differences_exact_for_quadratic():
+    A, y, _, _ = gaussian_instance(4, 9, 15, 3)
+    g = np.random.default_rng(8)
+    x = g.standard_normal(15)
+    mask = g.random(15) < 0.5
+    _, grad, _ = grad_fp64(x, mask, A, y)
+    h = 1e-3
+    for j in range(15):
+        e = np.zeros(15)
+        e[j] = h
+        lp = grad_fp64(x + e, mask, A, y)[0]
+        lm = grad_fp64(x - e, mask, A, y)[0]
+        assert abs((lp - lm) / (2 * h) - grad[j]) < 1e-9
+    assert not grad[~mask].any()
+
+
+def test_grad_matches_torch_autograd():
+    torch = pytest.importorskip("torch")
+    A, y, _, _ = gaussian_instance(5, 11, 23, 3)
+    g = np.random.default_rng(9)
+    x = g.standard_normal(23)
+    mask = (g.random(23) < 0.6).astype(np.float64)
+    xt = torch.tensor(x, requires_grad=True)
+    loss = 0.5 * ((torch.tensor(A) @ (torch.tensor(mask) * xt) - torch.tensor(y)) ** 2).sum()
+    loss.backward()
+    l, gr, _ = grad_fp64(x, mask, A, y)
+    assert abs(l - loss.item()) <= 1e-14 * abs(l)
+    np.testing.assert_allclose(gr, xt.grad.numpy(), rtol=1e-13, atol=1e-14)
+
+
+def test_adam_matches_torch_optim_adam():
+    torch = pytest.importorskip("torch")
+    g = np.random.default_rng(10)
+    grads = [g.standard_normal(7) * (1 + 10 * (i % 3)) for i in range(50)]
+    grads[5][2] = 0.0
+    p = torch.zeros(7, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([p], lr=0.03, betas=(0.9, 0.999), eps=1e-6, foreach=False)
+    th, m, v = np.zeros(7), np.zeros(7), np.zeros(7)
+    for i, gr in enumerate(grads):
+        p.grad = torch.tensor(gr)
+        opt.step()
+        th, m, v = adam_step_fp64(th, gr, m, v, i + 1, 0.03, 0.9, 0.999, 1e-6)
+    np.testing.assert_allclose(th, p.detach().numpy(), rtol=1e-12, atol=1e-15)
+
+
+def test_adam_zero_gradient_coordinates_do_not_move():
+    th, m, v = adam_step_fp64(np.array([1.5, -2.0]), np.array([0.0, 3.0]),
+                              np.zeros(2), np.zeros(2), 1, 0.1, 0.9, 0.999, 1e-8)
+    assert th[0] == 1.5 and m[0] == 0.0 and v[0] == 0.0
+
+
+# ------------------------------------------------------------------ O2 CLOMP
+def test_clomp_exact_inner_reduces_to_omp():
+    for seed in range(6):
+        A, y, _, _ = gaussian_instance(seed, 30, 90, 6)
+        y = y + 0.02 * np.random.default_rng(seed).standard_normal(30)
+        a = omp_fp64(A, y, 8)
+        b = clomp_fp64(A, y, 8, inner="exact")
+        assert a.support == b.support
+        np.testing.assert_allclose(a.x, b.x, rtol=0, atol=1e-14)
+        assert abs(a.resid_norm - b.resid_norm) < 1e-14
+
+
+def test_clomp_orthonormal_dictionary_closed_form():
+    """With orthonormal columns the correlation of an unselected column is
+    a_j^T y whatever s is, so CLOMP selects the k largest |a_j^T y| in
+    decreasing order and refines to x_S = A_S^T y, for any Adam trajectory."""
+    g = np.random.default_rng(12)
+    Q, _ = np.linalg.qr(g.standard_normal((20, 20)))
+    y = g.standard_normal(20)
+    c = Q.T @ y
+    order = list(np.argsort(-np.abs(c), kind="stable")[:7])
+    for T in (1, 3, 32):
+        res = clomp_fp64(Q, y, 7, ClompParams(inner_steps=T))
+        assert res.support == [int(j) for j in order]
+        np.testing.assert_allclose(res.x[order], c[order], rtol=0, atol=1e-13)
+        assert not np.delete(res.x, order).any()
+
+
+def test_clomp_first_adam_step_closed_form():
+    """From s = m = v = 0 the first Adam step on the single selected column j
+    moves s_j by lr * c_j / (|c_j| + eps), with g = -c_j."""
+    A, y, _, _ = gaussian_instance(13, 10, 40, 3)
+    p = ClompParams(inner_steps=1, lr_rel=0.05, eps_rel=1e-3)
+    res = clomp_fp64(A, y, 1, p)
+    c = A.T @ y
+    j = int(np.argmax(np.abs(c)))
+    sigma = abs(c[j])
+    lr, eps = 0.05 * sigma, 1e-3 * sigma
+    assert res.support == [j]
+    assert abs(res.extra["s_adam"][0] - lr * c[j] / (abs(c[j]) + eps)) < 1e-15 * sigma
+
+
+def test_clomp_matches_autograd_and_torch_adam_rendering():
+    """Independent rendering of the paper's CLOMP with framework pieces: s is a
+    torch parameter of n entries, the forward is A (mask * s), the loss is
+    1/2 ||y' - y||^2, backward by autograd, update by torch.optim.Adam."""
+    torch = pytest.importorskip("torch")
+    for seed in range(3):
+        A, y, _, _ = gaussian_instance(seed, 16, 48, 4)
+        y = y + 0.01 * np.random.default_rng(seed).standard_normal(16)
+        P = ClompParams(inner_steps=12, lr_rel=0.05)
+        ref = clomp_fp64(A, y, 5, P)
+        At, yt = torch.tensor(A), torch.tensor(y)
+        s = torch.zeros(48, dtype=torch.float64, requires_grad=True)
+        mask = torch.zeros(48, dtype=torch.float64)
+        opt = None
+        S = []
+        for t in range(5):
+            with torch.no_grad():
+                c = At.T @ (yt - At @ (mask * s))
+                score = c.abs().clone()
+                score[mask.bool()] = -float("inf")
+                j = int(torch.argmax(score))
+                if t == 0:
+                    sig = float(c.abs().max())
+                    opt = torch.optim.Adam([s], lr=0.05 * sig, betas=(0.9, 0.999),
+                                           eps=1e-8 * sig, foreach=False)
+                mask[j] = 1.0
+                S.append(j)
+            for _ in range(12):
+                opt.zero_grad()
+                loss = 0.5 * ((At @ (mask * s) - yt) ** 2).sum()
+                loss.backward()
+                opt.step()
+        assert S == ref.support
+        np.testing.assert_allclose(s.detach().numpy()[S], ref.extra["s_adam"],
+                                   rtol=1e-11, atol=1e-13)
+
+
+def test_clomp_power_of_two_scaling_equivariance():
+    A, y, _, _ = gaussian_instance(14, 32, 128, 6)
+    y = y + 0.01 * np.random.default_rng(0).standard_normal(32)
+    a = clomp_fp64(A, y, 8)
+    for p in (-7, 3, 20):
+        b = clomp_fp64(A, y * 2.0 ** p, 8)
+        assert b.support == a.support
+        np.testing.assert_array_equal(b.extra["s_adam"], a.extra["s_adam"] * 2.0 ** p)
+        np.testing.assert_allclose(b.x, a.x * 2.0 ** p, rtol=1e-14, atol=0)
+
+
+def test_clomp_column_permutation_equivariance():
+    A, y, _, _ = gaussian_instance(15, 24, 80, 5)
+    perm = np.random.default_rng(4).permutation(80)
+    a = clomp_fp64(A, y, 6)
+    b = clomp_fp64(A[:, perm], y, 6)
+    assert [int(perm[j]) for j in b.support] == a.support
+    np.testing.assert_allclose(b.x, a.x[perm], rtol=0, atol=1e-12)
+
+
+def test_clomp_exact_recovery_noiseless():
+    recovered = 0
+    for seed in range(20):
+        A, y, supp, s = gaussian_instance(seed, 64, 256, 8)
+        res = clomp_fp64(A, y, 8)
+        if sorted(res.support) == list(supp):
+            recovered += 1
+            assert np.max(np.abs(res.x - s)) < 1e-10
+            assert res.resid_norm < 1e-12
+    assert recovered >= 17
+
+
+def test_clomp_bf16_style_refinement_uses_master():
+    """Selection on a perturbed copy, refinement on the master: the final x is
+    the master least squares on the selected support."""
+    A, y, _, _ = gaussian_instance(16, 40, 120, 5)
+    Ab = A * (1 + 2.0 ** -8 * np.random.default_rng(1).choice([-1, 1], A.shape))
+    res = clomp_fp64(Ab, y, 5, A_refine=A)
+    np.testing.assert_allclose(res.x[res.support], lstsq_support(A, y, res.support),
+                               rtol=0, atol=1e-14)
+    assert abs(res.resid_norm - resid_norm_fp64(A, y, res.support, res.x[res.support])) < 1e-15
+
+
+def test_clomp_flags():
+    A, y, _, _ = gaussian_instance(17, 6, 20, 2)
+    r = clomp_fp64(A, np.zeros(6), 3)
+    assert r.status & ST_ZERO_Y and r.support == []
+    r = clomp_fp64(A, y, 10)
+    assert r.status & ST_K_CAPPED and len(r.support) == 6
+
+
+def test_workload_generators_are_deterministic():
+    a = W.single_small(3)
+    b = W.single_small(3)
+    np.testing.assert_array_equal(a.At, b.At)
+    np.testing.assert_array_equal(a.y, b.y)
+    assert a.At.shape == (256, 64) and a.At.dtype == np.float32
+    sb = W.image_batch(0.1)
+    assert sb.m == 26 and sb.At.shape == (256, 32) and sb.Y.shape == (256, 26)
+    assert not sb.At[:, 26:].any()
+    specs = W.uneven_specs(64)
+    for sp in specs:
+        assert 512 <= sp.n <= 8192 and 0.09 * sp.n <= sp.m <= 0.51 * sp.n
+        assert math.ceil(sp.n / 64) <= sp.k <= sp.n // 16
