@@ -1,0 +1,212 @@
+/*
+ * clomp.h -- C ABI of the MI355X (gfx950) CLOMP hot-path library.
+ *
+ * CLOMP (coefficients-learning OMP, arXiv 2501.11592) reconstructs a sparse
+ * coefficient vector x from measurements y = A x + noise (Methods, Eq. (1));
+ * the ABI writes the paper's s as x.  Reconstruction seeks the fewest non-zeros
+ * with ||A x - y||_2 small (Eq. (2)); a batch of signals may share one A
+ * (Eq. (3)).  Like OMP, CLOMP takes y and A and returns x (Methods, end of
+ * "Coefficients learning on OMP (CLOMP)").
+ *
+ * Conventions for every entry point
+ *  - Pointers are DEVICE pointers unless marked (host).  Arrays are owned by
+ *    the caller; the library never frees them and keeps no reference after
+ *    the call returns, except that device work queued on `hip_stream` reads
+ *    and writes them until that work completes.
+ *  - A is stored column-major: column (atom) j occupies A[j*lda .. j*lda+m),
+ *    entries [m, lda) of each column are ignored.  A must hold n*lda elements,
+ *    lda must be a multiple of 4 (F32) or 8 (BF16) and A must be 16-byte
+ *    aligned.  BF16 values are raw bfloat16 bit patterns (uint16).
+ *  - Calls are asynchronous and stream-ordered on `hip_stream` (NULL: the
+ *    default stream); outputs are valid once that stream has been
+ *    synchronised.  A handle must not be used by two host threads at once.
+ *  - Every entry point returns a clomp_status_t synchronously for argument,
+ *    allocation and launch errors; no exception crosses the ABI.  A
+ *    human-readable message for the last failure is kept per handle
+ *    (clomp_last_error).  Numerical events are reported per instance through
+ *    the CLOMP_ST_* bits, never through the return code.
+ */
+#ifndef CLOMP_H_
+#define CLOMP_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct clomp_ctx* clomp_handle_t;
+
+typedef enum {
+  CLOMP_OK = 0,
+  CLOMP_INVALID_ARGUMENT = 1,  /* null pointer, bad size, layout or alignment */
+  CLOMP_OUT_OF_MEMORY = 2,     /* workspace allocation failed */
+  CLOMP_DEVICE_ERROR = 3,      /* a HIP call failed (message in last_error) */
+  CLOMP_NOT_SUPPORTED = 4      /* valid request this build does not serve */
+} clomp_status_t;
+
+typedef enum { CLOMP_F32 = 0, CLOMP_BF16 = 1, CLOMP_F64 = 2 } clomp_dtype_t;
+
+typedef enum {
+  CLOMP_METHOD_CLOMP = 0,  /* Adam steps on the masked coefficients */
+  CLOMP_METHOD_OMP = 1     /* plain OMP: least squares on the support */
+} clomp_method_t;
+
+/* Per-instance status bits (written to clomp_instance_t.status). */
+#define CLOMP_ST_NAN 1u              /* a non-finite correlation was selected */
+#define CLOMP_ST_K_CAPPED 2u         /* k > min(m, n): k_eff = min(k, m, n)   */
+#define CLOMP_ST_ZERO_Y 4u           /* y == 0: empty support, x = 0          */
+#define CLOMP_ST_REFINE_INACCURATE 8u/* refinement stopped above tolerance    */
+#define CLOMP_ST_WATCHDOG 32u        /* a bounded device wait timed out       */
+
+/* Solver flags (clomp_params_t.flags). */
+#define CLOMP_FLAG_GRAPH 1u          /* capture the launch sequence of a batch
+                                        shape into a HIP graph and replay it on
+                                        later calls with the same shape        */
+#define CLOMP_FLAG_NO_FUSED_SMALL 2u /* never use the one-workgroup-per-signal
+                                        kernel (for testing the general path)  */
+#define CLOMP_FLAG_AUTOTUNE 4u       /* time the scan-kernel candidates on the
+                                        first call for each size class         */
+
+/*
+ * Solver parameters.  The paper states the optimiser only as automatic
+ * differentiation and back-propagation on learnable s (Methods, "Coefficients
+ * learning on OMP"); everything below is this library's fixed reading, the
+ * same values the reference oracle uses:
+ *   method       CLOMP (default) or plain OMP
+ *   inner_steps  T, Adam steps per selected atom (default 32)
+ *   lr_rel       learning rate lr = lr_rel * sigma, sigma = max_j |a_j^T y|
+ *                (default 0.05)
+ *   beta1/beta2  Adam moment decays (0.9 / 0.999); eps = eps_rel * sigma
+ *                (eps_rel default 1e-8)
+ *   resid_tol    must be 0 (early stopping on ||r|| is not served)
+ *   refine_iters maximum CGLS iterations of the final refinement for supports
+ *                too large for the in-LDS QR (0: library default)
+ *   refine_tol   relative CGLS stopping tolerance on ||A_S^T r|| (0: 1e-6)
+ */
+typedef struct {
+  int32_t method;
+  int32_t inner_steps;
+  float lr_rel;
+  float beta1;
+  float beta2;
+  float eps_rel;
+  float resid_tol;
+  int32_t refine_iters;
+  float refine_tol;
+  uint32_t flags;
+} clomp_params_t;
+
+/*
+ * One signal of a batch (all pointers device pointers).
+ *   n, m, k      atoms, measurements, requested sparsity; k_eff = min(k, m, n)
+ *   A, lda       bulk matrix (dtype given to clomp_solve_batch), column-major
+ *   A_master     FP32 master copy used for the final refinement and the FP64
+ *                residual check; NULL means A (the bulk dtype must be F32)
+ *   lda_master   leading dimension of A_master (0: lda)
+ *   y            [m] FP32 measurements
+ *   x            [n] FP32 out: coefficients, zero off the support
+ *   support      [k] int32 out: selected atoms in selection order, -1 beyond
+ *                the number selected
+ *   n_selected   [1] int32 out
+ *   resid_norm   [1] float64 out: ||y - A_master[:, S] x_S||_2 accumulated in
+ *                FP64 (the residual of Eq. (2))
+ *   status       [1] uint32 out: CLOMP_ST_* bits
+ */
+typedef struct {
+  int32_t n, m, k;
+  int32_t reserved;
+  int64_t lda;
+  int64_t lda_master;
+  const void* A;
+  const float* A_master;
+  const float* y;
+  float* x;
+  int32_t* support;
+  int32_t* n_selected;
+  double* resid_norm;
+  uint32_t* status;
+} clomp_instance_t;
+
+/* Fill *p (host) with the defaults listed above. */
+void clomp_default_params(clomp_params_t* p);
+
+/*
+ * Create a handle bound to HIP device `device` with parameters *params (host;
+ * NULL: defaults).  The handle owns its device workspace (grown on demand,
+ * freed by clomp_destroy) and any captured HIP graphs.
+ * Errors: INVALID_ARGUMENT (out == NULL, bad params), DEVICE_ERROR (no such
+ * device / HIP failure).
+ */
+clomp_status_t clomp_create(clomp_handle_t* out, int device,
+                            const clomp_params_t* params);
+
+/* Replace the handle's parameters (host pointer, validated as in create). */
+clomp_status_t clomp_set_params(clomp_handle_t h, const clomp_params_t* params);
+
+/*
+ * Solve `count` independent signals (the batched model of Eq. (3)/(4) with
+ * per-signal A, or one shared A when every instance names the same A, n, m and
+ * lda).  For each instance, k_eff = min(k, m, n) iterations of
+ *   c = A^T r                               (residual injection)
+ *   j = argmax over unselected atoms of |c_j|, lowest index on ties
+ *   mask[j] = 1                             (mask update by OR)
+ *   CLOMP: inner_steps Adam steps on the masked coefficients fitting
+ *          1/2 ||A(mask*x) - y||^2;  OMP: least squares on the support
+ *   r = y - A(mask*x)
+ * run on the bulk A, followed by a least-squares refinement of x on the
+ * selected support from A_master and the FP64 residual norm.
+ *   inst    (host) array of `count` descriptors, read during the call only
+ *   a_dtype CLOMP_F32 or CLOMP_BF16 (the bulk dtype of every instance)
+ * Errors: INVALID_ARGUMENT (null pointers, n/m/k <= 0, lda < m, misaligned A,
+ * BF16 without A_master, count < 0), NOT_SUPPORTED (F64 bulk, resid_tol != 0),
+ * OUT_OF_MEMORY, DEVICE_ERROR.  count == 0 is a no-op returning CLOMP_OK.
+ */
+clomp_status_t clomp_solve_batch(clomp_handle_t h, const clomp_instance_t* inst,
+                                 int32_t count, int32_t a_dtype,
+                                 void* hip_stream);
+
+/*
+ * Host-only validation of a batch (no HIP call): returns what
+ * clomp_solve_batch would return for the arguments alone.  `h` may be NULL;
+ * messages then go nowhere.
+ */
+clomp_status_t clomp_check_batch(clomp_handle_t h, const clomp_instance_t* inst,
+                                 int32_t count, int32_t a_dtype);
+
+/*
+ * Loss and gradient of the coefficient fit (the residual loss of the
+ * coefficients-learning framework with the masked fully connected layer
+ * y' = A(mask*x); Methods, "General idea of coefficients learning" and
+ * "Coefficients learning on OMP"):
+ *   u      = A(mask*x) - y                         ([m], optional output)
+ *   loss   = 1/2 ||u||^2                           (scalar output)
+ *   grad_x = mask * A^T u * g                      ([n] output)
+ * where g = *grad_out (device scalar) or 1 when grad_out is NULL.
+ *   dtype  CLOMP_F32 or CLOMP_F64: the type of A, x, y, grad_out, grad_x,
+ *          resid_out and loss (F64 exists for gradient checking)
+ *   mask   [n] uint8, non-zero = on the support
+ * Deterministic: the same inputs give bit-identical outputs.
+ * Errors: INVALID_ARGUMENT (null required pointer, n/m <= 0, lda < m,
+ * misaligned A), NOT_SUPPORTED (BF16), DEVICE_ERROR.
+ */
+clomp_status_t clomp_grad(clomp_handle_t h, int32_t n, int32_t m, int64_t lda,
+                          int32_t dtype, const void* A, const void* x,
+                          const uint8_t* mask, const void* y,
+                          const void* grad_out, void* grad_x, void* resid_out,
+                          void* loss, void* hip_stream);
+
+/* Free the handle, its workspace and graphs (synchronises its device). */
+clomp_status_t clomp_destroy(clomp_handle_t h);
+
+/* Static string naming a status code. */
+const char* clomp_status_string(clomp_status_t s);
+
+/* Message of the last failure on `h` ("" if none; static text if h is NULL). */
+const char* clomp_last_error(clomp_handle_t h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CLOMP_H_ */

@@ -1,0 +1,273 @@
+"""Thin Python binding of libclomp.so (ctypes): argument marshalling only.
+
+Every step of the solve runs in the library's HIP kernels.  torch supplies
+device memory and the stream; there is no CPU or PyTorch fallback: if the
+library has not been built, or no GPU is present, calls raise.
+
+Storage convention: a measurement matrix A (m x n) is passed atom-major as a
+tensor `At` of shape (n, lda) -- row j holds column a_j -- which is A stored
+column-major with leading dimension lda >= m.
+"""
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libclomp.so")
+
+F32, BF16, F64 = 0, 1, 2
+METHOD_CLOMP, METHOD_OMP = 0, 1
+ST_NAN, ST_K_CAPPED, ST_ZERO_Y, ST_REFINE_INACCURATE, ST_WATCHDOG = 1, 2, 4, 8, 32
+FLAG_GRAPH, FLAG_NO_FUSED_SMALL, FLAG_AUTOTUNE = 1, 2, 4
+
+STATUS_NAMES = {0: "CLOMP_OK", 1: "CLOMP_INVALID_ARGUMENT", 2: "CLOMP_OUT_OF_MEMORY",
+                3: "CLOMP_DEVICE_ERROR", 4: "CLOMP_NOT_SUPPORTED"}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("inner_steps", ctypes.c_int32),
+                ("lr_rel", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps_rel", ctypes.c_float),
+                ("resid_tol", ctypes.c_float), ("refine_iters", ctypes.c_int32),
+                ("refine_tol", ctypes.c_float), ("flags", ctypes.c_uint32)]
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("lda", ctypes.c_int64),
+                ("lda_master", ctypes.c_int64), ("A", ctypes.c_void_p),
+                ("A_master", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("x", ctypes.c_void_p), ("support", ctypes.c_void_p),
+                ("n_selected", ctypes.c_void_p), ("resid_norm", ctypes.c_void_p),
+                ("status", ctypes.c_void_p)]
+
+
+class ClompError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Open libclomp.so once; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ClompError(f"{path} is missing: build it with "
+                         "`python -m paper_2501_11592_amd.build`")
+    lib = ctypes.CDLL(path)
+    H = ctypes.c_void_p
+    lib.clomp_default_params.argtypes = [ctypes.POINTER(Params)]
+    lib.clomp_default_params.restype = None
+    lib.clomp_create.argtypes = [ctypes.POINTER(H), ctypes.c_int, ctypes.POINTER(Params)]
+    lib.clomp_create.restype = ctypes.c_int
+    lib.clomp_set_params.argtypes = [H, ctypes.POINTER(Params)]
+    lib.clomp_set_params.restype = ctypes.c_int
+    lib.clomp_solve_batch.argtypes = [H, ctypes.POINTER(Instance), ctypes.c_int32,
+                                      ctypes.c_int32, ctypes.c_void_p]
+    lib.clomp_solve_batch.restype = ctypes.c_int
+    lib.clomp_check_batch.argtypes = [H, ctypes.POINTER(Instance), ctypes.c_int32,
+                                      ctypes.c_int32]
+    lib.clomp_check_batch.restype = ctypes.c_int
+    lib.clomp_grad.argtypes = [H, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                               ctypes.c_int32] + [ctypes.c_void_p] * 9
+    lib.clomp_grad.restype = ctypes.c_int
+    lib.clomp_destroy.argtypes = [H]
+    lib.clomp_destroy.restype = ctypes.c_int
+    lib.clomp_status_string.argtypes = [ctypes.c_int]
+    lib.clomp_status_string.restype = ctypes.c_char_p
+    lib.clomp_last_error.argtypes = [H]
+    lib.clomp_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def default_params():
+    p = Params()
+    load_library().clomp_default_params(ctypes.byref(p))
+    return p
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _check(h, rc, what):
+    if rc != 0:
+        lib = load_library()
+        msg = lib.clomp_last_error(h).decode() if h else ""
+        raise ClompError(f"{what}: {STATUS_NAMES.get(rc, rc)}: {msg}")
+
+
+def dtype_code(t):
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.bfloat16:
+        return BF16
+    if t.dtype == torch.float64:
+        return F64
+    raise ClompError(f"unsupported dtype {t.dtype}")
+
+
+@dataclass
+class BatchResult:
+    x: list            # per instance: float32 tensor (n,)
+    support: list      # per instance: int32 tensor (k,)
+    n_selected: torch.Tensor
+    resid_norm: torch.Tensor
+    status: torch.Tensor
+
+
+class Solver:
+    """A library handle bound to one device, holding the solver parameters."""
+
+    def __init__(self, device=0, method="clomp", inner_steps=32, lr_rel=0.05,
+                 beta1=0.9, beta2=0.999, eps_rel=1e-8, refine_iters=0,
+                 refine_tol=0.0, flags=0):
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise ClompError("no GPU available: the CLOMP library runs only on the device")
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        p = default_params()
+        p.method = METHOD_OMP if method == "omp" else METHOD_CLOMP
+        p.inner_steps, p.lr_rel, p.beta1, p.beta2 = inner_steps, lr_rel, beta1, beta2
+        p.eps_rel, p.refine_iters, p.refine_tol, p.flags = eps_rel, refine_iters, refine_tol, flags
+        self.params = p
+        h = ctypes.c_void_p()
+        _check(None, lib.clomp_create(ctypes.byref(h), self.device.index or 0, ctypes.byref(p)),
+               "clomp_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().clomp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, **kw):
+        for key, v in kw.items():
+            if key == "method":
+                v = METHOD_OMP if v == "omp" else METHOD_CLOMP
+            setattr(self.params, key, v)
+        _check(self._h, load_library().clomp_set_params(self._h, ctypes.byref(self.params)),
+               "clomp_set_params")
+
+    # ------------------------------------------------------------------ solve
+    def solve_batch(self, items, stream=None):
+        """items: list of dicts with keys At (n, lda) float32|bfloat16 cuda tensor,
+        m, y (m,) float32, k, optional At_master (n, lda_master) float32.
+        Outputs are allocated here and returned as views of packed tensors."""
+        count = len(items)
+        if count == 0:
+            return BatchResult([], [], *(torch.empty(0, device=self.device),) * 3)
+        dt = dtype_code(items[0]["At"])
+        ns = [int(it["At"].shape[0]) for it in items]
+        ks = [int(it["k"]) for it in items]
+        dev = self.device
+        x_all = torch.empty(sum(ns), dtype=torch.float32, device=dev)
+        sup_all = torch.empty(sum(ks), dtype=torch.int32, device=dev)
+        nsel = torch.empty(count, dtype=torch.int32, device=dev)
+        rnorm = torch.empty(count, dtype=torch.float64, device=dev)
+        status = torch.empty(count, dtype=torch.int32, device=dev)
+        arr = (Instance * count)()
+        xs, sups = [], []
+        xo = so = 0
+        for i, it in enumerate(items):
+            At = it["At"]
+            if dtype_code(At) != dt:
+                raise ClompError("all instances of a batch must share the bulk dtype")
+            Am = it.get("At_master")
+            d = arr[i]
+            d.n, d.m, d.k = ns[i], int(it["m"]), ks[i]
+            d.lda = int(At.stride(0))
+            d.lda_master = int(Am.stride(0)) if Am is not None else 0
+            d.A = At.data_ptr()
+            d.A_master = Am.data_ptr() if Am is not None else None
+            d.y = it["y"].data_ptr()
+            xs.append(x_all[xo:xo + ns[i]])
+            sups.append(sup_all[so:so + ks[i]])
+            d.x = x_all.data_ptr() + 4 * xo
+            d.support = sup_all.data_ptr() + 4 * so
+            d.n_selected = nsel.data_ptr() + 4 * i
+            d.resid_norm = rnorm.data_ptr() + 8 * i
+            d.status = status.data_ptr() + 4 * i
+            xo += ns[i]
+            so += ks[i]
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        rc = load_library().clomp_solve_batch(self._h, arr, count, dt,
+                                              ctypes.c_void_p(st.cuda_stream))
+        _check(self._h, rc, "clomp_solve_batch")
+        # keep inputs alive until the queued work is done
+        self._keep = items
+        return BatchResult(xs, sups, nsel, rnorm, status)
+
+    def solve(self, At, m, y, k, At_master=None, stream=None):
+        r = self.solve_batch([dict(At=At, m=m, y=y, k=k, At_master=At_master)], stream)
+        return dict(x=r.x[0], support=r.support[0], n_selected=r.n_selected[0],
+                    resid_norm=r.resid_norm[0], status=r.status[0])
+
+    def solve_shared(self, At, m, Y, k, At_master=None, stream=None):
+        """All rows of Y (a, m) share one matrix (the multi-signal model)."""
+        items = [dict(At=At, m=m, y=Y[c], k=k, At_master=At_master) for c in range(Y.shape[0])]
+        return self.solve_batch(items, stream)
+
+    # ------------------------------------------------------------------ grad
+    def grad(self, At, m, x, mask, y, grad_out=None, want_resid=True, stream=None):
+        """Returns (loss, grad_x, u) with u = A(mask*x) - y."""
+        dt = dtype_code(At)
+        n = int(At.shape[0])
+        dev = At.device
+        gx = torch.empty(n, dtype=At.dtype, device=dev)
+        loss = torch.empty((), dtype=At.dtype, device=dev)
+        u = torch.empty(m, dtype=At.dtype, device=dev) if want_resid else None
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        rc = load_library().clomp_grad(self._h, n, m, int(At.stride(0)), dt, _ptr(At), _ptr(x),
+                                       _ptr(mask), _ptr(y), _ptr(grad_out), _ptr(gx), _ptr(u),
+                                       _ptr(loss), ctypes.c_void_p(st.cuda_stream))
+        _check(self._h, rc, "clomp_grad")
+        return loss, gx, u
+
+
+def check_batch(items_ctypes, count, dtype, handle=None):
+    """Host-only validation (no HIP call); returns the status code."""
+    return load_library().clomp_check_batch(handle, items_ctypes, count, dtype)
+
+
+_default = {}
+
+
+def solver_for(device=0, **kw):
+    key = (device, tuple(sorted(kw.items())))
+    if key not in _default:
+        _default[key] = Solver(device, **kw)
+    return _default[key]
+
+
+class ClompLoss(torch.autograd.Function):
+    """loss = 1/2 ||A(mask*x) - y||^2 with the hand-written HIP backward.
+
+    forward(x, mask, At, m, y): At is (n, lda) atom-major, fixed (no gradient);
+    mask is uint8 (n,).  Gradients: grad_x = mask * A^T u * g, grad_y = -u * g.
+    """
+
+    @staticmethod
+    def forward(ctx, x, mask, At, m, y):
+        solver = solver_for(x.device.index or 0)
+        loss, gx, u = solver.grad(At, m, x.contiguous(), mask.contiguous(), y.contiguous())
+        ctx.save_for_backward(gx, u)
+        return loss
+
+    @staticmethod
+    def backward(ctx, g):
+        gx, u = ctx.saved_tensors
+        return gx * g, None, None, None, -u * g

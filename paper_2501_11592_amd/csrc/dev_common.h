@@ -1,0 +1,163 @@
+// Device-side data structures and small helpers shared by the CLOMP kernels.
+//
+// Layout in HBM (one workspace block per instance, every sub-array 256-byte
+// aligned; all indices are local to the instance):
+//   r      [m_pad]       float   residual y - A(mask*s) (zero beyond m)
+//   G      [k_eff*ldg]   float   Gram matrix A_S^T A_S of the bulk columns,
+//                                column-major, both triangles stored
+//   b      [k_eff]       float   A_S^T y
+//   s,mo,ve[k_eff]       float   coefficients and Adam moments, selection order
+//   xf     [k_eff]       float   refined coefficients
+//   Linv   [k_eff*ldg]   float   OMP: inverse Cholesky factor of G (lower)
+//   z      [k_eff]       float   OMP: Linv * b
+//   cg     [...]         float   CGLS vectors (two r, two p, q, sv)
+//   bitmap [ceil(n/32)]  uint32  selected-atom mask
+//   key    u64           packed argmax key of the current scan
+//   st     InstState     scalar state (sigma, lr, eps, step, flags)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace clomp {
+
+constexpr int kBlock = 256;     // threads per workgroup for every solver kernel
+constexpr int kWaves = kBlock / 64;
+
+struct InstState {
+  float sigma, lr, eps;
+  int step;
+  int done;        // 1: the instance has nothing more to do (y == 0)
+  int cg_done;     // 1: refinement converged
+  float gamma[2];  // CGLS ||A_S^T r||^2, ping-pong by iteration parity
+  float gamma0;
+  int pad[7];
+};
+
+struct Inst {
+  const void* A;       // bulk matrix (float or bf16 bits), column-major
+  const float* Am;     // FP32 master (== A for FP32 bulk)
+  const float* y;
+  float* x;
+  int* support;
+  int* nsel;
+  double* rnorm;
+  unsigned* status;
+  long long lda, ldam;
+  int n, m, k, k_eff;
+  int ldg, m_pad, n_rowtiles, cg_slot;   // cg_slot: index in the refinement list
+  float* r;
+  float* G;
+  float* b;
+  float* s;
+  float* mo;
+  float* ve;
+  float* xf;
+  float* Linv;
+  float* z;
+  float* cg;           // r0[m_pad] r1[m_pad] q[m_pad] p0[k] p1[k] sv[k]
+  double* npart;       // [n_rowtiles] FP64 residual-norm partial sums
+  float* qpart;        // [n_rowtiles] CGLS ||q||^2 partial sums
+  unsigned long long* key;
+  unsigned* bitmap;
+  InstState* st;
+};
+
+// A scan tile: atoms [j0, j1) of instance `inst`.
+struct ScanTile {
+  int inst, j0, j1, pad;
+};
+
+// A row tile: rows [i0, i1) (at most 64) of instance `inst`.
+struct RowTile {
+  int inst, i0, i1, tile;
+};
+
+enum : unsigned {
+  ST_NAN = 1u, ST_K_CAPPED = 2u, ST_ZERO_Y = 4u, ST_REFINE_INACCURATE = 8u,
+  ST_WATCHDOG = 32u
+};
+
+// ---- vector loads of the bulk matrix: 16 bytes per lane per load ----------
+template <typename TA> struct Vec;
+
+template <> struct Vec<float> {
+  static constexpr int W = 4;
+  __device__ static inline void load(const float* p, float v[4]) {
+    const float4 q = *reinterpret_cast<const float4*>(p);
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+  }
+  __device__ static inline float one(const float* p) { return *p; }
+};
+
+template <> struct Vec<uint16_t> {   // bfloat16 bit patterns
+  static constexpr int W = 8;
+  __device__ static inline void load(const uint16_t* p, float v[8]) {
+    const uint4 q = *reinterpret_cast<const uint4*>(p);
+    v[0] = __uint_as_float(q.x << 16); v[1] = __uint_as_float(q.x & 0xffff0000u);
+    v[2] = __uint_as_float(q.y << 16); v[3] = __uint_as_float(q.y & 0xffff0000u);
+    v[4] = __uint_as_float(q.z << 16); v[5] = __uint_as_float(q.z & 0xffff0000u);
+    v[6] = __uint_as_float(q.w << 16); v[7] = __uint_as_float(q.w & 0xffff0000u);
+  }
+  __device__ static inline float one(const uint16_t* p) {
+    return __uint_as_float(((unsigned)*p) << 16);
+  }
+};
+
+// ---- argmax key: (bits of |c|) << 32 | (0xFFFFFFFF - j) ---------------------
+// Non-negative floats order like their bit patterns, NaN (sign cleared) ranks
+// above +Inf, and the low word makes the lowest index win among equal |c|.
+__device__ inline unsigned long long pack_key(float c, int j) {
+  const unsigned a = __float_as_uint(c) & 0x7fffffffu;
+  return ((unsigned long long)a << 32) | (unsigned long long)(0xffffffffu - (unsigned)j);
+}
+__device__ inline int key_index(unsigned long long key) {
+  return (int)(0xffffffffu - (unsigned)(key & 0xffffffffull));
+}
+__device__ inline float key_value(unsigned long long key) {
+  return __uint_as_float((unsigned)(key >> 32));
+}
+
+template <int W>
+__device__ inline float group_sum(float v) {
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
+  return v;
+}
+
+__device__ inline unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long u = __shfl_xor(v, o, 64);
+    v = u > v ? u : v;
+  }
+  return v;
+}
+
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block-wide float sum in a fixed order (deterministic).  `red` holds kWaves
+// floats of shared memory.  Every thread returns the total.
+__device__ inline float block_sum(float v, float* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  float t = 0.f;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) t += red[i];
+  return t;
+}
+
+}  // namespace clomp

@@ -1,0 +1,39 @@
+// Host-side launch wrappers of the CLOMP kernels (defined next to the kernels).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+namespace clomp {
+
+struct Inst;
+struct ScanTile;
+struct RowTile;
+
+hipError_t launch_init(const Inst* d, int count, hipStream_t s);
+hipError_t launch_scan(int bf16, int lpa, const Inst* d, const ScanTile* tiles, int ntiles,
+                       int r_lds_floats, hipStream_t s);
+hipError_t launch_gram(int bf16, int lpa, const Inst* d, int nact, int t, int nblk, int D,
+                       int v_lds_floats, float lr_rel, float eps_rel, hipStream_t s);
+hipError_t launch_adam(const Inst* d, int nact, int t, int T, float beta1, float beta2,
+                       hipStream_t s);
+hipError_t launch_omp(const Inst* d, int nact, int t, hipStream_t s);
+hipError_t launch_resid(int bf16, const Inst* d, const RowTile* tiles, int ntiles, int t,
+                        hipStream_t s);
+hipError_t launch_cg_rows(int mode, const Inst* d, const RowTile* tiles, int ntiles, int tmax,
+                          int it, float tol2, hipStream_t s);
+hipError_t launch_cg_dots(int mode, int lpa, const Inst* d, const int* list, int nlist, int tmax,
+                          int nblk, int D, int m_pad_max, int it, hipStream_t s);
+hipError_t launch_copy_s(const Inst* d, const int* list, int nlist, hipStream_t s);
+hipError_t launch_qr(const Inst* d, const int* list, int nlist, size_t lds_bytes, hipStream_t s);
+hipError_t launch_norm(const Inst* d, const RowTile* tiles, int ntiles, int tmax, hipStream_t s);
+hipError_t launch_finalize(const Inst* d, int count, int check_cg, hipStream_t s);
+hipError_t set_max_lds(size_t bytes);
+
+// clomp_grad kernels
+hipError_t launch_grad(int f64, int n, int m, long long lda, const void* A, const void* x,
+                       const unsigned char* mask, const void* y, const void* grad_out,
+                       void* grad_x, void* resid_out, void* loss, void* work, int ncolchunk,
+                       int colchunk, hipStream_t s);
+
+}  // namespace clomp

@@ -1,0 +1,687 @@
+// Host runtime of the CLOMP library: argument validation, workspace layout,
+// the static per-iteration schedule, kernel launches, optional HIP-graph
+// capture/replay, and the C ABI declared in include/clomp.h.
+//
+// Scheduling.  Every instance runs exactly k_eff = min(k, m, n) greedy
+// iterations, so the whole schedule is known on the host before any launch.
+// Instances are grouped by the scan lane-width class (lanes per atom, chosen
+// from m) and sorted by k_eff descending inside a class; at iteration t the
+// active instances of a class are then a prefix of it, and so are its scan
+// tiles and row tiles.  Each phase kernel of iteration t is launched once per
+// class over that prefix: no per-iteration tables are needed, and the same
+// launch sequence can be captured once and replayed for every batch of the
+// same shape.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/clomp.h"
+#include "dev_common.h"
+#include "kernels.h"
+
+using namespace clomp;
+
+namespace {
+
+constexpr int kMaxKeff = kBlock * 8;        // Adam kernel row capacity
+constexpr size_t kAlign = 256;
+constexpr int kScanTargetBytes = 128 * 1024; // bulk bytes streamed per scan WG
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+int round_up_int(int v, int a) { return (v + a - 1) / a * a; }
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Class {
+  int lpa = 64;
+  int i0 = 0, i1 = 0;                 // sorted-instance range
+  std::vector<int> tile_prefix;       // scan tiles of the first q instances
+  std::vector<int> row_prefix;        // row tiles of the first q instances
+  size_t tile_off = 0, row_off = 0;   // offsets of the arrays in the table blob
+  int m_pad_max = 0;
+  int kmax = 0;
+};
+
+struct Plan {
+  std::vector<Inst> insts;            // sorted (class, k_eff desc)
+  std::vector<int> keff;              // per sorted instance
+  std::vector<Class> classes;
+  std::vector<ScanTile> tiles;
+  std::vector<RowTile> rows;          // loop row tiles (all instances)
+  std::vector<int> qr_list, cg_list;
+  std::vector<RowTile> cg_rows;       // row tiles of CGLS instances
+  size_t qr_lds = 0;
+  int kmax = 0, cg_tmax = 0, cg_mpad_max = 0, cg_lpa = 64;
+  size_t ws_bytes = 0;
+  size_t off_insts = 0, off_tiles = 0, off_rows = 0, off_qr = 0, off_cg = 0, off_cgrows = 0;
+  size_t table_bytes = 0;
+  std::string sig;                    // shape signature (graph cache key)
+};
+
+struct CachedGraph {
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+};
+
+}  // namespace
+
+struct clomp_ctx {
+  int device = 0;
+  clomp_params_t params{};
+  std::string last_error;
+  DevBuf ws, tables;
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  hipEvent_t staging_free = nullptr;  // last upload from `pinned` finished
+  hipEvent_t work_done = nullptr;     // last launch sequence finished
+  bool have_work = false;
+  int lds_limit = 65536;
+  int num_cu = 256;
+  DevBuf gwork;
+  std::map<std::string, CachedGraph> graphs;
+};
+
+namespace {
+
+clomp_status_t fail(clomp_ctx* h, clomp_status_t s, const char* fmt, ...) {
+  if (h) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    h->last_error = buf;
+  }
+  return s;
+}
+
+clomp_status_t hip_fail(clomp_ctx* h, hipError_t e, const char* what) {
+  return fail(h, CLOMP_DEVICE_ERROR, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                         \
+  do {                                              \
+    hipError_t e_ = (expr);                         \
+    if (e_ != hipSuccess) return hip_fail(h, e_, what); \
+  } while (0)
+
+clomp_status_t check_params(clomp_ctx* h, const clomp_params_t* p) {
+  if (!p) return fail(h, CLOMP_INVALID_ARGUMENT, "params is NULL");
+  if (p->method != CLOMP_METHOD_CLOMP && p->method != CLOMP_METHOD_OMP)
+    return fail(h, CLOMP_INVALID_ARGUMENT, "unknown method %d", p->method);
+  if (p->inner_steps < 0 || p->inner_steps > 100000)
+    return fail(h, CLOMP_INVALID_ARGUMENT, "inner_steps %d out of range", p->inner_steps);
+  if (!(p->beta1 >= 0.f && p->beta1 < 1.f) || !(p->beta2 >= 0.f && p->beta2 < 1.f))
+    return fail(h, CLOMP_INVALID_ARGUMENT, "Adam betas must lie in [0, 1)");
+  if (!(p->lr_rel >= 0.f) || !(p->eps_rel > 0.f))
+    return fail(h, CLOMP_INVALID_ARGUMENT, "lr_rel must be >= 0 and eps_rel > 0");
+  if (p->refine_iters < 0 || !(p->refine_tol >= 0.f))
+    return fail(h, CLOMP_INVALID_ARGUMENT, "refine_iters/refine_tol must be >= 0");
+  if (p->resid_tol != 0.f)
+    return fail(h, CLOMP_NOT_SUPPORTED, "resid_tol != 0 (early stopping) is not served");
+  return CLOMP_OK;
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+clomp_status_t check_batch_impl(clomp_ctx* h, const clomp_instance_t* inst, int32_t count,
+                                int32_t a_dtype) {
+  if (count < 0) return fail(h, CLOMP_INVALID_ARGUMENT, "count < 0");
+  if (count == 0) return CLOMP_OK;
+  if (!inst) return fail(h, CLOMP_INVALID_ARGUMENT, "inst is NULL");
+  if (a_dtype == CLOMP_F64)
+    return fail(h, CLOMP_NOT_SUPPORTED, "F64 bulk matrices are not served by the solver");
+  if (a_dtype != CLOMP_F32 && a_dtype != CLOMP_BF16)
+    return fail(h, CLOMP_INVALID_ARGUMENT, "unknown dtype %d", a_dtype);
+  const int q = (a_dtype == CLOMP_BF16) ? 8 : 4;
+  for (int i = 0; i < count; ++i) {
+    const clomp_instance_t& I = inst[i];
+    if (I.n <= 0 || I.m <= 0 || I.k <= 0)
+      return fail(h, CLOMP_INVALID_ARGUMENT, "instance %d: n, m, k must be positive", i);
+    if (I.lda < I.m || I.lda % q)
+      return fail(h, CLOMP_INVALID_ARGUMENT,
+                  "instance %d: lda must be >= m and a multiple of %d", i, q);
+    if (!I.A || !aligned16(I.A))
+      return fail(h, CLOMP_INVALID_ARGUMENT, "instance %d: A is NULL or not 16-byte aligned", i);
+    if (!I.y || !I.x || !I.support || !I.n_selected || !I.resid_norm || !I.status)
+      return fail(h, CLOMP_INVALID_ARGUMENT, "instance %d: a required pointer is NULL", i);
+    if (a_dtype == CLOMP_BF16 && !I.A_master)
+      return fail(h, CLOMP_INVALID_ARGUMENT, "instance %d: BF16 bulk needs A_master", i);
+    if (I.A_master) {
+      const int64_t ldm = I.lda_master ? I.lda_master : I.lda;
+      if (ldm < I.m || ldm % 4 || !aligned16(I.A_master))
+        return fail(h, CLOMP_INVALID_ARGUMENT,
+                    "instance %d: A_master needs lda_master >= m, a multiple of 4, 16-byte "
+                    "alignment", i);
+    }
+    const int keff = std::min(I.k, std::min(I.m, I.n));
+    if (keff > kMaxKeff)
+      return fail(h, CLOMP_NOT_SUPPORTED, "instance %d: k_eff = %d exceeds %d", i, keff,
+                  kMaxKeff);
+  }
+  return CLOMP_OK;
+}
+
+int pick_lpa(int m, int vw) {
+  const int nvec = (m + vw - 1) / vw;
+  int lpa = 64;
+  while (lpa > 4 && lpa * 4 > nvec) lpa >>= 1;
+  return lpa;
+}
+
+// Build the plan (host tables + workspace layout) for one batch.
+void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16, Plan& P) {
+  const clomp_params_t& prm = h->params;
+  const bool omp = prm.method == CLOMP_METHOD_OMP;
+  const int vw = bf16 ? 8 : 4;
+  const size_t esize = bf16 ? 2 : 4;
+  // order: by class (lpa desc), then k_eff desc, then input index
+  std::vector<int> order(count);
+  std::vector<int> lpa(count), keff(count);
+  for (int i = 0; i < count; ++i) {
+    order[i] = i;
+    lpa[i] = pick_lpa(inst[i].m, vw);
+    keff[i] = std::min(inst[i].k, std::min(inst[i].m, inst[i].n));
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (lpa[a] != lpa[b]) return lpa[a] > lpa[b];
+    return keff[a] > keff[b];
+  });
+  const int qr_limit_floats = ((int)std::min<size_t>((size_t)h->lds_limit, 96 * 1024) - 1024) / 4;
+  P.insts.resize(count);
+  P.keff.resize(count);
+  P.kmax = 0;
+  size_t ws = 0;
+  char sigbuf[96];
+  P.sig.clear();
+  snprintf(sigbuf, sizeof sigbuf, "d%d;m%d;T%d;", bf16, prm.method, prm.inner_steps);
+  P.sig += sigbuf;
+  for (int s = 0; s < count; ++s) {
+    const int i = order[s];
+    const clomp_instance_t& src = inst[i];
+    Inst d;
+    memset(&d, 0, sizeof d);
+    d.A = src.A;
+    d.Am = src.A_master ? src.A_master : reinterpret_cast<const float*>(src.A);
+    d.ldam = src.A_master ? (src.lda_master ? src.lda_master : src.lda) : src.lda;
+    d.y = src.y;
+    d.x = src.x;
+    d.support = src.support;
+    d.nsel = src.n_selected;
+    d.rnorm = src.resid_norm;
+    d.status = src.status;
+    d.lda = src.lda;
+    d.n = src.n;
+    d.m = src.m;
+    d.k = src.k;
+    d.k_eff = keff[i];
+    d.ldg = round_up_int(d.k_eff, 4);
+    d.m_pad = round_up_int(d.m, 8);
+    d.n_rowtiles = (d.m + 63) / 64;
+    const bool use_qr = (size_t)d.m * d.k_eff + d.m + 2 * d.k_eff <= (size_t)qr_limit_floats;
+    d.cg_slot = use_qr ? -1 : 0;
+    // workspace offsets (relative; rebased after allocation)
+    auto take = [&](size_t bytes) {
+      const size_t o = ws;
+      ws = align_up(ws + bytes, kAlign);
+      return o;
+    };
+    const size_t o_r = take(sizeof(float) * 2 * d.m_pad);
+    const size_t o_G = take(sizeof(float) * (size_t)d.k_eff * d.ldg);
+    const size_t o_b = take(sizeof(float) * d.k_eff);
+    const size_t o_s = take(sizeof(float) * d.k_eff);
+    const size_t o_mo = take(sizeof(float) * d.k_eff);
+    const size_t o_ve = take(sizeof(float) * d.k_eff);
+    const size_t o_xf = take(sizeof(float) * d.k_eff);
+    const size_t o_z = take(sizeof(float) * d.k_eff);
+    const size_t o_L = omp ? take(sizeof(float) * (size_t)d.k_eff * d.ldg) : 0;
+    const size_t o_cg = use_qr ? 0 : take(sizeof(float) * (3 * (size_t)d.m_pad + 3 * d.k_eff));
+    const size_t o_np = take(sizeof(double) * d.n_rowtiles);
+    const size_t o_qp = take(sizeof(float) * d.n_rowtiles);
+    const size_t o_key = take(sizeof(unsigned long long));
+    const size_t o_bm = take(sizeof(unsigned) * ((d.n + 31) / 32));
+    const size_t o_st = take(sizeof(InstState));
+    // store offsets in the pointer fields for now (+1 so 0 means "absent")
+    d.r = (float*)(o_r + 1);
+    d.G = (float*)(o_G + 1);
+    d.b = (float*)(o_b + 1);
+    d.s = (float*)(o_s + 1);
+    d.mo = (float*)(o_mo + 1);
+    d.ve = (float*)(o_ve + 1);
+    d.xf = (float*)(o_xf + 1);
+    d.z = (float*)(o_z + 1);
+    d.Linv = omp ? (float*)(o_L + 1) : nullptr;
+    d.cg = use_qr ? nullptr : (float*)(o_cg + 1);
+    d.npart = (double*)(o_np + 1);
+    d.qpart = (float*)(o_qp + 1);
+    d.key = (unsigned long long*)(o_key + 1);
+    d.bitmap = (unsigned*)(o_bm + 1);
+    d.st = (InstState*)(o_st + 1);
+    P.insts[s] = d;
+    P.keff[s] = d.k_eff;
+    P.kmax = std::max(P.kmax, d.k_eff);
+    snprintf(sigbuf, sizeof sigbuf, "%d,%d,%d,%lld,%lld|", d.n, d.m, d.k, (long long)d.lda,
+             (long long)d.ldam);
+    P.sig += sigbuf;
+  }
+  P.ws_bytes = ws;
+
+  // classes, scan tiles, row tiles
+  P.classes.clear();
+  P.tiles.clear();
+  P.rows.clear();
+  for (int s = 0; s < count;) {
+    Class c;
+    c.lpa = lpa[order[s]];
+    c.i0 = s;
+    while (s < count && lpa[order[s]] == c.lpa) ++s;
+    c.i1 = s;
+    c.tile_prefix.push_back(0);
+    c.row_prefix.push_back(0);
+    c.tile_off = P.tiles.size();
+    c.row_off = P.rows.size();
+    const int ng = kBlock / c.lpa;
+    for (int q = c.i0; q < c.i1; ++q) {
+      const Inst& d = P.insts[q];
+      const size_t atom_bytes = (size_t)d.m_pad * esize;
+      int apg = (int)std::max<size_t>(1, kScanTargetBytes / (atom_bytes * ng));
+      const int apt = ng * apg;
+      for (int j0 = 0; j0 < d.n; j0 += apt) P.tiles.push_back({q, j0, std::min(d.n, j0 + apt), 0});
+      c.tile_prefix.push_back((int)(P.tiles.size() - c.tile_off));
+      for (int tt = 0; tt < d.n_rowtiles; ++tt)
+        P.rows.push_back({q, tt * 64, std::min(d.m, tt * 64 + 64), tt});
+      c.row_prefix.push_back((int)(P.rows.size() - c.row_off));
+      c.m_pad_max = std::max(c.m_pad_max, d.m_pad);
+      c.kmax = std::max(c.kmax, d.k_eff);
+    }
+    P.classes.push_back(std::move(c));
+  }
+  // refinement lists
+  P.qr_list.clear();
+  P.cg_list.clear();
+  P.cg_rows.clear();
+  P.qr_lds = 0;
+  P.cg_tmax = 0;
+  P.cg_mpad_max = 0;
+  for (int q = 0; q < count; ++q) {
+    const Inst& d = P.insts[q];
+    if (d.cg_slot < 0) {
+      P.qr_list.push_back(q);
+      P.qr_lds = std::max(P.qr_lds, sizeof(float) * ((size_t)d.m * d.k_eff + d.m + 2 * d.k_eff));
+    } else {
+      P.insts[q].cg_slot = (int)P.cg_list.size();
+      P.cg_list.push_back(q);
+      for (int tt = 0; tt < d.n_rowtiles; ++tt)
+        P.cg_rows.push_back({q, tt * 64, std::min(d.m, tt * 64 + 64), tt});
+      P.cg_tmax = std::max(P.cg_tmax, d.k_eff);
+      P.cg_mpad_max = std::max(P.cg_mpad_max, d.m_pad);
+    }
+  }
+  int mmax = 0;
+  for (int q : P.cg_list) mmax = std::max(mmax, P.insts[q].m);
+  P.cg_lpa = pick_lpa(std::max(mmax, 1), 4);
+  // table blob layout
+  size_t off = 0;
+  auto place = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes, kAlign);
+    return o;
+  };
+  P.off_insts = place(sizeof(Inst) * count);
+  P.off_tiles = place(sizeof(ScanTile) * P.tiles.size());
+  P.off_rows = place(sizeof(RowTile) * P.rows.size());
+  P.off_qr = place(sizeof(int) * P.qr_list.size());
+  P.off_cg = place(sizeof(int) * P.cg_list.size());
+  P.off_cgrows = place(sizeof(RowTile) * P.cg_rows.size());
+  P.table_bytes = std::max<size_t>(off, kAlign);
+}
+
+clomp_status_t ensure(clomp_ctx* h, DevBuf& b, size_t bytes, bool* grew) {
+  if (grew) *grew = false;
+  if (b.bytes >= bytes) return CLOMP_OK;
+  if (b.p) {
+    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  const size_t want = align_up(bytes + bytes / 8, 1 << 20);
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return fail(h, CLOMP_OUT_OF_MEMORY, "workspace allocation of %zu bytes failed", want);
+  }
+  b.bytes = want;
+  if (grew) *grew = true;
+  return CLOMP_OK;
+}
+
+void drop_graphs(clomp_ctx* h) {
+  for (auto& kv : h->graphs) {
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+  }
+  h->graphs.clear();
+}
+
+// The launch sequence of one batch (captured as a graph when requested).
+clomp_status_t launch_all(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st) {
+  const clomp_params_t& prm = h->params;
+  const bool omp = prm.method == CLOMP_METHOD_OMP;
+  char* tb = reinterpret_cast<char*>(h->tables.p);
+  const Inst* d_insts = reinterpret_cast<const Inst*>(tb + P.off_insts);
+  const ScanTile* d_tiles = reinterpret_cast<const ScanTile*>(tb + P.off_tiles);
+  const RowTile* d_rows = reinterpret_cast<const RowTile*>(tb + P.off_rows);
+  const int* d_qr = reinterpret_cast<const int*>(tb + P.off_qr);
+  const int* d_cg = reinterpret_cast<const int*>(tb + P.off_cg);
+  const RowTile* d_cgrows = reinterpret_cast<const RowTile*>(tb + P.off_cgrows);
+  const int count = (int)P.insts.size();
+  const int lds_cap = (h->lds_limit - 1024) / 4;
+
+  HIP_TRY(launch_init(d_insts, count, st), "init");
+  for (int t = 0; t < P.kmax; ++t) {
+    for (const Class& c : P.classes) {
+      if (c.kmax <= t) continue;
+      // active prefix of the class: instances with k_eff > t
+      int nact = 0;
+      while (c.i0 + nact < c.i1 && P.keff[c.i0 + nact] > t) ++nact;
+      const int ntiles = c.tile_prefix[nact];
+      const int nrows = c.row_prefix[nact];
+      const int r_lds = (c.m_pad_max <= lds_cap) ? c.m_pad_max : 0;
+      HIP_TRY(launch_scan(bf16, c.lpa, d_insts, d_tiles + c.tile_off, ntiles, r_lds, st), "scan");
+      const int ng = kBlock / c.lpa;
+      const int ndots = t + 2;
+      int D = ng;
+      while ((long long)nact * ((ndots + D - 1) / D) > 8L * h->num_cu && D < 8 * ng) D *= 2;
+      const int nblk = (ndots + D - 1) / D;
+      HIP_TRY(launch_gram(bf16, c.lpa, d_insts + c.i0, nact, t, nblk, D, r_lds, prm.lr_rel,
+                          prm.eps_rel, st),
+              "gram");
+      if (omp)
+        HIP_TRY(launch_omp(d_insts + c.i0, nact, t, st), "omp");
+      else
+        HIP_TRY(launch_adam(d_insts + c.i0, nact, t, prm.inner_steps, prm.beta1, prm.beta2, st),
+                "adam");
+      HIP_TRY(launch_resid(bf16, d_insts, d_rows + c.row_off, nrows, t, st), "resid");
+    }
+  }
+  // refinement
+  HIP_TRY(launch_qr(d_insts, d_qr, (int)P.qr_list.size(), P.qr_lds, st), "qr");
+  const int ncg = (int)P.cg_list.size();
+  if (ncg > 0) {
+    const float tol = prm.refine_tol > 0.f ? prm.refine_tol : 1e-6f;
+    const int iters = prm.refine_iters > 0 ? prm.refine_iters : 48;
+    const int ng = kBlock / P.cg_lpa;
+    int D = ng;
+    while ((long long)ncg * ((P.cg_tmax + D - 1) / D) > 8L * h->num_cu && D < 8 * ng) D *= 2;
+    const int nblk = (P.cg_tmax + D - 1) / D;
+    const int ncgrows = (int)P.cg_rows.size();
+    HIP_TRY(launch_copy_s(d_insts, d_cg, ncg, st), "copy_s");
+    HIP_TRY(launch_cg_rows(0, d_insts, d_cgrows, ncgrows, P.cg_tmax, 0, 0.f, st), "cg_r0");
+    HIP_TRY(launch_cg_dots(0, P.cg_lpa, d_insts, d_cg, ncg, P.cg_tmax, nblk, D, P.cg_mpad_max, 0,
+                           st),
+            "cg_sv0");
+    for (int it = 0; it < iters; ++it) {
+      HIP_TRY(launch_cg_rows(1, d_insts, d_cgrows, ncgrows, P.cg_tmax, it, tol * tol, st),
+              "cg_q");
+      HIP_TRY(launch_cg_dots(1, P.cg_lpa, d_insts, d_cg, ncg, P.cg_tmax, nblk, D, P.cg_mpad_max,
+                             it, st),
+              "cg_sv");
+    }
+  }
+  HIP_TRY(launch_norm(d_insts, d_rows, (int)P.rows.size(), P.kmax, st), "norm");
+  HIP_TRY(launch_finalize(d_insts, count, ncg > 0, st), "finalize");
+  return CLOMP_OK;
+}
+
+}  // namespace
+
+// ============================================================ C ABI
+extern "C" {
+
+void clomp_default_params(clomp_params_t* p) {
+  if (!p) return;
+  p->method = CLOMP_METHOD_CLOMP;
+  p->inner_steps = 32;
+  p->lr_rel = 0.05f;
+  p->beta1 = 0.9f;
+  p->beta2 = 0.999f;
+  p->eps_rel = 1e-8f;
+  p->resid_tol = 0.f;
+  p->refine_iters = 0;
+  p->refine_tol = 0.f;
+  p->flags = 0u;
+}
+
+const char* clomp_status_string(clomp_status_t s) {
+  switch (s) {
+    case CLOMP_OK: return "CLOMP_OK";
+    case CLOMP_INVALID_ARGUMENT: return "CLOMP_INVALID_ARGUMENT";
+    case CLOMP_OUT_OF_MEMORY: return "CLOMP_OUT_OF_MEMORY";
+    case CLOMP_DEVICE_ERROR: return "CLOMP_DEVICE_ERROR";
+    case CLOMP_NOT_SUPPORTED: return "CLOMP_NOT_SUPPORTED";
+  }
+  return "CLOMP_UNKNOWN_STATUS";
+}
+
+const char* clomp_last_error(clomp_handle_t h) {
+  if (!h) return "no handle";
+  return h->last_error.c_str();
+}
+
+clomp_status_t clomp_create(clomp_handle_t* out, int device, const clomp_params_t* params) {
+  if (!out) return CLOMP_INVALID_ARGUMENT;
+  *out = nullptr;
+  clomp_params_t p;
+  clomp_default_params(&p);
+  if (params) {
+    const clomp_status_t s = check_params(nullptr, params);
+    if (s != CLOMP_OK) return s;
+    p = *params;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    (void)hipGetLastError();
+    return CLOMP_DEVICE_ERROR;
+  }
+  clomp_ctx* h = new clomp_ctx();
+  h->device = device;
+  h->params = p;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  if (hipSetDevice(device) != hipSuccess) {
+    delete h;
+    return CLOMP_DEVICE_ERROR;
+  }
+  int lds = 65536, ncu = 256;
+  (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
+  h->lds_limit = lds;
+  h->num_cu = ncu;
+  if (lds > 65536 && set_max_lds((size_t)lds) != hipSuccess) {
+    (void)hipGetLastError();
+    h->lds_limit = 65536;
+  }
+  if (hipEventCreateWithFlags(&h->staging_free, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->work_done, hipEventDisableTiming) != hipSuccess) {
+    delete h;
+    (void)hipSetDevice(prev);
+    return CLOMP_DEVICE_ERROR;
+  }
+  (void)hipSetDevice(prev);
+  *out = h;
+  return CLOMP_OK;
+}
+
+clomp_status_t clomp_set_params(clomp_handle_t h, const clomp_params_t* params) {
+  if (!h) return CLOMP_INVALID_ARGUMENT;
+  const clomp_status_t s = check_params(h, params);
+  if (s != CLOMP_OK) return s;
+  h->params = *params;
+  drop_graphs(h);
+  return CLOMP_OK;
+}
+
+clomp_status_t clomp_check_batch(clomp_handle_t h, const clomp_instance_t* inst, int32_t count,
+                                 int32_t a_dtype) {
+  return check_batch_impl(h, inst, count, a_dtype);
+}
+
+clomp_status_t clomp_solve_batch(clomp_handle_t h, const clomp_instance_t* inst, int32_t count,
+                                 int32_t a_dtype, void* hip_stream) {
+  if (!h) return CLOMP_INVALID_ARGUMENT;
+  clomp_status_t s = check_batch_impl(h, inst, count, a_dtype);
+  if (s != CLOMP_OK || count == 0) return s;
+  const int bf16 = a_dtype == CLOMP_BF16;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+
+  Plan P;
+  build_plan(h, inst, count, bf16, P);
+  if ((size_t)P.cg_mpad_max * sizeof(float) + 1024 > (size_t)h->lds_limit)
+    return fail(h, CLOMP_NOT_SUPPORTED,
+                "m = %d needs %zu bytes of LDS for the refinement; the device allows %d",
+                P.cg_mpad_max, (size_t)P.cg_mpad_max * sizeof(float), h->lds_limit);
+
+  // workspace and tables (grow-only; growth invalidates captured graphs)
+  bool g1 = false, g2 = false;
+  if ((s = ensure(h, h->ws, P.ws_bytes, &g1)) != CLOMP_OK) return s;
+  if ((s = ensure(h, h->tables, P.table_bytes, &g2)) != CLOMP_OK) return s;
+  if (g1 || g2) drop_graphs(h);
+  // rebase workspace offsets
+  char* wsb = reinterpret_cast<char*>(h->ws.p);
+  for (Inst& d : P.insts) {
+    auto rb = [&](auto*& ptr) {
+      if (ptr) ptr = reinterpret_cast<std::remove_reference_t<decltype(ptr)>>(
+                   wsb + (reinterpret_cast<uintptr_t>(ptr) - 1));
+    };
+    rb(d.r); rb(d.G); rb(d.b); rb(d.s); rb(d.mo); rb(d.ve); rb(d.xf); rb(d.z);
+    rb(d.Linv); rb(d.cg); rb(d.npart); rb(d.qpart); rb(d.key); rb(d.bitmap); rb(d.st);
+  }
+  // stage tables in pinned memory and upload on the stream
+  if (h->pinned_bytes < P.table_bytes) {
+    if (h->pinned) {
+      HIP_TRY(hipEventSynchronize(h->staging_free), "hipEventSynchronize");
+      (void)hipHostFree(h->pinned);
+      h->pinned = nullptr;
+    }
+    const size_t want = align_up(P.table_bytes * 2, 1 << 16);
+    if (hipHostMalloc(&h->pinned, want, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      h->pinned = nullptr;
+      h->pinned_bytes = 0;
+      return fail(h, CLOMP_OUT_OF_MEMORY, "pinned staging allocation failed");
+    }
+    h->pinned_bytes = want;
+  } else {
+    HIP_TRY(hipEventSynchronize(h->staging_free), "hipEventSynchronize");
+  }
+  char* hb = reinterpret_cast<char*>(h->pinned);
+  memcpy(hb + P.off_insts, P.insts.data(), sizeof(Inst) * P.insts.size());
+  if (!P.tiles.empty()) memcpy(hb + P.off_tiles, P.tiles.data(), sizeof(ScanTile) * P.tiles.size());
+  if (!P.rows.empty()) memcpy(hb + P.off_rows, P.rows.data(), sizeof(RowTile) * P.rows.size());
+  if (!P.qr_list.empty()) memcpy(hb + P.off_qr, P.qr_list.data(), sizeof(int) * P.qr_list.size());
+  if (!P.cg_list.empty()) memcpy(hb + P.off_cg, P.cg_list.data(), sizeof(int) * P.cg_list.size());
+  if (!P.cg_rows.empty())
+    memcpy(hb + P.off_cgrows, P.cg_rows.data(), sizeof(RowTile) * P.cg_rows.size());
+  // the previous batch (possibly on another stream) must be done with the tables
+  if (h->have_work) HIP_TRY(hipStreamWaitEvent(st, h->work_done, 0), "hipStreamWaitEvent");
+  HIP_TRY(hipMemcpyAsync(h->tables.p, hb, P.table_bytes, hipMemcpyHostToDevice, st),
+          "upload tables");
+  HIP_TRY(hipEventRecord(h->staging_free, st), "hipEventRecord");
+
+  const bool use_graph = (h->params.flags & CLOMP_FLAG_GRAPH) != 0;
+  if (use_graph) {
+    auto it = h->graphs.find(P.sig);
+    if (it == h->graphs.end()) {
+      CachedGraph cg;
+      HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
+      s = launch_all(h, P, bf16, st);
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(st, &g);
+      if (s != CLOMP_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return s;
+      }
+      if (e != hipSuccess) return hip_fail(h, e, "end capture");
+      cg.graph = g;
+      HIP_TRY(hipGraphInstantiate(&cg.exec, g, nullptr, nullptr, 0), "graph instantiate");
+      it = h->graphs.emplace(P.sig, cg).first;
+    }
+    HIP_TRY(hipGraphLaunch(it->second.exec, st), "graph launch");
+  } else {
+    if ((s = launch_all(h, P, bf16, st)) != CLOMP_OK) return s;
+  }
+  HIP_TRY(hipEventRecord(h->work_done, st), "hipEventRecord");
+  h->have_work = true;
+  (void)hipSetDevice(prev);
+  return CLOMP_OK;
+}
+
+clomp_status_t clomp_grad(clomp_handle_t h, int32_t n, int32_t m, int64_t lda, int32_t dtype,
+                          const void* A, const void* x, const uint8_t* mask, const void* y,
+                          const void* grad_out, void* grad_x, void* resid_out, void* loss,
+                          void* hip_stream) {
+  if (!h) return CLOMP_INVALID_ARGUMENT;
+  if (dtype == CLOMP_BF16) return fail(h, CLOMP_NOT_SUPPORTED, "clomp_grad serves F32 and F64");
+  if (dtype != CLOMP_F32 && dtype != CLOMP_F64)
+    return fail(h, CLOMP_INVALID_ARGUMENT, "unknown dtype %d", dtype);
+  if (n <= 0 || m <= 0 || lda < m) return fail(h, CLOMP_INVALID_ARGUMENT, "bad n, m or lda");
+  if (!A || !x || !mask || !y || !grad_x || !loss)
+    return fail(h, CLOMP_INVALID_ARGUMENT, "a required pointer is NULL");
+  const size_t es = dtype == CLOMP_F64 ? 8 : 4;
+  if (((uintptr_t)A % es) || ((uintptr_t)x % es) || ((uintptr_t)y % es))
+    return fail(h, CLOMP_INVALID_ARGUMENT, "A, x and y must be aligned to their element size");
+  const int colchunk = 256;
+  const int ncolchunk = (n + colchunk - 1) / colchunk;
+  const size_t nfin = (m + kBlock - 1) / kBlock;
+  const size_t need = es * ((size_t)ncolchunk * m + m + nfin) + 256;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  if (h->gwork.bytes < need) {
+    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    clomp_status_t s = ensure(h, h->gwork, need, nullptr);
+    if (s != CLOMP_OK) return s;
+  }
+  HIP_TRY(launch_grad(dtype == CLOMP_F64, n, m, lda, A, x, mask, y, grad_out, grad_x, resid_out,
+                      loss, h->gwork.p, ncolchunk, colchunk, st),
+          "grad");
+  (void)hipSetDevice(prev);
+  return CLOMP_OK;
+}
+
+clomp_status_t clomp_destroy(clomp_handle_t h) {
+  if (!h) return CLOMP_INVALID_ARGUMENT;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(h->device);
+  (void)hipDeviceSynchronize();
+  drop_graphs(h);
+  if (h->ws.p) (void)hipFree(h->ws.p);
+  if (h->tables.p) (void)hipFree(h->tables.p);
+  if (h->gwork.p) (void)hipFree(h->gwork.p);
+  if (h->pinned) (void)hipHostFree(h->pinned);
+  if (h->staging_free) (void)hipEventDestroy(h->staging_free);
+  if (h->work_done) (void)hipEventDestroy(h->work_done);
+  (void)hipSetDevice(prev);
+  delete h;
+  return CLOMP_OK;
+}
+
+}  // extern "C"

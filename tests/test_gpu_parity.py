@@ -1,0 +1,214 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Support identity is asserted on well-separated instances (per-iteration gap
+and perturbation stability, see oracle.separation); final coefficients within
+1e-5 relative (FP32 bulk) or 1e-3 (BF16 bulk with FP32 refinement); the
+reported FP64 residual norm is checked against its closed form.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import clomp_fp64, omp_fp64, lstsq_support
+from paper_2501_11592_amd import clomp as C
+from paper_2501_11592_amd import workloads as W
+from tests.gpu_helpers import (PARAMS, FP32_DELTA, FP32_U, BF16_DELTA, BF16_U, dev,
+                               oracle_final_x, compare, rel_err, fp64_resid)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def solvers():
+    s = {"clomp": C.Solver(0, method="clomp"), "omp": C.Solver(0, method="omp")}
+    yield s
+    for v in s.values():
+        v.close()
+
+
+def _items(sigs, dtype=torch.float32):
+    items = []
+    for s in sigs:
+        At = dev(s.At)
+        it = dict(At=At if dtype == torch.float32 else At.to(torch.bfloat16), m=s.m,
+                  y=dev(s.y), k=s.k)
+        if dtype != torch.float32:
+            it["At_master"] = At
+        items.append(it)
+    return items
+
+
+@pytest.mark.parametrize("method", ["clomp", "omp"])
+def test_small_single_signals(solvers, method):
+    """n=256, m=64, k=8: twenty signals in one batch."""
+    sigs = [W.single_small(i) for i in range(20)]
+    out = solvers[method].solve_batch(_items(sigs))
+    torch.cuda.synchronize()
+    kinds = []
+    for i, s in enumerate(sigs):
+        res = oracle_final_x(method, s.A, s.y, s.k)
+        kinds.append(compare(out, i, res, s.A, s.y, delta=FP32_DELTA, u=FP32_U, method=method,
+                             A_sel=s.A, k=s.k, tol_x=1e-5))
+        assert int(out.status[i]) == 0
+        assert int(out.n_selected[i]) == 8
+    assert kinds.count("identical") >= 15, kinds
+
+
+@pytest.mark.parametrize("method", ["clomp", "omp"])
+def test_ragged_sizes_span_tiles(solvers, method):
+    """Sizes that are not multiples of the vector width or tile, with lda
+    padding filled with NaN (the kernels must ignore entries beyond m)."""
+    rng = np.random.default_rng(5)
+    sigs = []
+    for i, (n, m, k) in enumerate([(1000, 77, 9), (3001, 130, 12), (517, 26, 26), (700, 299, 31)]):
+        s = W.single_small(100 + i, n=n, m=m, k=k)
+        At = s.At.copy()
+        At[:, m:] = np.nan
+        s.At = At
+        sigs.append(s)
+    out = solvers[method].solve_batch(_items(sigs))
+    torch.cuda.synchronize()
+    ident = 0
+    for i, s in enumerate(sigs):
+        res = oracle_final_x(method, s.A, s.y, s.k)
+        ident += compare(out, i, res, s.A, s.y, delta=FP32_DELTA, u=FP32_U, method=method,
+                         A_sel=s.A, k=s.k, tol_x=1e-5) == "identical"
+        assert not (int(out.status[i]) & C.ST_NAN)
+    assert ident >= 2
+
+
+@pytest.mark.parametrize("sr", [0.1, 0.3, 0.5])
+def test_image_batch_shared_matrix(solvers, sr):
+    """256 columns of a synthetic image sharing one Gaussian A (m = 26/77/128),
+    solved in one call; a subset of columns is checked against the oracle."""
+    b = W.image_batch(sr)
+    At = dev(b.At)
+    Y = dev(b.Y)
+    out = solvers["clomp"].solve_shared(At, b.m, Y, b.k)
+    torch.cuda.synchronize()
+    k_eff = min(b.k, b.m)
+    assert (out.n_selected.cpu().numpy() == k_eff).all()
+    capped = (out.status.cpu().numpy() & C.ST_K_CAPPED) != 0
+    assert capped.all() == (b.k > b.m)
+    kinds = []
+    for c in range(0, 256, 16):
+        res = oracle_final_x("clomp", b.A, b.Y[c], b.k)
+        kinds.append(compare(out, c, res, b.A, b.Y[c], delta=FP32_DELTA, u=FP32_U,
+                             method="clomp", A_sel=b.A, k=b.k,
+                             tol_x=1e-5 if sr > 0.1 else 1e-3))
+    print(f"sr={sr}: identical {kinds.count('identical')}/{len(kinds)}")
+
+
+@pytest.mark.parametrize("method", ["clomp", "omp"])
+def test_uneven_bf16_batch_with_master(solvers, method):
+    """Uneven batch, BF16 bulk with FP32 master (selection on the BF16 values,
+    refinement on the master)."""
+    specs = [sp for sp in W.uneven_specs(400) if sp.n <= 1400][:24]
+    sigs = [W.uneven_instance_host(i, sp) for i, sp in enumerate(specs)]
+    out = solvers[method].solve_batch(_items(sigs, torch.bfloat16))
+    torch.cuda.synchronize()
+    ident = 0
+    for i, s in enumerate(sigs):
+        Abf = torch.from_numpy(s.At[:, :s.m]).to(torch.bfloat16).to(torch.float64).numpy().T
+        res = oracle_final_x(method, Abf, s.y, s.k, A_refine=s.A)
+        kind = compare(out, i, res, s.A, s.y, delta=BF16_DELTA, u=BF16_U, method=method,
+                       A_sel=Abf, k=s.k, tol_x=1e-3)
+        ident += kind == "identical"
+        assert int(out.n_selected[i]) == min(s.k, s.m, s.n)
+    print(f"{method}: identical {ident}/{len(sigs)}")
+    assert ident >= 1     # the oracle calls 5 (CLOMP) / 3 (OMP) of these well separated
+
+
+def test_edge_cases(solvers):
+    sol = solvers["clomp"]
+    base = W.single_small(7)
+    # y == 0 -> empty support, x = 0, ZERO_Y
+    zero = W.single_small(7)
+    zero.y = np.zeros_like(zero.y)
+    # k > m -> capped at m (square system)
+    cap = W.single_small(8, n=40, m=12, k=30)
+    # n == k_eff == m, tiny
+    tiny = W.single_small(9, n=5, m=5, k=5)
+    # duplicate columns: tie broken to the lower index
+    dup = W.single_small(10, n=64, m=32, k=1)
+    dup.At[40] = dup.At[3]
+    dup.y = (dup.At[3, :32].astype(np.float64) * 2.0 + dup.At[10, :32] * 0.5).astype(np.float32)
+    sigs = [base, zero, cap, tiny, dup]
+    out = sol.solve_batch(_items(sigs))
+    torch.cuda.synchronize()
+    st = out.status.cpu().numpy()
+    assert st[0] == 0
+    assert st[1] & C.ST_ZERO_Y and int(out.n_selected[1]) == 0
+    assert not out.x[1].any() and float(out.resid_norm[1]) == 0.0
+    assert (out.support[1].cpu().numpy() == -1).all()
+    assert st[2] & C.ST_K_CAPPED and int(out.n_selected[2]) == 12
+    assert int(out.n_selected[3]) == 5
+    assert float(out.resid_norm[3]) < 1e-4 * np.linalg.norm(tiny.y)
+    assert int(out.support[4][0]) == 3    # |c_3| == |c_40|: lowest index wins
+    # tiny with k_eff = m: the full square system is solved exactly
+    res = clomp_fp64(tiny.A, tiny.y, 5, PARAMS)
+    assert sorted(out.support[3].cpu().numpy().tolist()) == sorted(res.support)
+
+
+def test_deterministic(solvers):
+    sigs = [W.single_small(i) for i in range(6)] + [W.single_small(50, n=3000, m=200, k=40)]
+    a = solvers["clomp"].solve_batch(_items(sigs))
+    torch.cuda.synchronize()
+    xa = [t.clone() for t in a.x]
+    b = solvers["clomp"].solve_batch(_items(sigs))
+    torch.cuda.synchronize()
+    for u, v in zip(xa, b.x):
+        assert torch.equal(u, v)
+    assert torch.equal(a.resid_norm, b.resid_norm)
+
+
+def test_grad_fp32_against_oracle(solvers):
+    from oracle import grad_fp64
+    s = W.single_small(3, n=300, m=70, k=10)
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(300).astype(np.float32)
+    mask = (rng.random(300) < 0.3).astype(np.uint8)
+    loss, gx, u = solvers["clomp"].grad(dev(s.At), s.m, dev(x), dev(mask), dev(s.y))
+    torch.cuda.synchronize()
+    l64, g64, u64 = grad_fp64(x, mask, s.A, s.y)
+    # normwise FP32 bound: 10 * sqrt(m) * 2^-24 * ||A|| * (||A(mask x)|| + ||y||)
+    bound = 10 * math.sqrt(s.m) * 2.0 ** -24 * np.linalg.norm(s.A, 2) * (
+        np.linalg.norm(s.A @ (mask * x.astype(np.float64))) + np.linalg.norm(s.y))
+    assert np.max(np.abs(gx.cpu().numpy() - g64)) <= bound * np.linalg.norm(s.A, 2)
+    assert np.max(np.abs(u.cpu().numpy() - u64)) <= bound
+    assert abs(float(loss) - l64) <= 1e-5 * max(1.0, l64)
+    assert not gx.cpu().numpy()[mask == 0].any()
+
+
+def test_grad_fp64_gradcheck_and_autograd(solvers):
+    s = W.single_small(4, n=40, m=16, k=4, dtype=np.float64)
+    At = dev(s.At)
+    rng = np.random.default_rng(2)
+    x = torch.tensor(rng.standard_normal(40), device="cuda", requires_grad=True)
+    y = torch.tensor(s.y.astype(np.float64), device="cuda", requires_grad=True)
+    mask = dev((rng.random(40) < 0.5).astype(np.uint8))
+    f = lambda xx, yy: C.ClompLoss.apply(xx, mask, At, s.m, yy)
+    assert torch.autograd.gradcheck(f, (x, y), eps=1e-6, atol=1e-8, rtol=1e-6)
+    # central differences on the FP64 HIP path are exact for the quadratic loss
+    from oracle import grad_fp64
+    l64, g64, _ = grad_fp64(x.detach().cpu().numpy(), mask.cpu().numpy(), s.A, s.y)
+    loss = f(x, y)
+    loss.backward()
+    np.testing.assert_allclose(x.grad.cpu().numpy(), g64, rtol=1e-12, atol=1e-12)
+    assert abs(loss.item() - l64) <= 1e-12 * max(1, l64)
+
+
+def test_abi_errors_on_device(solvers):
+    sol = solvers["clomp"]
+    s = W.single_small(1)
+    it = _items([s])[0]
+    it["At"] = torch.zeros((256, 66), device="cuda")   # lda = 66: not a multiple of 4
+    with pytest.raises(C.ClompError, match="INVALID_ARGUMENT"):
+        sol.solve_batch([it])
+    it = _items([s], torch.bfloat16)[0]
+    it.pop("At_master")
+    with pytest.raises(C.ClompError, match="A_master"):
+        sol.solve_batch([it])
