@@ -67,6 +67,9 @@ typedef enum {
                                         kernel (for testing the general path)  */
 #define CLOMP_FLAG_AUTOTUNE 4u       /* time the scan-kernel candidates on the
                                         first call for each size class         */
+#define CLOMP_FLAG_PROFILE 8u        /* record HIP events around every phase
+                                        launch (ignored while capturing graphs);
+                                        read with clomp_profile_read           */
 
 /*
  * Solver parameters.  The paper states the optimiser only as automatic
@@ -195,6 +198,29 @@ clomp_status_t clomp_grad(clomp_handle_t h, int32_t n, int32_t m, int64_t lda,
                           const uint8_t* mask, const void* y,
                           const void* grad_out, void* grad_x, void* resid_out,
                           void* loss, void* hip_stream);
+
+/*
+ * Phase timings gathered under CLOMP_FLAG_PROFILE, accumulated over every
+ * solve since the last clomp_profile_reset.  Phases: 0 scan (c = A^T r and
+ * argmax), 1 gram (selection record and new Gram column), 2 coef (Adam or the
+ * OMP update), 3 resid (r = y - A_S s), 4 refine (QR or CGLS), 5 norm (FP64
+ * residual norm and output scatter), 6 init.
+ *   ms[p]        summed device time between HIP events recorded on the launch
+ *                stream immediately before and after each launch of phase p
+ *   launches[p]  number of launches of phase p
+ *   scan_bytes   algorithmic bytes of the scan launches: for every active
+ *                instance and iteration, m*n*elem (the bulk columns) + 4m (r)
+ *                + n/8 (selection bitmap)
+ * Synchronises on the recorded events.  Errors: INVALID_ARGUMENT, DEVICE_ERROR.
+ */
+typedef struct {
+  double ms[8];
+  int64_t launches[8];
+  double scan_bytes;
+} clomp_profile_t;
+
+clomp_status_t clomp_profile_read(clomp_handle_t h, clomp_profile_t* out /*host*/);
+clomp_status_t clomp_profile_reset(clomp_handle_t h);
 
 /* Free the handle, its workspace and graphs (synchronises its device). */
 clomp_status_t clomp_destroy(clomp_handle_t h);

@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(_HERE, "libclomp.so")
 F32, BF16, F64 = 0, 1, 2
 METHOD_CLOMP, METHOD_OMP = 0, 1
 ST_NAN, ST_K_CAPPED, ST_ZERO_Y, ST_REFINE_INACCURATE, ST_WATCHDOG = 1, 2, 4, 8, 32
-FLAG_GRAPH, FLAG_NO_FUSED_SMALL, FLAG_AUTOTUNE = 1, 2, 4
+FLAG_GRAPH, FLAG_NO_FUSED_SMALL, FLAG_AUTOTUNE, FLAG_PROFILE = 1, 2, 4, 8
+PHASES = ("scan", "gram", "coef", "resid", "refine", "norm", "init")
 
 STATUS_NAMES = {0: "CLOMP_OK", 1: "CLOMP_INVALID_ARGUMENT", 2: "CLOMP_OUT_OF_MEMORY",
                 3: "CLOMP_DEVICE_ERROR", 4: "CLOMP_NOT_SUPPORTED"}
@@ -43,6 +44,11 @@ class Instance(ctypes.Structure):
                 ("x", ctypes.c_void_p), ("support", ctypes.c_void_p),
                 ("n_selected", ctypes.c_void_p), ("resid_norm", ctypes.c_void_p),
                 ("status", ctypes.c_void_p)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_int64 * 8),
+                ("scan_bytes", ctypes.c_double)]
 
 
 class ClompError(RuntimeError):
@@ -77,6 +83,10 @@ def load_library(path=LIB_PATH):
     lib.clomp_grad.argtypes = [H, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
                                ctypes.c_int32] + [ctypes.c_void_p] * 9
     lib.clomp_grad.restype = ctypes.c_int
+    lib.clomp_profile_read.argtypes = [H, ctypes.POINTER(Profile)]
+    lib.clomp_profile_read.restype = ctypes.c_int
+    lib.clomp_profile_reset.argtypes = [H]
+    lib.clomp_profile_reset.restype = ctypes.c_int
     lib.clomp_destroy.argtypes = [H]
     lib.clomp_destroy.restype = ctypes.c_int
     lib.clomp_status_string.argtypes = [ctypes.c_int]
@@ -161,6 +171,18 @@ class Solver:
             setattr(self.params, key, v)
         _check(self._h, load_library().clomp_set_params(self._h, ctypes.byref(self.params)),
                "clomp_set_params")
+
+    def profile_reset(self):
+        _check(self._h, load_library().clomp_profile_reset(self._h), "clomp_profile_reset")
+
+    def profile_read(self):
+        """Per-phase device time (ms) and launch counts since the last reset."""
+        p = Profile()
+        _check(self._h, load_library().clomp_profile_read(self._h, ctypes.byref(p)),
+               "clomp_profile_read")
+        return {"ms": {PHASES[i]: p.ms[i] for i in range(len(PHASES))},
+                "launches": {PHASES[i]: int(p.launches[i]) for i in range(len(PHASES))},
+                "scan_bytes": p.scan_bytes}
 
     # ------------------------------------------------------------------ solve
     def solve_batch(self, items, stream=None):

@@ -12,7 +12,11 @@ struct RowTile;
 
 hipError_t launch_init(const Inst* d, int count, hipStream_t s);
 hipError_t launch_scan(int bf16, int lpa, const Inst* d, const ScanTile* tiles, int ntiles,
-                       int r_lds_floats, hipStream_t s);
+                       int r_lds_floats, int reverse, hipStream_t s);
+hipError_t launch_scan_reg(int bf16, int lpa, int nch, const Inst* d, const ScanTile* tiles,
+                           int ntiles, int reverse, hipStream_t s);
+hipError_t launch_gram_reg(int bf16, int lpa, int nch, const Inst* d, int nact, int t, int nblk,
+                           int D, float lr_rel, float eps_rel, hipStream_t s);
 hipError_t launch_gram(int bf16, int lpa, const Inst* d, int nact, int t, int nblk, int D,
                        int v_lds_floats, float lr_rel, float eps_rel, hipStream_t s);
 hipError_t launch_adam(const Inst* d, int nact, int t, int T, float beta1, float beta2,

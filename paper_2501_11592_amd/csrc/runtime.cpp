@@ -52,6 +52,7 @@ struct Class {
   size_t tile_off = 0, row_off = 0;   // offsets of the arrays in the table blob
   int m_pad_max = 0;
   int kmax = 0;
+  int nch = 0;                        // register-kernel vectors per lane (0: LDS kernels)
 };
 
 struct Plan {
@@ -91,6 +92,13 @@ struct clomp_ctx {
   int num_cu = 256;
   DevBuf gwork;
   std::map<std::string, CachedGraph> graphs;
+  // profiling (CLOMP_FLAG_PROFILE)
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  struct Rec { int phase; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  double scan_bytes = 0.0;
+  bool profiling = false;
 };
 
 namespace {
@@ -306,6 +314,15 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
       c.m_pad_max = std::max(c.m_pad_max, d.m_pad);
       c.kmax = std::max(c.kmax, d.k_eff);
     }
+    // register kernels when every lane's share of the longest column fits in
+    // 64 registers
+    {
+      const int nvec = (c.m_pad_max + vw - 1) / vw;
+      const int per_lane = (nvec + c.lpa - 1) / c.lpa;
+      int nch = 1;
+      while (nch < per_lane) nch <<= 1;
+      c.nch = (nch * vw <= 64) ? nch : 0;   // at most 64 floats of r per lane
+    }
     P.classes.push_back(std::move(c));
   }
   // refinement lists
@@ -376,6 +393,35 @@ void drop_graphs(clomp_ctx* h) {
   h->graphs.clear();
 }
 
+enum Phase { PH_SCAN = 0, PH_GRAM, PH_COEF, PH_RESID, PH_REFINE, PH_NORM, PH_INIT };
+
+hipEvent_t pool_event(clomp_ctx* h) {
+  if (h->ev_used == h->ev_pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->ev_pool.push_back(e);
+  }
+  return h->ev_pool[h->ev_used++];
+}
+
+// Bracket one phase launch with events when profiling.
+struct PhaseScope {
+  clomp_ctx* h;
+  int phase;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  PhaseScope(clomp_ctx* h_, int p, hipStream_t s) : h(h_), phase(p), st(s) {
+    if (h->profiling && (a = pool_event(h))) (void)hipEventRecord(a, st);
+  }
+  ~PhaseScope() {
+    if (!a) return;
+    hipEvent_t b = pool_event(h);
+    if (!b) return;
+    (void)hipEventRecord(b, st);
+    h->recs.push_back({phase, a, b});
+  }
+};
+
 // The launch sequence of one batch (captured as a graph when requested).
 clomp_status_t launch_all(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st) {
   const clomp_params_t& prm = h->params;
@@ -390,7 +436,10 @@ clomp_status_t launch_all(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st)
   const int count = (int)P.insts.size();
   const int lds_cap = (h->lds_limit - 1024) / 4;
 
-  HIP_TRY(launch_init(d_insts, count, st), "init");
+  {
+    PhaseScope ps(h, PH_INIT, st);
+    HIP_TRY(launch_init(d_insts, count, st), "init");
+  }
   for (int t = 0; t < P.kmax; ++t) {
     for (const Class& c : P.classes) {
       if (c.kmax <= t) continue;
@@ -400,26 +449,59 @@ clomp_status_t launch_all(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st)
       const int ntiles = c.tile_prefix[nact];
       const int nrows = c.row_prefix[nact];
       const int r_lds = (c.m_pad_max <= lds_cap) ? c.m_pad_max : 0;
-      HIP_TRY(launch_scan(bf16, c.lpa, d_insts, d_tiles + c.tile_off, ntiles, r_lds, st), "scan");
+      {
+        PhaseScope ps(h, PH_SCAN, st);
+        if (c.nch > 0)
+          HIP_TRY(launch_scan_reg(bf16, c.lpa, c.nch, d_insts, d_tiles + c.tile_off, ntiles, t & 1,
+                                  st),
+                  "scan");
+        else
+          HIP_TRY(launch_scan(bf16, c.lpa, d_insts, d_tiles + c.tile_off, ntiles, r_lds, t & 1, st),
+                  "scan");
+      }
+      if (h->profiling) {
+        const double esz = bf16 ? 2.0 : 4.0;
+        for (int q = c.i0; q < c.i0 + nact; ++q) {
+          const Inst& d = P.insts[q];
+          h->scan_bytes += (double)d.m * d.n * esz + 4.0 * d.m + d.n / 8.0;
+        }
+      }
       const int ng = kBlock / c.lpa;
       const int ndots = t + 2;
       int D = ng;
       while ((long long)nact * ((ndots + D - 1) / D) > 8L * h->num_cu && D < 8 * ng) D *= 2;
       const int nblk = (ndots + D - 1) / D;
-      HIP_TRY(launch_gram(bf16, c.lpa, d_insts + c.i0, nact, t, nblk, D, r_lds, prm.lr_rel,
-                          prm.eps_rel, st),
-              "gram");
-      if (omp)
-        HIP_TRY(launch_omp(d_insts + c.i0, nact, t, st), "omp");
-      else
-        HIP_TRY(launch_adam(d_insts + c.i0, nact, t, prm.inner_steps, prm.beta1, prm.beta2, st),
-                "adam");
-      HIP_TRY(launch_resid(bf16, d_insts, d_rows + c.row_off, nrows, t, st), "resid");
+      {
+        PhaseScope ps(h, PH_GRAM, st);
+        if (c.nch > 0)
+          HIP_TRY(launch_gram_reg(bf16, c.lpa, c.nch, d_insts + c.i0, nact, t, nblk, D,
+                                  prm.lr_rel, prm.eps_rel, st),
+                  "gram");
+        else
+          HIP_TRY(launch_gram(bf16, c.lpa, d_insts + c.i0, nact, t, nblk, D, r_lds, prm.lr_rel,
+                              prm.eps_rel, st),
+                  "gram");
+      }
+      {
+        PhaseScope ps(h, PH_COEF, st);
+        if (omp)
+          HIP_TRY(launch_omp(d_insts + c.i0, nact, t, st), "omp");
+        else
+          HIP_TRY(launch_adam(d_insts + c.i0, nact, t, prm.inner_steps, prm.beta1, prm.beta2,
+                              st),
+                  "adam");
+      }
+      {
+        PhaseScope ps(h, PH_RESID, st);
+        HIP_TRY(launch_resid(bf16, d_insts, d_rows + c.row_off, nrows, t, st), "resid");
+      }
     }
   }
   // refinement
-  HIP_TRY(launch_qr(d_insts, d_qr, (int)P.qr_list.size(), P.qr_lds, st), "qr");
   const int ncg = (int)P.cg_list.size();
+  {
+  PhaseScope ref_scope(h, PH_REFINE, st);
+  HIP_TRY(launch_qr(d_insts, d_qr, (int)P.qr_list.size(), P.qr_lds, st), "qr");
   if (ncg > 0) {
     const float tol = prm.refine_tol > 0.f ? prm.refine_tol : 1e-6f;
     const int iters = prm.refine_iters > 0 ? prm.refine_iters : 48;
@@ -441,6 +523,8 @@ clomp_status_t launch_all(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st)
               "cg_sv");
     }
   }
+  }
+  PhaseScope ps(h, PH_NORM, st);
   HIP_TRY(launch_norm(d_insts, d_rows, (int)P.rows.size(), P.kmax, st), "norm");
   HIP_TRY(launch_finalize(d_insts, count, ncg > 0, st), "finalize");
   return CLOMP_OK;
@@ -605,6 +689,7 @@ clomp_status_t clomp_solve_batch(clomp_handle_t h, const clomp_instance_t* inst,
   HIP_TRY(hipEventRecord(h->staging_free, st), "hipEventRecord");
 
   const bool use_graph = (h->params.flags & CLOMP_FLAG_GRAPH) != 0;
+  h->profiling = !use_graph && (h->params.flags & CLOMP_FLAG_PROFILE) != 0;
   if (use_graph) {
     auto it = h->graphs.find(P.sig);
     if (it == h->graphs.end()) {
@@ -666,6 +751,29 @@ clomp_status_t clomp_grad(clomp_handle_t h, int32_t n, int32_t m, int64_t lda, i
   return CLOMP_OK;
 }
 
+clomp_status_t clomp_profile_reset(clomp_handle_t h) {
+  if (!h) return CLOMP_INVALID_ARGUMENT;
+  for (const auto& r : h->recs) (void)hipEventSynchronize(r.b);
+  h->recs.clear();
+  h->ev_used = 0;
+  h->scan_bytes = 0.0;
+  return CLOMP_OK;
+}
+
+clomp_status_t clomp_profile_read(clomp_handle_t h, clomp_profile_t* out) {
+  if (!h || !out) return CLOMP_INVALID_ARGUMENT;
+  memset(out, 0, sizeof *out);
+  for (const auto& r : h->recs) {
+    HIP_TRY(hipEventSynchronize(r.b), "hipEventSynchronize");
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
+    out->ms[r.phase] += ms;
+    out->launches[r.phase] += 1;
+  }
+  out->scan_bytes = h->scan_bytes;
+  return CLOMP_OK;
+}
+
 clomp_status_t clomp_destroy(clomp_handle_t h) {
   if (!h) return CLOMP_INVALID_ARGUMENT;
   int prev = 0;
@@ -679,6 +787,7 @@ clomp_status_t clomp_destroy(clomp_handle_t h) {
   if (h->pinned) (void)hipHostFree(h->pinned);
   if (h->staging_free) (void)hipEventDestroy(h->staging_free);
   if (h->work_done) (void)hipEventDestroy(h->work_done);
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   (void)hipSetDevice(prev);
   delete h;
   return CLOMP_OK;

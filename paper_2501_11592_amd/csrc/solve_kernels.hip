@@ -64,10 +64,13 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const Inst* __restrict__ i
 template <typename TA, int LPA>
 __global__ __launch_bounds__(kBlock) void scan_kernel(const Inst* __restrict__ insts,
                                                       const ScanTile* __restrict__ tiles,
-                                                      int r_in_lds) {
+                                                      int r_in_lds, int reverse) {
   extern __shared__ float smem[];
   __shared__ unsigned long long wbest[kWaves];
-  const ScanTile tile = tiles[blockIdx.x];
+  // Odd iterations walk the tiles backwards, so a scan starts on the columns
+  // the previous scan streamed last (still resident in the memory-side cache
+  // when the dictionary is about the cache's size).
+  const ScanTile tile = tiles[reverse ? (gridDim.x - 1 - blockIdx.x) : blockIdx.x];
   const Inst& I = insts[tile.inst];
   if (I.st->done) return;
   constexpr int VW = Vec<TA>::W;
@@ -105,6 +108,73 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const Inst* __restrict__ i
     acc = group_sum<LPA>(acc);
     const unsigned sel = (bitmap[j >> 5] >> (j & 31)) & 1u;
     const unsigned long long key = sel ? 0ull : pack_key(acc, j);
+    best = key > best ? key : best;
+  }
+  best = wave_max_u64(best);
+  if ((threadIdx.x & 63) == 0) wbest[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long b = wbest[0];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) b = wbest[w] > b ? wbest[w] : b;
+    if (b) atomicMax(I.key, b);
+  }
+}
+
+// Register variant: when every lane's share of a column is at most NCH
+// vectors, r lives in registers and each atom's NCH loads are issued together
+// (no LDS staging, no barrier before streaming starts).
+template <typename TA, int LPA, int NCH>
+__global__ __launch_bounds__(kBlock) void scan_reg_kernel(const Inst* __restrict__ insts,
+                                                          const ScanTile* __restrict__ tiles,
+                                                          int reverse) {
+  __shared__ unsigned long long wbest[kWaves];
+  const ScanTile tile = tiles[reverse ? (gridDim.x - 1 - blockIdx.x) : blockIdx.x];
+  const Inst& I = insts[tile.inst];
+  if (I.st->done) return;
+  constexpr int VW = Vec<TA>::W;
+  const int m = I.m;
+  const int nvec = (m + VW - 1) / VW;
+  const int tail = m - (nvec - 1) * VW;
+  const int gl = threadIdx.x % LPA;
+  const int grp = threadIdx.x / LPA;
+  constexpr int NG = kBlock / LPA;
+  float rr[NCH][VW];
+#pragma unroll
+  for (int q = 0; q < NCH; ++q) {
+    const int c = gl + q * LPA;
+#pragma unroll
+    for (int e = 0; e < VW; ++e) rr[q][e] = (c < nvec) ? I.r[c * VW + e] : 0.f;
+  }
+  const TA* A = reinterpret_cast<const TA*>(I.A);
+  const long long lda = I.lda;
+  const unsigned* bitmap = I.bitmap;
+  unsigned long long best = 0ull;
+  for (int j = tile.j0 + grp; j < tile.j1; j += NG) {
+    const TA* col = A + (long long)j * lda;
+    float v[NCH][VW];
+#pragma unroll
+    for (int q = 0; q < NCH; ++q) {
+      const int c = gl + q * LPA;
+      if (c < nvec) {
+        Vec<TA>::load(col + (long long)c * VW, v[q]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VW; ++e) v[q][e] = 0.f;
+      }
+      if (c == nvec - 1) {
+#pragma unroll
+        for (int e = 0; e < VW; ++e) v[q][e] = (e < tail) ? v[q][e] : 0.f;
+      }
+    }
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < NCH; ++q)
+#pragma unroll
+      for (int e = 0; e < VW; ++e) acc[e & 3] = fmaf(v[q][e], rr[q][e], acc[e & 3]);
+    float a = group_sum<LPA>((acc[0] + acc[1]) + (acc[2] + acc[3]));
+    const unsigned sel = (bitmap[j >> 5] >> (j & 31)) & 1u;
+    const unsigned long long key = sel ? 0ull : pack_key(a, j);
     best = key > best ? key : best;
   }
   best = wave_max_u64(best);
@@ -239,6 +309,95 @@ __global__ __launch_bounds__(kBlock) void gram_kernel(const Inst* __restrict__ i
   }
 }
 
+// Register variant of the Gram kernel (lane share of a column <= NCH vectors):
+// no LDS staging; each dot issues the a_j and partner-column loads together.
+template <typename TA, int LPA, int NCH>
+__global__ __launch_bounds__(kBlock) void gram_reg_kernel(const Inst* __restrict__ insts, int t,
+                                                          int nblk, int D, float lr_rel,
+                                                          float eps_rel) {
+  const int ii = blockIdx.x / nblk;
+  const int blk = blockIdx.x - ii * nblk;
+  const Inst& I = insts[ii];
+  if (I.st->done) return;
+  const unsigned long long key = *I.key;
+  const int j = key_index(key);
+  if (key == 0ull || j < 0 || j >= I.n) {
+    if (blk == 0 && threadIdx.x == 0) {
+      I.st->done = 1;
+      atomicOr(I.status, ST_WATCHDOG);
+    }
+    return;
+  }
+  constexpr int VW = Vec<TA>::W;
+  const int m = I.m;
+  const int nvec = (m + VW - 1) / VW;
+  const int tail = m - (nvec - 1) * VW;
+  const TA* A = reinterpret_cast<const TA*>(I.A);
+  const long long lda = I.lda;
+  const TA* colj = A + (long long)j * lda;
+  const float* yw = I.r + I.m_pad;
+  const int gl = threadIdx.x % LPA;
+  const int grp = threadIdx.x / LPA;
+  constexpr int NG = kBlock / LPA;
+  const int l0 = blk * D;
+  const int l1 = min(l0 + D, t + 2);
+  for (int l = l0 + grp; l < l1; l += NG) {
+    float aj[NCH][VW], v[NCH][VW];
+    const bool ydot = l == t + 1;
+    const TA* colv = A + (long long)((l < t) ? I.support[l] : j) * lda;
+#pragma unroll
+    for (int q = 0; q < NCH; ++q) {
+      const int c = gl + q * LPA;
+      if (c < nvec) {
+        Vec<TA>::load(colj + (long long)c * VW, aj[q]);
+        if (ydot) {
+#pragma unroll
+          for (int e = 0; e < VW; ++e) v[q][e] = yw[c * VW + e];
+        } else {
+          Vec<TA>::load(colv + (long long)c * VW, v[q]);
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < VW; ++e) aj[q][e] = v[q][e] = 0.f;
+      }
+      if (c == nvec - 1) {
+        // entries beyond m are ignored padding (possibly NaN): zero both
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+          aj[q][e] = (e < tail) ? aj[q][e] : 0.f;
+          v[q][e] = (e < tail) ? v[q][e] : 0.f;
+        }
+      }
+    }
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < NCH; ++q)
+#pragma unroll
+      for (int e = 0; e < VW; ++e) acc[e & 3] = fmaf(aj[q][e], v[q][e], acc[e & 3]);
+    const float d = group_sum<LPA>((acc[0] + acc[1]) + (acc[2] + acc[3]));
+    if (gl == 0) {
+      if (ydot) {
+        I.b[t] = d;
+      } else {
+        I.G[l + (long long)t * I.ldg] = d;
+        I.G[t + (long long)l * I.ldg] = d;
+      }
+    }
+  }
+  if (blk == 0 && threadIdx.x == 0) {
+    I.support[t] = j;
+    I.bitmap[j >> 5] |= (1u << (j & 31));
+    *I.nsel = t + 1;
+    const float cj = key_value(key);
+    if (!(cj <= 3.402823466e38f)) atomicOr(I.status, ST_NAN);
+    if (t == 0) {
+      I.st->sigma = cj;
+      I.st->lr = lr_rel * cj;
+      I.st->eps = eps_rel * cj;
+    }
+  }
+}
+
 // ============================================================ Adam (CLOMP)
 // One workgroup per active instance; rows of G are split over the threads
 // (up to kRPT rows each).  T steps of
@@ -279,7 +438,22 @@ __global__ __launch_bounds__(kBlock) void adam_kernel(const Inst* __restrict__ i
     const float bc2 = (float)(1.0 - pow((double)beta2, (double)step));
 #pragma unroll
     for (int q = 0; q < kRPT; ++q) g[q] = 0.f;
-    for (int c = 0; c < t1; ++c) {
+    // rows of G are streamed from L2; four columns per pass keep four
+    // independent loads in flight per row
+    int c = 0;
+    for (; c + 4 <= t1; c += 4) {
+      const float s0 = ssh[c], s1 = ssh[c + 1], s2 = ssh[c + 2], s3 = ssh[c + 3];
+      const float* G0 = G + (long long)c * ldg;
+#pragma unroll
+      for (int q = 0; q < kRPT; ++q) {
+        const int r = threadIdx.x + q * kBlock;
+        if (r < t1) {
+          const float u0 = G0[r], u1 = G0[ldg + r], u2 = G0[2 * ldg + r], u3 = G0[3 * ldg + r];
+          g[q] = fmaf(u3, s3, fmaf(u2, s2, fmaf(u1, s1, fmaf(u0, s0, g[q]))));
+        }
+      }
+    }
+    for (; c < t1; ++c) {
       const float sc = ssh[c];
       const float* Gc = G + (long long)c * ldg;
 #pragma unroll
@@ -318,16 +492,139 @@ __global__ __launch_bounds__(kBlock) void adam_kernel(const Inst* __restrict__ i
   }
 }
 
+// Register-resident variant for t+1 <= 256 (1024 threads, 16 waves).
+// Wave w owns the 16 columns [16w, 16w+16) of G and lane l the rows
+// [4l, 4l+4): a 4 x 16 tile of G lives in each lane's registers for the whole
+// launch.  Because G is symmetric, the 16 coefficients wave w multiplies by
+// are exactly the rows 16w..16w+15 whose Adam state its lanes 0..15 own, so
+// they never leave the wave: they are broadcast with readlane.  One barrier
+// per step exchanges the partial row sums (double-buffered in LDS); each
+// row's 16 partials are then added in a fixed order.
+constexpr int kRegRows = 256;
+
+__global__ __launch_bounds__(1024) void adam_reg_kernel(const Inst* __restrict__ insts, int t,
+                                                        int T, float beta1, float beta2) {
+  __shared__ float4 part[2][16][64];   // [buffer][wave][lane] -> rows 4l..4l+3
+  // the launch uses ceil((t+1)/16) waves: every wave owns live columns
+  const int nw = blockDim.x >> 6;
+  const Inst& I = insts[blockIdx.x];
+  if (I.st->done) {
+    if (threadIdx.x == 0) *I.key = 0ull;
+    return;
+  }
+  const int t1 = t + 1;
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int c0 = 16 * w;
+  const bool active = c0 < t1;          // wave-uniform
+  const long long ldg = I.ldg;
+  float Gr[4][16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (active && 4 * lane < t1 && c0 + c < t1)
+      q = *reinterpret_cast<const float4*>(I.G + (long long)(c0 + c) * ldg + 4 * lane);
+    // rows beyond t1 inside the last float4 hold stale values: zero them
+    const int rb = 4 * lane;
+    Gr[0][c] = (rb + 0 < t1) ? q.x : 0.f;
+    Gr[1][c] = (rb + 1 < t1) ? q.y : 0.f;
+    Gr[2][c] = (rb + 2 < t1) ? q.z : 0.f;
+    Gr[3][c] = (rb + 3 < t1) ? q.w : 0.f;
+  }
+  // Adam state of row R = 16w + lane (lanes 0..15)
+  const int R = c0 + lane;
+  const bool own = lane < 16 && R < t1;
+  float sv = 0.f, mo = 0.f, ve = 0.f, bb = 0.f;
+  if (own) {
+    sv = I.s[R];
+    mo = I.mo[R];
+    ve = I.ve[R];
+    bb = I.b[R];
+  }
+  const float lr = I.st->lr, eps = I.st->eps;
+  const int step0 = I.st->step;
+  double b1p = pow((double)beta1, (double)step0);
+  double b2p = pow((double)beta2, (double)step0);
+  // slots of waves beyond nw stay zero so every row reads 16 partials
+  // unconditionally (independent LDS loads, no branches)
+  for (int q = nw + w; q < 16; q += nw) {
+    part[0][q][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+    part[1][q][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  for (int it = 0; it < T; ++it) {
+    const int buf = it & 1;
+    b1p *= beta1;
+    b2p *= beta2;
+    // bias-correction factors for this step (1 - beta^step in float64, then a
+    // float reciprocal), formed before the barrier
+    const float ibc1 = __builtin_amdgcn_rcpf((float)(1.0 - b1p));
+    const float ibc2 = __builtin_amdgcn_rcpf((float)(1.0 - b2p));
+    // per-row sums over the wave's 16 columns, four interleaved chains each
+    float acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[i][u] = 0.f;
+    if (active) {
+      const int sbits = __float_as_int(sv);
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        const float sc = __int_as_float(__builtin_amdgcn_readlane(sbits, c));
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i][c & 3] = fmaf(Gr[i][c], sc, acc[i][c & 3]);
+      }
+    }
+    float rs[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) rs[i] = (acc[i][0] + acc[i][1]) + (acc[i][2] + acc[i][3]);
+    part[buf][w][lane] = make_float4(rs[0], rs[1], rs[2], rs[3]);
+    __syncthreads();
+    if (own) {
+      // partials of row R: element (R & 3) of part[buf][w'][R >> 2], w' = 0..15,
+      // added as a balanced tree in a fixed order
+      const float* pf = reinterpret_cast<const float*>(&part[buf][0][0]) + R;
+      float p[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) p[q] = pf[q * 256];
+#pragma unroll
+      for (int h = 8; h > 0; h >>= 1)
+#pragma unroll
+        for (int q = 0; q < h; ++q) p[q] = p[q] + p[q + h];
+      const float gr = p[0] - bb;
+      mo = beta1 * mo + (1.f - beta1) * gr;
+      ve = beta2 * ve + (1.f - beta2) * (gr * gr);
+      const float mh = mo * ibc1;
+      const float vh = ve * ibc2;
+      // hardware square root and reciprocal (1 ulp)
+      sv = sv - lr * mh * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(vh) + eps);
+    }
+  }
+  if (own) {
+    I.s[R] = sv;
+    I.mo[R] = mo;
+    I.ve[R] = ve;
+  }
+  if (threadIdx.x == 0) {
+    I.st->step = step0 + T;
+    *I.key = 0ull;
+  }
+}
+
 // ============================================================ OMP coefficients
-// One workgroup per active instance.  With L L^T = G_S and Linv = L^{-1}
-// (lower triangular), appending column t with Gram column g (g_tt last):
-//   w = Linv g[0:t],  lambda = sqrt(g_tt - w.w),
-//   Linv[t, :t] = -(w^T Linv) / lambda,  Linv[t, t] = 1 / lambda,
-//   z_t = (b_t - w.z) / lambda,  x_S = Linv^T z.
-// Every step is a parallel triangular mat-vec; no sequential solve is needed.
-__global__ __launch_bounds__(kBlock) void omp_chol_kernel(const Inst* __restrict__ insts, int t) {
-  extern __shared__ float osh[];  // gcol[t1] | w[t1]
-  __shared__ float red[kWaves];
+// One workgroup per active instance.  Keeps Ginv = G_S^{-1} (column-major,
+// both triangles, in the Linv buffer) and the least-squares coefficients
+// x_S = Ginv b in s.  Appending atom t with Gram column g (gamma = g_tt):
+//   v = Ginv g,  delta = gamma - g.v,  alpha = (b_t - g.x_S) / delta,
+//   x_S <- [x_S - alpha v ; alpha],
+//   Ginv <- [[Ginv + v v^T / delta, -v / delta], [-v^T / delta, 1 / delta]]
+// (bordered inverse).  Both sweeps over Ginv are coalesced (column c read or
+// updated by consecutive rows r); there is no sequential triangular solve.
+constexpr int kOmpThreads = 1024;
+
+__global__ __launch_bounds__(kOmpThreads) void omp_ginv_kernel(const Inst* __restrict__ insts,
+                                                               int t) {
+  extern __shared__ float osh[];  // g[t1] | v[t1] | vpart[4][t1]
+  __shared__ float red[kOmpThreads / 64];
   const Inst& I = insts[blockIdx.x];
   if (I.st->done) {
     if (threadIdx.x == 0) *I.key = 0ull;
@@ -335,46 +632,73 @@ __global__ __launch_bounds__(kBlock) void omp_chol_kernel(const Inst* __restrict
   }
   const int t1 = t + 1;
   const long long ld = I.ldg;
-  float* L = I.Linv;
-  float* gcol = osh;
-  float* w = osh + t1;
-  for (int r = threadIdx.x; r < t1; r += kBlock) gcol[r] = I.G[r + (long long)t * ld];
+  float* Gi = I.Linv;
+  float* g = osh;
+  float* v = osh + t1;
+  float* vpart = osh + 2 * t1;
+  const int tid = threadIdx.x;
+  const int rl = tid & 255;      // row lane
+  const int cg = tid >> 8;       // column group: columns c = cg, cg+4, ...
+  for (int r = tid; r < t1; r += kOmpThreads) g[r] = I.G[r + (long long)t * ld];
   __syncthreads();
-  for (int r = threadIdx.x; r < t; r += kBlock) {
-    float acc = 0.f;
-    for (int c = 0; c <= r; ++c) acc = fmaf(L[r + (long long)c * ld], gcol[c], acc);
-    w[r] = acc;
+  // v = Ginv g over the first t rows / columns: 4 column groups, rows strided
+  for (int r = rl; r < t; r += 256) {
+    float a0 = 0.f, a1 = 0.f;
+    int c = cg;
+    for (; c + 4 < t; c += 8) {
+      a0 = fmaf(Gi[r + (long long)c * ld], g[c], a0);
+      a1 = fmaf(Gi[r + (long long)(c + 4) * ld], g[c + 4], a1);
+    }
+    if (c < t) a0 = fmaf(Gi[r + (long long)c * ld], g[c], a0);
+    vpart[cg * t1 + r] = a0 + a1;
   }
   __syncthreads();
-  float part = 0.f, pz = 0.f;
-  for (int r = threadIdx.x; r < t; r += kBlock) {
-    part = fmaf(w[r], w[r], part);
-    pz = fmaf(w[r], I.z[r], pz);
+  float pv = 0.f, px = 0.f;
+  for (int r = tid; r < t; r += kOmpThreads) {
+    const float vr = (vpart[r] + vpart[t1 + r]) + (vpart[2 * t1 + r] + vpart[3 * t1 + r]);
+    v[r] = vr;
+    pv = fmaf(g[r], vr, pv);
+    px = fmaf(g[r], I.s[r], px);
   }
-  const float ww = block_sum(part, red);
-  const float wz = block_sum(pz, red);
-  const float gtt = gcol[t];
-  float lam2 = gtt - ww;
-  const bool bad = !(lam2 > 1e-7f * gtt);
-  if (bad) lam2 = fmaxf(1e-7f * gtt, 1e-30f);
-  const float lam = sqrtf(lam2);
-  for (int c = threadIdx.x; c < t; c += kBlock) {
-    float acc = 0.f;
-    for (int r = c; r < t; ++r) acc = fmaf(w[r], L[r + (long long)c * ld], acc);
-    L[t + (long long)c * ld] = -acc / lam;
+  // block sums (fixed order over the 16 waves)
+  pv = wave_sum(pv);
+  px = wave_sum(px);
+  __shared__ float red2[kOmpThreads / 64];
+  if ((tid & 63) == 0) {
+    red[tid >> 6] = pv;
+    red2[tid >> 6] = px;
   }
-  if (threadIdx.x == 0) {
-    L[t + (long long)t * ld] = 1.f / lam;
-    I.z[t] = (I.b[t] - wz) / lam;
+  __syncthreads();
+  float gv = 0.f, gx = 0.f;
+#pragma unroll
+  for (int q = 0; q < kOmpThreads / 64; ++q) {
+    gv += red[q];
+    gx += red2[q];
+  }
+  const float gamma = g[t];
+  float delta = gamma - gv;
+  const bool bad = !(delta > 1e-7f * gamma);
+  if (bad) delta = fmaxf(1e-7f * gamma, 1e-30f);
+  const float inv = 1.f / delta;
+  const float alpha = (I.b[t] - gx) * inv;
+  for (int r = tid; r < t; r += kOmpThreads) {
+    I.s[r] = fmaf(-alpha, v[r], I.s[r]);
+    const float w = -v[r] * inv;
+    Gi[r + (long long)t * ld] = w;
+    Gi[t + (long long)r * ld] = w;
+  }
+  // rank-one update Ginv += v v^T / delta: column groups x rows, coalesced
+  for (int c = cg; c < t; c += 4) {
+    const float vc = v[c] * inv;
+    float* col = Gi + (long long)c * ld;
+    for (int r = rl; r < t; r += 256) col[r] = fmaf(v[r], vc, col[r]);
+  }
+  if (tid == 0) {
+    I.s[t] = alpha;
+    Gi[t + (long long)t * ld] = inv;
     if (bad) atomicOr(I.status, ST_REFINE_INACCURATE);
+    *I.key = 0ull;
   }
-  __syncthreads();
-  for (int c = threadIdx.x; c < t1; c += kBlock) {
-    float acc = 0.f;
-    for (int r = c; r < t1; ++r) acc = fmaf(L[r + (long long)c * ld], I.z[r], acc);
-    I.s[c] = acc;
-  }
-  if (threadIdx.x == 0) *I.key = 0ull;
 }
 
 // ============================================================ rows kernels
@@ -411,8 +735,12 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const Inst* __restrict__ i
     float pg = 0.f;
     for (int l = threadIdx.x; l < t1; l += kBlock) pg = fmaf(sv[l], sv[l], pg);
     const float gamma = block_sum(pg, red);
-    const float gamma0 = (it == 0) ? gamma : I.st->gamma0;
-    if (it > 0 && gamma <= tol2 * gamma0) {
+    // stop once ||A_S^T r|| <= tol * ||A_S^T y|| (b holds A_S^T y of the bulk
+    // columns, equal to the master's up to the bulk rounding)
+    float pb = 0.f;
+    for (int l = threadIdx.x; l < t1; l += kBlock) pb = fmaf(I.b[l], I.b[l], pb);
+    const float bnorm2 = block_sum(pb, red);
+    if (gamma <= tol2 * bnorm2) {
       if (rt.tile == 0 && threadIdx.x == 0) I.st->cg_done = 1;
       return;
     }
@@ -424,10 +752,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const Inst* __restrict__ i
       coef[l] = p;
       if (rt.tile == 0) pnew[l] = p;
     }
-    if (rt.tile == 0 && threadIdx.x == 0) {
-      I.st->gamma[it & 1] = gamma;
-      if (it == 0) I.st->gamma0 = gamma;
-    }
+    if (rt.tile == 0 && threadIdx.x == 0) I.st->gamma[it & 1] = gamma;
   } else {
     for (int l = threadIdx.x; l < t1; l += kBlock) coef[l] = src[l];
   }
@@ -447,8 +772,21 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const Inst* __restrict__ i
   const int i = rt.i0 + lane;
   float acc = 0.f;
   if (i < rt.i1) {
-    for (int l = w; l < t1; l += kWaves)
-      acc = fmaf(Vec<TA>::one(A + (long long)sup[l] * lda + i), coef[l], acc);
+    // columns l = w, w+4, ...: eight independent chains keep eight loads in
+    // flight per lane
+    float a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = 0.f;
+    int l = w;
+    for (; l + 7 * kWaves < t1; l += 8 * kWaves) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int ll = l + u * kWaves;
+        a[u] = fmaf(Vec<TA>::one(A + (long long)sup[ll] * lda + i), coef[ll], a[u]);
+      }
+    }
+    for (; l < t1; l += kWaves) a[0] = fmaf(Vec<TA>::one(A + (long long)sup[l] * lda + i), coef[l], a[0]);
+    acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   }
   part[w * 64 + lane] = acc;
   __syncthreads();
@@ -670,15 +1008,15 @@ __global__ __launch_bounds__(kBlock) void copy_s_kernel(const Inst* __restrict__
 // ============================================================ launchers
 template <typename TA>
 static hipError_t scan_dispatch(int lpa, const Inst* d, const ScanTile* tiles, int ntiles,
-                                int r_lds_floats, hipStream_t s) {
+                                int r_lds_floats, int reverse, hipStream_t s) {
   const size_t lds = (size_t)r_lds_floats * sizeof(float);
   const int flag = r_lds_floats > 0;
   switch (lpa) {
-    case 4: hipLaunchKernelGGL((scan_kernel<TA, 4>), dim3(ntiles), dim3(kBlock), lds, s, d, tiles, flag); break;
-    case 8: hipLaunchKernelGGL((scan_kernel<TA, 8>), dim3(ntiles), dim3(kBlock), lds, s, d, tiles, flag); break;
-    case 16: hipLaunchKernelGGL((scan_kernel<TA, 16>), dim3(ntiles), dim3(kBlock), lds, s, d, tiles, flag); break;
-    case 32: hipLaunchKernelGGL((scan_kernel<TA, 32>), dim3(ntiles), dim3(kBlock), lds, s, d, tiles, flag); break;
-    default: hipLaunchKernelGGL((scan_kernel<TA, 64>), dim3(ntiles), dim3(kBlock), lds, s, d, tiles, flag); break;
+    case 4: hipLaunchKernelGGL((scan_kernel<TA, 4>), dim3(ntiles), dim3(kBlock), lds, s, d, tiles, flag, reverse); break;
+    case 8: hipLaunchKernelGGL((scan_kernel<TA, 8>), dim3(ntiles), dim3(kBlock), lds, s, d, tiles, flag, reverse); break;
+    case 16: hipLaunchKernelGGL((scan_kernel<TA, 16>), dim3(ntiles), dim3(kBlock), lds, s, d, tiles, flag, reverse); break;
+    case 32: hipLaunchKernelGGL((scan_kernel<TA, 32>), dim3(ntiles), dim3(kBlock), lds, s, d, tiles, flag, reverse); break;
+    default: hipLaunchKernelGGL((scan_kernel<TA, 64>), dim3(ntiles), dim3(kBlock), lds, s, d, tiles, flag, reverse); break;
   }
   return hipGetLastError();
 }
@@ -688,11 +1026,77 @@ hipError_t launch_init(const Inst* d, int count, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_scan(int bf16, int lpa, const Inst* d, const ScanTile* tiles, int ntiles,
-                       int r_lds_floats, hipStream_t s) {
+template <typename TA, int LPA>
+static hipError_t scan_reg_dispatch(int nch, const Inst* d, const ScanTile* tiles, int ntiles,
+                                    int reverse, hipStream_t s) {
+  const dim3 g(ntiles), b(kBlock);
+  switch (nch) {
+    case 1: hipLaunchKernelGGL((scan_reg_kernel<TA, LPA, 1>), g, b, 0, s, d, tiles, reverse); break;
+    case 2: hipLaunchKernelGGL((scan_reg_kernel<TA, LPA, 2>), g, b, 0, s, d, tiles, reverse); break;
+    case 4: hipLaunchKernelGGL((scan_reg_kernel<TA, LPA, 4>), g, b, 0, s, d, tiles, reverse); break;
+    case 8: hipLaunchKernelGGL((scan_reg_kernel<TA, LPA, 8>), g, b, 0, s, d, tiles, reverse); break;
+    default: hipLaunchKernelGGL((scan_reg_kernel<TA, LPA, 16>), g, b, 0, s, d, tiles, reverse); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename TA>
+static hipError_t scan_reg_lpa(int lpa, int nch, const Inst* d, const ScanTile* tiles, int ntiles,
+                               int reverse, hipStream_t s) {
+  switch (lpa) {
+    case 4: return scan_reg_dispatch<TA, 4>(nch, d, tiles, ntiles, reverse, s);
+    case 8: return scan_reg_dispatch<TA, 8>(nch, d, tiles, ntiles, reverse, s);
+    case 16: return scan_reg_dispatch<TA, 16>(nch, d, tiles, ntiles, reverse, s);
+    case 32: return scan_reg_dispatch<TA, 32>(nch, d, tiles, ntiles, reverse, s);
+    default: return scan_reg_dispatch<TA, 64>(nch, d, tiles, ntiles, reverse, s);
+  }
+}
+
+template <typename TA, int LPA>
+static hipError_t gram_reg_dispatch(int nch, const Inst* d, int nact, int t, int nblk, int D,
+                                    float lr_rel, float eps_rel, hipStream_t s) {
+  const dim3 g(nact * nblk), b(kBlock);
+  switch (nch) {
+    case 1: hipLaunchKernelGGL((gram_reg_kernel<TA, LPA, 1>), g, b, 0, s, d, t, nblk, D, lr_rel, eps_rel); break;
+    case 2: hipLaunchKernelGGL((gram_reg_kernel<TA, LPA, 2>), g, b, 0, s, d, t, nblk, D, lr_rel, eps_rel); break;
+    case 4: hipLaunchKernelGGL((gram_reg_kernel<TA, LPA, 4>), g, b, 0, s, d, t, nblk, D, lr_rel, eps_rel); break;
+    case 8: hipLaunchKernelGGL((gram_reg_kernel<TA, LPA, 8>), g, b, 0, s, d, t, nblk, D, lr_rel, eps_rel); break;
+    default: hipLaunchKernelGGL((gram_reg_kernel<TA, LPA, 16>), g, b, 0, s, d, t, nblk, D, lr_rel, eps_rel); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename TA>
+static hipError_t gram_reg_lpa(int lpa, int nch, const Inst* d, int nact, int t, int nblk, int D,
+                               float lr_rel, float eps_rel, hipStream_t s) {
+  switch (lpa) {
+    case 4: return gram_reg_dispatch<TA, 4>(nch, d, nact, t, nblk, D, lr_rel, eps_rel, s);
+    case 8: return gram_reg_dispatch<TA, 8>(nch, d, nact, t, nblk, D, lr_rel, eps_rel, s);
+    case 16: return gram_reg_dispatch<TA, 16>(nch, d, nact, t, nblk, D, lr_rel, eps_rel, s);
+    case 32: return gram_reg_dispatch<TA, 32>(nch, d, nact, t, nblk, D, lr_rel, eps_rel, s);
+    default: return gram_reg_dispatch<TA, 64>(nch, d, nact, t, nblk, D, lr_rel, eps_rel, s);
+  }
+}
+
+hipError_t launch_scan_reg(int bf16, int lpa, int nch, const Inst* d, const ScanTile* tiles,
+                           int ntiles, int reverse, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  return bf16 ? scan_dispatch<uint16_t>(lpa, d, tiles, ntiles, r_lds_floats, s)
-              : scan_dispatch<float>(lpa, d, tiles, ntiles, r_lds_floats, s);
+  return bf16 ? scan_reg_lpa<uint16_t>(lpa, nch, d, tiles, ntiles, reverse, s)
+              : scan_reg_lpa<float>(lpa, nch, d, tiles, ntiles, reverse, s);
+}
+
+hipError_t launch_gram_reg(int bf16, int lpa, int nch, const Inst* d, int nact, int t, int nblk,
+                           int D, float lr_rel, float eps_rel, hipStream_t s) {
+  if (nact <= 0) return hipSuccess;
+  return bf16 ? gram_reg_lpa<uint16_t>(lpa, nch, d, nact, t, nblk, D, lr_rel, eps_rel, s)
+              : gram_reg_lpa<float>(lpa, nch, d, nact, t, nblk, D, lr_rel, eps_rel, s);
+}
+
+hipError_t launch_scan(int bf16, int lpa, const Inst* d, const ScanTile* tiles, int ntiles,
+                       int r_lds_floats, int reverse, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  return bf16 ? scan_dispatch<uint16_t>(lpa, d, tiles, ntiles, r_lds_floats, reverse, s)
+              : scan_dispatch<float>(lpa, d, tiles, ntiles, r_lds_floats, reverse, s);
 }
 
 template <typename TA>
@@ -721,15 +1125,19 @@ hipError_t launch_gram(int bf16, int lpa, const Inst* d, int nact, int t, int nb
 hipError_t launch_adam(const Inst* d, int nact, int t, int T, float beta1, float beta2,
                        hipStream_t s) {
   if (nact <= 0) return hipSuccess;
-  hipLaunchKernelGGL(adam_kernel, dim3(nact), dim3(kBlock), (size_t)(t + 1) * sizeof(float), s,
-                     d, t, T, beta1, beta2);
+  if (t + 1 <= kRegRows)
+    hipLaunchKernelGGL(adam_reg_kernel, dim3(nact), dim3(64 * ((t + 16) / 16)), 0, s, d, t, T,
+                       beta1, beta2);
+  else
+    hipLaunchKernelGGL(adam_kernel, dim3(nact), dim3(kBlock), (size_t)(t + 1) * sizeof(float), s,
+                       d, t, T, beta1, beta2);
   return hipGetLastError();
 }
 
 hipError_t launch_omp(const Inst* d, int nact, int t, hipStream_t s) {
   if (nact <= 0) return hipSuccess;
-  hipLaunchKernelGGL(omp_chol_kernel, dim3(nact), dim3(kBlock), (size_t)2 * (t + 1) * sizeof(float),
-                     s, d, t);
+  hipLaunchKernelGGL(omp_ginv_kernel, dim3(nact), dim3(kOmpThreads),
+                     (size_t)6 * (t + 1) * sizeof(float), s, d, t);
   return hipGetLastError();
 }
 
