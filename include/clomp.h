@@ -70,6 +70,10 @@ typedef enum {
 #define CLOMP_FLAG_PROFILE 8u        /* record HIP events around every phase
                                         launch (ignored while capturing graphs);
                                         read with clomp_profile_read           */
+#define CLOMP_FLAG_RESIDUAL_FLOW 16u /* always use the residual schedule      */
+#define CLOMP_FLAG_CORR_FLOW 32u     /* always use the correlation-update
+                                        schedule (default: only for batches of
+                                        at most 8 signals)                     */
 
 /*
  * Solver parameters.  The paper states the optimiser only as automatic
@@ -200,23 +204,35 @@ clomp_status_t clomp_grad(clomp_handle_t h, int32_t n, int32_t m, int64_t lda,
                           void* loss, void* hip_stream);
 
 /*
+ * Schedules.  The residual schedule runs, per iteration, a scan c = A^T r with
+ * the argmax, the Gram column, the coefficient update and r = y - A_S s.  The
+ * correlation-update schedule (few large signals) uses c = A^T y - H s with
+ * H[:, l] = A^T a_{S_l}: each iteration's pass over A computes the new column
+ * of H and runs in the same launch as the coefficient update, and a scan of H
+ * gives the next argmax.  Both compute the same correlations.
+ *
  * Phase timings gathered under CLOMP_FLAG_PROFILE, accumulated over every
- * solve since the last clomp_profile_reset.  Phases: 0 scan (c = A^T r and
- * argmax), 1 gram (selection record and new Gram column), 2 coef (Adam or the
- * OMP update), 3 resid (r = y - A_S s), 4 refine (QR or CGLS), 5 norm (FP64
- * residual norm and output scatter), 6 init.
+ * solve since the last clomp_profile_reset.  Phases: 0 scan (residual
+ * schedule: c = A^T r and argmax; correlation schedule: c = A^T y or
+ * c0 - H s and argmax), 1 gram (selection record and new Gram column),
+ * 2 coef (Adam or the OMP update), 3 resid (r = y - A_S s), 4 refine (QR or
+ * CGLS), 5 norm (FP64 residual norm and output scatter), 6 init, 7 pass
+ * (correlation schedule: coefficient update fused with the pass over A).
  *   ms[p]        summed device time between HIP events recorded on the launch
  *                stream immediately before and after each launch of phase p
  *   launches[p]  number of launches of phase p
- *   scan_bytes   algorithmic bytes of the scan launches: for every active
- *                instance and iteration, m*n*elem (the bulk columns) + 4m (r)
- *                + n/8 (selection bitmap)
+ *   scan_bytes   algorithmic bytes of phase-0 launches: per active instance,
+ *                m*n*elem + 4m + n/8 for a scan of A, or 4*n*(t+1) + n/8 for
+ *                a scan of H at iteration t
+ *   pass_bytes   algorithmic bytes of phase-7 launches: m*n*elem + 4n per
+ *                active instance (the bulk columns and the new column of H)
  * Synchronises on the recorded events.  Errors: INVALID_ARGUMENT, DEVICE_ERROR.
  */
 typedef struct {
   double ms[8];
   int64_t launches[8];
   double scan_bytes;
+  double pass_bytes;
 } clomp_profile_t;
 
 clomp_status_t clomp_profile_read(clomp_handle_t h, clomp_profile_t* out /*host*/);

@@ -22,7 +22,8 @@ F32, BF16, F64 = 0, 1, 2
 METHOD_CLOMP, METHOD_OMP = 0, 1
 ST_NAN, ST_K_CAPPED, ST_ZERO_Y, ST_REFINE_INACCURATE, ST_WATCHDOG = 1, 2, 4, 8, 32
 FLAG_GRAPH, FLAG_NO_FUSED_SMALL, FLAG_AUTOTUNE, FLAG_PROFILE = 1, 2, 4, 8
-PHASES = ("scan", "gram", "coef", "resid", "refine", "norm", "init")
+FLAG_RESIDUAL_FLOW, FLAG_CORR_FLOW = 16, 32
+PHASES = ("scan", "gram", "coef", "resid", "refine", "norm", "init", "pass")
 
 STATUS_NAMES = {0: "CLOMP_OK", 1: "CLOMP_INVALID_ARGUMENT", 2: "CLOMP_OUT_OF_MEMORY",
                 3: "CLOMP_DEVICE_ERROR", 4: "CLOMP_NOT_SUPPORTED"}
@@ -48,7 +49,7 @@ class Instance(ctypes.Structure):
 
 class Profile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_int64 * 8),
-                ("scan_bytes", ctypes.c_double)]
+                ("scan_bytes", ctypes.c_double), ("pass_bytes", ctypes.c_double)]
 
 
 class ClompError(RuntimeError):
@@ -182,7 +183,7 @@ class Solver:
                "clomp_profile_read")
         return {"ms": {PHASES[i]: p.ms[i] for i in range(len(PHASES))},
                 "launches": {PHASES[i]: int(p.launches[i]) for i in range(len(PHASES))},
-                "scan_bytes": p.scan_bytes}
+                "scan_bytes": p.scan_bytes, "pass_bytes": p.pass_bytes}
 
     # ------------------------------------------------------------------ solve
     def solve_batch(self, items, stream=None):

@@ -12,7 +12,8 @@
 //   z      [k_eff]       float   OMP: Linv * b
 //   cg     [...]         float   CGLS vectors (two r, two p, q, sv)
 //   bitmap [ceil(n/32)]  uint32  selected-atom mask
-//   key    u64           packed argmax key of the current scan
+//   key    u64[2]        packed argmax key of the current scan (the
+//                        correlation-update schedule alternates the two slots)
 //   st     InstState     scalar state (sigma, lr, eps, step, flags)
 #pragma once
 
@@ -56,6 +57,10 @@ struct Inst {
   float* Linv;
   float* z;
   float* cg;           // r0[m_pad] r1[m_pad] q[m_pad] p0[k] p1[k] sv[k]
+  float* c0;           // [ldh] A^T y (correlation-update schedule)
+  float* dg;           // [ldh] ||a_j||^2 (correlation-update schedule)
+  float* H;            // [ldh * k_eff] columns A^T a_{S_l} (correlation-update schedule)
+  long long ldh;
   double* npart;       // [n_rowtiles] FP64 residual-norm partial sums
   float* qpart;        // [n_rowtiles] CGLS ||q||^2 partial sums
   unsigned long long* key;

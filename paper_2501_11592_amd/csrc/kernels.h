@@ -34,6 +34,15 @@ hipError_t launch_norm(const Inst* d, const RowTile* tiles, int ntiles, int tmax
 hipError_t launch_finalize(const Inst* d, int count, int check_cg, hipStream_t s);
 hipError_t set_max_lds(size_t bytes);
 
+// correlation-update schedule (few large signals)
+hipError_t launch_ypass(int bf16, int lpa, const Inst* d, const ScanTile* tiles, int ntiles,
+                        size_t lds, hipStream_t s);
+hipError_t launch_coef_pass(int bf16, int lpa, int omp, const Inst* dc, int nact, const Inst* d,
+                            const ScanTile* tiles, int ntiles, int t, int T, float beta1,
+                            float beta2, float lr_rel, float eps_rel, size_t lds, hipStream_t s);
+hipError_t launch_cscan(const Inst* d, const ScanTile* tiles, int ntiles, int t, hipStream_t s);
+hipError_t set_max_lds_pass(size_t bytes);
+
 // clomp_grad kernels
 hipError_t launch_grad(int f64, int n, int m, long long lda, const void* A, const void* x,
                        const unsigned char* mask, const void* y, const void* grad_out,

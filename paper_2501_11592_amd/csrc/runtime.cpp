@@ -35,6 +35,8 @@ namespace {
 constexpr int kMaxKeff = kBlock * 8;        // Adam kernel row capacity
 constexpr size_t kAlign = 256;
 constexpr int kScanTargetBytes = 128 * 1024; // bulk bytes streamed per scan WG
+constexpr int kPassTargetBytes = 256 * 1024; // bulk bytes per pass WG (1024 threads)
+constexpr int kPassThreadsHost = 1024;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 int round_up_int(int v, int a) { return (v + a - 1) / a * a; }
@@ -53,6 +55,8 @@ struct Class {
   int m_pad_max = 0;
   int kmax = 0;
   int nch = 0;                        // register-kernel vectors per lane (0: LDS kernels)
+  std::vector<int> htile_prefix, ctile_prefix;
+  size_t htile_off = 0, ctile_off = 0;
 };
 
 struct Plan {
@@ -65,6 +69,10 @@ struct Plan {
   std::vector<RowTile> cg_rows;       // row tiles of CGLS instances
   size_t qr_lds = 0;
   int kmax = 0, cg_tmax = 0, cg_mpad_max = 0, cg_lpa = 64;
+  bool hflow = false;                 // correlation-update schedule
+  std::vector<ScanTile> htiles;       // pass tiles (1024-thread workgroups)
+  std::vector<ScanTile> ctiles;       // 64-atom tiles of the H scan
+  size_t off_htiles = 0, off_ctiles = 0;
   size_t ws_bytes = 0;
   size_t off_insts = 0, off_tiles = 0, off_rows = 0, off_qr = 0, off_cg = 0, off_cgrows = 0;
   size_t table_bytes = 0;
@@ -97,8 +105,9 @@ struct clomp_ctx {
   size_t ev_used = 0;
   struct Rec { int phase; hipEvent_t a, b; };
   std::vector<Rec> recs;
-  double scan_bytes = 0.0;
+  double scan_bytes = 0.0, pass_bytes = 0.0;
   bool profiling = false;
+  bool pass_lds_ok = false;           // dynamic-LDS ceiling raised for pass kernels
 };
 
 namespace {
@@ -195,6 +204,8 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
   const bool omp = prm.method == CLOMP_METHOD_OMP;
   const int vw = bf16 ? 8 : 4;
   const size_t esize = bf16 ? 2 : 4;
+  char sigbuf[96];
+  P.sig.clear();
   // order: by class (lpa desc), then k_eff desc, then input index
   std::vector<int> order(count);
   std::vector<int> lpa(count), keff(count);
@@ -208,12 +219,28 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     return keff[a] > keff[b];
   });
   const int qr_limit_floats = ((int)std::min<size_t>((size_t)h->lds_limit, 96 * 1024) - 1024) / 4;
+  {
+    // correlation-update schedule: few signals, H within budget, the pass
+    // kernel's staged vector within LDS next to its 33 KB of static LDS
+    size_t hbytes = 0;
+    int mpad_max = 0;
+    for (int i = 0; i < count; ++i) {
+      hbytes += sizeof(float) * (size_t)round_up_int(inst[i].n, 64) * keff[i];
+      mpad_max = std::max(mpad_max, round_up_int(inst[i].m, 8));
+    }
+    const bool fits = h->pass_lds_ok &&
+                      (size_t)mpad_max * 4 + 34 * 1024 <= (size_t)h->lds_limit &&
+                      hbytes <= (size_t)16 << 30;
+    const uint32_t fl = prm.flags;
+    P.hflow = fits && !(fl & CLOMP_FLAG_RESIDUAL_FLOW) &&
+              ((fl & CLOMP_FLAG_CORR_FLOW) || count <= 8);
+  }
+  snprintf(sigbuf, sizeof sigbuf, "h%d;", (int)P.hflow);
+  P.sig += sigbuf;
   P.insts.resize(count);
   P.keff.resize(count);
   P.kmax = 0;
   size_t ws = 0;
-  char sigbuf[96];
-  P.sig.clear();
   snprintf(sigbuf, sizeof sigbuf, "d%d;m%d;T%d;", bf16, prm.method, prm.inner_steps);
   P.sig += sigbuf;
   for (int s = 0; s < count; ++s) {
@@ -256,9 +283,16 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     const size_t o_z = take(sizeof(float) * d.k_eff);
     const size_t o_L = omp ? take(sizeof(float) * (size_t)d.k_eff * d.ldg) : 0;
     const size_t o_cg = use_qr ? 0 : take(sizeof(float) * (3 * (size_t)d.m_pad + 3 * d.k_eff));
+    size_t o_c0 = 0, o_H = 0, o_dg = 0;
+    if (P.hflow) {
+      d.ldh = round_up_int(d.n, 256);
+      o_c0 = take(sizeof(float) * d.ldh);
+      o_dg = take(sizeof(float) * d.ldh);
+      o_H = take(sizeof(float) * (size_t)d.ldh * d.k_eff);
+    }
     const size_t o_np = take(sizeof(double) * d.n_rowtiles);
     const size_t o_qp = take(sizeof(float) * d.n_rowtiles);
-    const size_t o_key = take(sizeof(unsigned long long));
+    const size_t o_key = take(2 * sizeof(unsigned long long));
     const size_t o_bm = take(sizeof(unsigned) * ((d.n + 31) / 32));
     const size_t o_st = take(sizeof(InstState));
     // store offsets in the pointer fields for now (+1 so 0 means "absent")
@@ -272,6 +306,9 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     d.z = (float*)(o_z + 1);
     d.Linv = omp ? (float*)(o_L + 1) : nullptr;
     d.cg = use_qr ? nullptr : (float*)(o_cg + 1);
+    d.c0 = P.hflow ? (float*)(o_c0 + 1) : nullptr;
+    d.dg = P.hflow ? (float*)(o_dg + 1) : nullptr;
+    d.H = P.hflow ? (float*)(o_H + 1) : nullptr;
     d.npart = (double*)(o_np + 1);
     d.qpart = (float*)(o_qp + 1);
     d.key = (unsigned long long*)(o_key + 1);
@@ -311,6 +348,22 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
       for (int tt = 0; tt < d.n_rowtiles; ++tt)
         P.rows.push_back({q, tt * 64, std::min(d.m, tt * 64 + 64), tt});
       c.row_prefix.push_back((int)(P.rows.size() - c.row_off));
+      if (P.hflow) {
+        if (c.htile_prefix.empty()) {
+          c.htile_prefix.push_back(0);
+          c.ctile_prefix.push_back(0);
+          c.htile_off = P.htiles.size();
+          c.ctile_off = P.ctiles.size();
+        }
+        const int hng = kPassThreadsHost / c.lpa;
+        const int happ = (int)std::max<size_t>(1, kPassTargetBytes / (atom_bytes * hng));
+        const int hapt = hng * happ;
+        for (int j0 = 0; j0 < d.n; j0 += hapt)
+          P.htiles.push_back({q, j0, std::min(d.n, j0 + hapt), 0});
+        c.htile_prefix.push_back((int)(P.htiles.size() - c.htile_off));
+        for (int j0 = 0; j0 < d.n; j0 += 64) P.ctiles.push_back({q, j0, std::min(d.n, j0 + 64), 0});
+        c.ctile_prefix.push_back((int)(P.ctiles.size() - c.ctile_off));
+      }
       c.m_pad_max = std::max(c.m_pad_max, d.m_pad);
       c.kmax = std::max(c.kmax, d.k_eff);
     }
@@ -362,6 +415,8 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
   P.off_qr = place(sizeof(int) * P.qr_list.size());
   P.off_cg = place(sizeof(int) * P.cg_list.size());
   P.off_cgrows = place(sizeof(RowTile) * P.cg_rows.size());
+  P.off_htiles = place(sizeof(ScanTile) * P.htiles.size());
+  P.off_ctiles = place(sizeof(ScanTile) * P.ctiles.size());
   P.table_bytes = std::max<size_t>(off, kAlign);
 }
 
@@ -393,7 +448,7 @@ void drop_graphs(clomp_ctx* h) {
   h->graphs.clear();
 }
 
-enum Phase { PH_SCAN = 0, PH_GRAM, PH_COEF, PH_RESID, PH_REFINE, PH_NORM, PH_INIT };
+enum Phase { PH_SCAN = 0, PH_GRAM, PH_COEF, PH_RESID, PH_REFINE, PH_NORM, PH_INIT, PH_PASS };
 
 hipEvent_t pool_event(clomp_ctx* h) {
   if (h->ev_used == h->ev_pool.size()) {
@@ -422,6 +477,67 @@ struct PhaseScope {
   }
 };
 
+// Greedy loop of the correlation-update schedule.
+clomp_status_t launch_hflow(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st) {
+  const clomp_params_t& prm = h->params;
+  const bool omp = prm.method == CLOMP_METHOD_OMP;
+  char* tb = reinterpret_cast<char*>(h->tables.p);
+  const Inst* d_insts = reinterpret_cast<const Inst*>(tb + P.off_insts);
+  const ScanTile* d_htiles = reinterpret_cast<const ScanTile*>(tb + P.off_htiles);
+  const ScanTile* d_ctiles = reinterpret_cast<const ScanTile*>(tb + P.off_ctiles);
+  const double esz = bf16 ? 2.0 : 4.0;
+  auto nactive = [&](const Class& c, int t) {
+    int q = 0;
+    while (c.i0 + q < c.i1 && P.keff[c.i0 + q] > t) ++q;
+    return q;
+  };
+  // c0 = A^T y and the first argmax
+  for (const Class& c : P.classes) {
+    const int nall = c.i1 - c.i0;
+    const size_t lds = (size_t)c.m_pad_max * sizeof(float);
+    PhaseScope ps(h, PH_SCAN, st);
+    HIP_TRY(launch_ypass(bf16, c.lpa, d_insts, d_htiles + c.htile_off, c.htile_prefix[nall], lds,
+                         st),
+            "ypass");
+    if (h->profiling)
+      for (int q = c.i0; q < c.i1; ++q)
+        h->scan_bytes += (double)P.insts[q].m * P.insts[q].n * esz + 4.0 * P.insts[q].m;
+  }
+  for (int t = 0; t < P.kmax; ++t) {
+    for (const Class& c : P.classes) {
+      if (c.kmax <= t) continue;
+      const int nact = nactive(c, t);
+      const int nnext = nactive(c, t + 1);
+      {
+        // selection record, Gram column gathered from H, coefficient update of
+        // iteration t, fused with h_t = A^T a_{S_t} for the instances that
+        // select again
+        const size_t t1 = (size_t)t + 1;
+        size_t lds = (size_t)c.m_pad_max * sizeof(float);
+        lds = std::max(lds, (omp ? 6 : 1) * t1 * sizeof(float));
+        PhaseScope ps(h, PH_PASS, st);
+        HIP_TRY(launch_coef_pass(bf16, c.lpa, omp, d_insts + c.i0, nact, d_insts,
+                                 d_htiles + c.htile_off, c.htile_prefix[nnext], t,
+                                 prm.inner_steps, prm.beta1, prm.beta2, prm.lr_rel, prm.eps_rel,
+                                 lds, st),
+                "coef_pass");
+        if (h->profiling)
+          for (int q = c.i0; q < c.i0 + nnext; ++q)
+            h->pass_bytes += (double)P.insts[q].m * P.insts[q].n * esz + 4.0 * P.insts[q].n;
+      }
+      if (nnext > 0) {
+        PhaseScope ps(h, PH_SCAN, st);
+        HIP_TRY(launch_cscan(d_insts, d_ctiles + c.ctile_off, c.ctile_prefix[nnext], t + 1, st),
+                "cscan");
+        if (h->profiling)
+          for (int q = c.i0; q < c.i0 + nnext; ++q)
+            h->scan_bytes += 4.0 * P.insts[q].n * (t + 2) + P.insts[q].n / 8.0;
+      }
+    }
+  }
+  return CLOMP_OK;
+}
+
 // The launch sequence of one batch (captured as a graph when requested).
 clomp_status_t launch_all(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st) {
   const clomp_params_t& prm = h->params;
@@ -440,7 +556,11 @@ clomp_status_t launch_all(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st)
     PhaseScope ps(h, PH_INIT, st);
     HIP_TRY(launch_init(d_insts, count, st), "init");
   }
-  for (int t = 0; t < P.kmax; ++t) {
+  if (P.hflow) {
+    clomp_status_t hs = launch_hflow(h, P, bf16, st);
+    if (hs != CLOMP_OK) return hs;
+  }
+  for (int t = 0; t < (P.hflow ? 0 : P.kmax); ++t) {
     for (const Class& c : P.classes) {
       if (c.kmax <= t) continue;
       // active prefix of the class: instances with k_eff > t
@@ -598,6 +718,8 @@ clomp_status_t clomp_create(clomp_handle_t* out, int device, const clomp_params_
     (void)hipGetLastError();
     h->lds_limit = 65536;
   }
+  h->pass_lds_ok = set_max_lds_pass((size_t)h->lds_limit) == hipSuccess;
+  if (!h->pass_lds_ok) (void)hipGetLastError();
   if (hipEventCreateWithFlags(&h->staging_free, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&h->work_done, hipEventDisableTiming) != hipSuccess) {
     delete h;
@@ -654,7 +776,9 @@ clomp_status_t clomp_solve_batch(clomp_handle_t h, const clomp_instance_t* inst,
                    wsb + (reinterpret_cast<uintptr_t>(ptr) - 1));
     };
     rb(d.r); rb(d.G); rb(d.b); rb(d.s); rb(d.mo); rb(d.ve); rb(d.xf); rb(d.z);
-    rb(d.Linv); rb(d.cg); rb(d.npart); rb(d.qpart); rb(d.key); rb(d.bitmap); rb(d.st);
+    rb(d.Linv); rb(d.cg); rb(d.c0); rb(d.dg); rb(d.H); rb(d.npart); rb(d.qpart); rb(d.key);
+    rb(d.bitmap);
+    rb(d.st);
   }
   // stage tables in pinned memory and upload on the stream
   if (h->pinned_bytes < P.table_bytes) {
@@ -682,6 +806,10 @@ clomp_status_t clomp_solve_batch(clomp_handle_t h, const clomp_instance_t* inst,
   if (!P.cg_list.empty()) memcpy(hb + P.off_cg, P.cg_list.data(), sizeof(int) * P.cg_list.size());
   if (!P.cg_rows.empty())
     memcpy(hb + P.off_cgrows, P.cg_rows.data(), sizeof(RowTile) * P.cg_rows.size());
+  if (!P.htiles.empty())
+    memcpy(hb + P.off_htiles, P.htiles.data(), sizeof(ScanTile) * P.htiles.size());
+  if (!P.ctiles.empty())
+    memcpy(hb + P.off_ctiles, P.ctiles.data(), sizeof(ScanTile) * P.ctiles.size());
   // the previous batch (possibly on another stream) must be done with the tables
   if (h->have_work) HIP_TRY(hipStreamWaitEvent(st, h->work_done, 0), "hipStreamWaitEvent");
   HIP_TRY(hipMemcpyAsync(h->tables.p, hb, P.table_bytes, hipMemcpyHostToDevice, st),
@@ -757,6 +885,7 @@ clomp_status_t clomp_profile_reset(clomp_handle_t h) {
   h->recs.clear();
   h->ev_used = 0;
   h->scan_bytes = 0.0;
+  h->pass_bytes = 0.0;
   return CLOMP_OK;
 }
 
@@ -771,6 +900,7 @@ clomp_status_t clomp_profile_read(clomp_handle_t h, clomp_profile_t* out) {
     out->launches[r.phase] += 1;
   }
   out->scan_bytes = h->scan_bytes;
+  out->pass_bytes = h->pass_bytes;
   return CLOMP_OK;
 }
 

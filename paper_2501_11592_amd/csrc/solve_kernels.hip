@@ -49,7 +49,8 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const Inst* __restrict__ i
     InstState st = {};
     st.done = any_nz ? 0 : 1;
     *I.st = st;
-    *I.key = 0ull;
+    I.key[0] = 0ull;
+    I.key[1] = 0ull;
     *I.nsel = 0;
     unsigned status = (I.k > I.k_eff) ? ST_K_CAPPED : 0u;
     if (!any_nz) status |= ST_ZERO_Y;
@@ -405,12 +406,12 @@ __global__ __launch_bounds__(kBlock) void gram_reg_kernel(const Inst* __restrict
 //   s -= lr * (m / bc1) / (sqrt(v / bc2) + eps)
 // with bias corrections bc = 1 - beta^step (Kingma & Ba, Algorithm 1).  The
 // instance key is cleared for the next scan.
-constexpr int kRPT = 8;  // supports k_eff <= kBlock * kRPT = 2048
+constexpr int kMaxRows = 2048;  // k_eff capacity of the coefficient kernels
 
-__global__ __launch_bounds__(kBlock) void adam_kernel(const Inst* __restrict__ insts, int t,
-                                                      int T, float beta1, float beta2) {
-  extern __shared__ float ssh[];  // s[t+1]
-  const Inst& I = insts[blockIdx.x];
+template <int NT>
+__device__ void adam_global_body(const Inst& I, int t, int T, float beta1, float beta2,
+                                 float* ssh, bool clear_key = true) {
+  constexpr int kRPT = kMaxRows / NT;
   if (I.st->done) {
     if (threadIdx.x == 0) *I.key = 0ull;
     return;
@@ -421,7 +422,7 @@ __global__ __launch_bounds__(kBlock) void adam_kernel(const Inst* __restrict__ i
   float mo[kRPT], ve[kRPT], bb[kRPT], g[kRPT];
 #pragma unroll
   for (int q = 0; q < kRPT; ++q) {
-    const int r = threadIdx.x + q * kBlock;
+    const int r = threadIdx.x + q * NT;
     if (r < t1) {
       ssh[r] = I.s[r];
       mo[q] = I.mo[r];
@@ -446,7 +447,7 @@ __global__ __launch_bounds__(kBlock) void adam_kernel(const Inst* __restrict__ i
       const float* G0 = G + (long long)c * ldg;
 #pragma unroll
       for (int q = 0; q < kRPT; ++q) {
-        const int r = threadIdx.x + q * kBlock;
+        const int r = threadIdx.x + q * NT;
         if (r < t1) {
           const float u0 = G0[r], u1 = G0[ldg + r], u2 = G0[2 * ldg + r], u3 = G0[3 * ldg + r];
           g[q] = fmaf(u3, s3, fmaf(u2, s2, fmaf(u1, s1, fmaf(u0, s0, g[q]))));
@@ -458,14 +459,14 @@ __global__ __launch_bounds__(kBlock) void adam_kernel(const Inst* __restrict__ i
       const float* Gc = G + (long long)c * ldg;
 #pragma unroll
       for (int q = 0; q < kRPT; ++q) {
-        const int r = threadIdx.x + q * kBlock;
+        const int r = threadIdx.x + q * NT;
         if (r < t1) g[q] = fmaf(Gc[r], sc, g[q]);
       }
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kRPT; ++q) {
-      const int r = threadIdx.x + q * kBlock;
+      const int r = threadIdx.x + q * NT;
       if (r < t1) {
         const float gr = g[q] - bb[q];
         mo[q] = beta1 * mo[q] + (1.f - beta1) * gr;
@@ -479,7 +480,7 @@ __global__ __launch_bounds__(kBlock) void adam_kernel(const Inst* __restrict__ i
   }
 #pragma unroll
   for (int q = 0; q < kRPT; ++q) {
-    const int r = threadIdx.x + q * kBlock;
+    const int r = threadIdx.x + q * NT;
     if (r < t1) {
       I.s[r] = ssh[r];
       I.mo[r] = mo[q];
@@ -488,8 +489,14 @@ __global__ __launch_bounds__(kBlock) void adam_kernel(const Inst* __restrict__ i
   }
   if (threadIdx.x == 0) {
     I.st->step = step0 + T;
-    *I.key = 0ull;
+    if (clear_key) *I.key = 0ull;
   }
+}
+
+__global__ __launch_bounds__(kBlock) void adam_kernel(const Inst* __restrict__ insts, int t,
+                                                      int T, float beta1, float beta2) {
+  extern __shared__ float ssh[];  // s[t+1]
+  adam_global_body<kBlock>(insts[blockIdx.x], t, T, beta1, beta2, ssh);
 }
 
 // Register-resident variant for t+1 <= 256 (1024 threads, 16 waves).
@@ -502,12 +509,8 @@ __global__ __launch_bounds__(kBlock) void adam_kernel(const Inst* __restrict__ i
 // row's 16 partials are then added in a fixed order.
 constexpr int kRegRows = 256;
 
-__global__ __launch_bounds__(1024) void adam_reg_kernel(const Inst* __restrict__ insts, int t,
-                                                        int T, float beta1, float beta2) {
-  __shared__ float4 part[2][16][64];   // [buffer][wave][lane] -> rows 4l..4l+3
-  // the launch uses ceil((t+1)/16) waves: every wave owns live columns
-  const int nw = blockDim.x >> 6;
-  const Inst& I = insts[blockIdx.x];
+__device__ void adam_reg_body(const Inst& I, int t, int T, float beta1, float beta2,
+                              float4 (*part)[16][64], int nw, bool clear_key = true) {
   if (I.st->done) {
     if (threadIdx.x == 0) *I.key = 0ull;
     return;
@@ -606,8 +609,15 @@ __global__ __launch_bounds__(1024) void adam_reg_kernel(const Inst* __restrict__
   }
   if (threadIdx.x == 0) {
     I.st->step = step0 + T;
-    *I.key = 0ull;
+    if (clear_key) *I.key = 0ull;
   }
+}
+
+__global__ __launch_bounds__(1024) void adam_reg_kernel(const Inst* __restrict__ insts, int t,
+                                                        int T, float beta1, float beta2) {
+  __shared__ float4 part[2][16][64];   // [buffer][wave][lane] -> rows 4l..4l+3
+  // the launch uses ceil((t+1)/16) waves: every wave owns live columns
+  adam_reg_body(insts[blockIdx.x], t, T, beta1, beta2, part, blockDim.x >> 6);
 }
 
 // ============================================================ OMP coefficients
@@ -621,11 +631,8 @@ __global__ __launch_bounds__(1024) void adam_reg_kernel(const Inst* __restrict__
 // updated by consecutive rows r); there is no sequential triangular solve.
 constexpr int kOmpThreads = 1024;
 
-__global__ __launch_bounds__(kOmpThreads) void omp_ginv_kernel(const Inst* __restrict__ insts,
-                                                               int t) {
-  extern __shared__ float osh[];  // g[t1] | v[t1] | vpart[4][t1]
-  __shared__ float red[kOmpThreads / 64];
-  const Inst& I = insts[blockIdx.x];
+__device__ void omp_ginv_body(const Inst& I, int t, float* osh, float* red, float* red2,
+                              bool clear_key = true) {
   if (I.st->done) {
     if (threadIdx.x == 0) *I.key = 0ull;
     return;
@@ -663,7 +670,6 @@ __global__ __launch_bounds__(kOmpThreads) void omp_ginv_kernel(const Inst* __res
   // block sums (fixed order over the 16 waves)
   pv = wave_sum(pv);
   px = wave_sum(px);
-  __shared__ float red2[kOmpThreads / 64];
   if ((tid & 63) == 0) {
     red[tid >> 6] = pv;
     red2[tid >> 6] = px;
@@ -697,8 +703,15 @@ __global__ __launch_bounds__(kOmpThreads) void omp_ginv_kernel(const Inst* __res
     I.s[t] = alpha;
     Gi[t + (long long)t * ld] = inv;
     if (bad) atomicOr(I.status, ST_REFINE_INACCURATE);
-    *I.key = 0ull;
+    if (clear_key) *I.key = 0ull;
   }
+}
+
+__global__ __launch_bounds__(kOmpThreads) void omp_ginv_kernel(const Inst* __restrict__ insts,
+                                                               int t) {
+  extern __shared__ float osh[];  // g[t1] | v[t1] | vpart[4][t1]
+  __shared__ float red[kOmpThreads / 64], red2[kOmpThreads / 64];
+  omp_ginv_body(insts[blockIdx.x], t, osh, red, red2);
 }
 
 // ============================================================ rows kernels
@@ -1005,6 +1018,257 @@ __global__ __launch_bounds__(kBlock) void copy_s_kernel(const Inst* __restrict__
   if (threadIdx.x == 0) I.st->cg_done = 0;
 }
 
+// ============================================================ correlation-update schedule
+// For one (or a few) large signals the greedy loop is latency bound: the
+// Adam steps of an iteration are a serial chain on one CU while the scan
+// needs the whole GPU.  By linearity
+//   c = A^T r = A^T (y - A_S s) = A^T y - sum_l s_l (A^T a_{S_l}),
+// so with c0 = A^T y and H[:, l] = A^T a_{S_l} stored, the correlation of
+// iteration t+1 is c0 - H s (n * t multiply-adds from L2/MALL) and the one
+// full pass over A per iteration computes h_t = A^T a_{j_t}, which depends
+// only on the selected atom.  That pass runs in the same launch as the
+// coefficient update of iteration t (block 0 updates, the other blocks
+// stream A), hiding the serial Adam chain behind the HBM-bound pass.
+
+constexpr int kPassThreads = 1024;
+
+// One tile of a pass over A with a staged vector v (zero padded):
+//   MODE 0: v = y, writes c0[j] = a_j^T y and the argmax key of |c0|
+//   MODE 1: v = a_{S_t}, writes H[j, t] = a_j^T a_{S_t}
+template <typename TA, int LPA, int MODE>
+__device__ void pass_tile_body(const Inst& I, const ScanTile& tile, int t, float* vsh,
+                               unsigned long long* wbest) {
+  if (I.st->done) return;
+  constexpr int VW = Vec<TA>::W;
+  constexpr int NT = kPassThreads;
+  const int m = I.m;
+  const int nvec = (m + VW - 1) / VW;
+  const int tail = m - (nvec - 1) * VW;
+  const TA* A = reinterpret_cast<const TA*>(I.A);
+  const long long lda = I.lda;
+  if (MODE == 0) {
+    const float* yw = I.r + I.m_pad;   // zero padded beyond m
+    for (int i = threadIdx.x; i < nvec * VW; i += NT) vsh[i] = yw[i];
+  } else {
+    // the atom selected by the scan of iteration t (key slot t & 1 is not
+    // cleared before this launch ends)
+    const int jt = key_index(I.key[t & 1]);
+    if (jt < 0 || jt >= I.n) return;
+    const TA* colj = A + (long long)jt * lda;
+    for (int c = threadIdx.x; c < nvec; c += NT) {
+      float a[VW];
+      Vec<TA>::load(colj + (long long)c * VW, a);
+#pragma unroll
+      for (int e = 0; e < VW; ++e) vsh[c * VW + e] = (c * VW + e < m) ? a[e] : 0.f;
+    }
+  }
+  __syncthreads();
+  const int gl = threadIdx.x % LPA;
+  const int grp = threadIdx.x / LPA;
+  constexpr int NG = NT / LPA;
+  unsigned long long best = 0ull;
+  for (int j = tile.j0 + grp; j < tile.j1; j += NG) {
+    const TA* col = A + (long long)j * lda;
+    float acc = 0.f, nrm = 0.f;
+#pragma unroll 8
+    for (int c = gl; c < nvec; c += LPA) {
+      float v[VW];
+      Vec<TA>::load(col + (long long)c * VW, v);
+      if (c == nvec - 1) {
+#pragma unroll
+        for (int e = 0; e < VW; ++e) v[e] = (e < tail) ? v[e] : 0.f;
+      }
+      const float* vv = vsh + c * VW;
+#pragma unroll
+      for (int e = 0; e < VW; ++e) {
+        acc = fmaf(v[e], vv[e], acc);
+        if (MODE == 0) nrm = fmaf(v[e], v[e], nrm);
+      }
+    }
+    acc = group_sum<LPA>(acc);
+    if (MODE == 0) {
+      // the first pass also records ||a_j||^2, the Gram diagonal
+      nrm = group_sum<LPA>(nrm);
+      if (gl == 0) {
+        I.c0[j] = acc;
+        I.dg[j] = nrm;
+      }
+      const unsigned long long key = pack_key(acc, j);
+      best = key > best ? key : best;
+    } else {
+      if (gl == 0) I.H[j + (long long)t * I.ldh] = acc;
+    }
+  }
+  if (MODE == 0) {
+    best = wave_max_u64(best);
+    if ((threadIdx.x & 63) == 0) wbest[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long b = wbest[0];
+      for (int w = 1; w < NT / 64; ++w) b = wbest[w] > b ? wbest[w] : b;
+      if (b) atomicMax(I.key, b);
+    }
+  }
+}
+
+template <typename TA, int LPA>
+__global__ __launch_bounds__(kPassThreads) void ypass_kernel(const Inst* __restrict__ insts,
+                                                             const ScanTile* __restrict__ tiles) {
+  extern __shared__ float dsh[];
+  __shared__ unsigned long long wbest[kPassThreads / 64];
+  const ScanTile tile = tiles[blockIdx.x];
+  pass_tile_body<TA, LPA, 0>(insts[tile.inst], tile, 0, dsh, wbest);
+}
+
+enum CoefKind : int { COEF_ADAM_REG = 0, COEF_ADAM_GLOBAL = 1, COEF_OMP = 2 };
+
+// Blocks [0, nact): coefficient update of iteration t for the class's active
+// instances (insts_c = class base).  Blocks [nact, ...): h_t pass tiles.
+template <typename TA, int LPA, int COEF>
+__global__ __launch_bounds__(kPassThreads) void coef_pass_kernel(
+    const Inst* __restrict__ insts_c, int nact, const Inst* __restrict__ insts,
+    const ScanTile* __restrict__ tiles, int t, int T, float beta1, float beta2, float lr_rel,
+    float eps_rel) {
+  extern __shared__ float dsh[];
+  __shared__ float4 part[2][16][64];
+  __shared__ float red[kPassThreads / 64], red2[kPassThreads / 64];
+  __shared__ unsigned long long wbest[kPassThreads / 64];
+  if ((int)blockIdx.x < nact) {
+    const Inst& I = insts_c[blockIdx.x];
+    if (I.st->done) return;
+    // selection record and the new Gram column, gathered from H:
+    //   G[l, t] = a_{S_l}^T a_j = H[j, l] (l < t),  G[t, t] = ||a_j||^2,
+    //   b_t = a_j^T y = c0[j]
+    const unsigned long long key = I.key[t & 1];
+    const int j = key_index(key);
+    if (key == 0ull || j < 0 || j >= I.n) {
+      if (threadIdx.x == 0) {
+        I.st->done = 1;
+        atomicOr(I.status, ST_WATCHDOG);
+      }
+      return;
+    }
+    for (int l = threadIdx.x; l < t; l += kPassThreads) {
+      const float g = I.H[j + (long long)l * I.ldh];
+      I.G[l + (long long)t * I.ldg] = g;
+      I.G[t + (long long)l * I.ldg] = g;
+    }
+    if (threadIdx.x == 0) {
+      I.G[t + (long long)t * I.ldg] = I.dg[j];
+      I.b[t] = I.c0[j];
+      I.support[t] = j;
+      I.bitmap[j >> 5] |= (1u << (j & 31));
+      *I.nsel = t + 1;
+      const float cj = key_value(key);
+      if (!(cj <= 3.402823466e38f)) atomicOr(I.status, ST_NAN);
+      if (t == 0) {
+        I.st->sigma = cj;
+        I.st->lr = lr_rel * cj;
+        I.st->eps = eps_rel * cj;
+      }
+      I.key[(t + 1) & 1] = 0ull;   // slot of the next scan
+    }
+    __syncthreads();
+    if (COEF == COEF_ADAM_REG)
+      adam_reg_body(I, t, T, beta1, beta2, part, kPassThreads / 64, false);
+    else if (COEF == COEF_ADAM_GLOBAL)
+      adam_global_body<kPassThreads>(I, t, T, beta1, beta2, dsh, false);
+    else
+      omp_ginv_body(I, t, dsh, red, red2, false);
+    return;
+  }
+  const ScanTile tile = tiles[blockIdx.x - nact];
+  pass_tile_body<TA, LPA, 1>(insts[tile.inst], tile, t, dsh, wbest);
+}
+
+// c_j = c0_j - sum_{l<t} H[j, l] s_l for a 64-atom tile.  Lane (q, u) of
+// wave w covers atoms 4q..4q+3 (float4 loads) and the columns l = L, L+64, ...
+// with slice L = 4w + u; slices are added with shuffles inside a wave, then
+// across the 16 waves in LDS, in a fixed order.  Then |c| with the exclusion
+// of selected atoms and the argmax key (slot t & 1) by atomicMax.
+constexpr int kCscanThreads = 1024;
+constexpr int kCscanAtoms = 64;
+
+__global__ __launch_bounds__(kCscanThreads) void cscan_kernel(const Inst* __restrict__ insts,
+                                                              const ScanTile* __restrict__ tiles,
+                                                              int t) {
+  __shared__ float4 part[16][16];
+  const ScanTile tile = tiles[blockIdx.x];
+  const Inst& I = insts[tile.inst];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int q = lane & 15;
+  const int L = 4 * w + (lane >> 4);
+  const int j = tile.j0 + 4 * q;          // tiles start at multiples of 64
+  // loads that do not depend on the sum are issued first (c0 is padded to a
+  // multiple of 256 entries, so the float4 read stays inside the buffer)
+  const int done = I.st->done;
+  float4 c0v = make_float4(0.f, 0.f, 0.f, 0.f);
+  unsigned bits = 0u;
+  if (w == 0 && lane < 16 && j < tile.j1) {
+    c0v = *reinterpret_cast<const float4*>(I.c0 + j);
+    bits = I.bitmap[j >> 5];
+  }
+  const float* ssh = I.s;                  // t coefficients, read through L2
+  float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
+  if (!done && j < tile.j1) {
+    const float* Hj = I.H + j;
+    const long long ldh = I.ldh;
+    int l = L;
+    for (; l + 64 < t; l += 128) {
+      const float4 h0 = *reinterpret_cast<const float4*>(Hj + (long long)l * ldh);
+      const float4 h1 = *reinterpret_cast<const float4*>(Hj + (long long)(l + 64) * ldh);
+      const float s0 = ssh[l], s1 = ssh[l + 64];
+      a0.x = fmaf(h0.x, s0, a0.x); a0.y = fmaf(h0.y, s0, a0.y);
+      a0.z = fmaf(h0.z, s0, a0.z); a0.w = fmaf(h0.w, s0, a0.w);
+      a1.x = fmaf(h1.x, s1, a1.x); a1.y = fmaf(h1.y, s1, a1.y);
+      a1.z = fmaf(h1.z, s1, a1.z); a1.w = fmaf(h1.w, s1, a1.w);
+    }
+    if (l < t) {
+      const float4 h0 = *reinterpret_cast<const float4*>(Hj + (long long)l * ldh);
+      const float s0 = ssh[l];
+      a0.x = fmaf(h0.x, s0, a0.x); a0.y = fmaf(h0.y, s0, a0.y);
+      a0.z = fmaf(h0.z, s0, a0.z); a0.w = fmaf(h0.w, s0, a0.w);
+    }
+  }
+  float4 v = make_float4(a0.x + a1.x, a0.y + a1.y, a0.z + a1.z, a0.w + a1.w);
+  // the four slices of a wave (lanes q, q+16, q+32, q+48)
+#pragma unroll
+  for (int o = 16; o < 64; o <<= 1) {
+    v.x += __shfl_xor(v.x, o, 64);
+    v.y += __shfl_xor(v.y, o, 64);
+    v.z += __shfl_xor(v.z, o, 64);
+    v.w += __shfl_xor(v.w, o, 64);
+  }
+  if (lane < 16) part[w][lane] = v;
+  __syncthreads();
+  if (w == 0 && !done) {
+    unsigned long long key = 0ull;
+    if (lane < 16) {
+      float4 sum = part[0][lane];
+#pragma unroll
+      for (int ww = 1; ww < 16; ++ww) {
+        const float4 u = part[ww][lane];
+        sum.x += u.x; sum.y += u.y; sum.z += u.z; sum.w += u.w;
+      }
+      const float hs[4] = {sum.x, sum.y, sum.z, sum.w};
+      const float cs[4] = {c0v.x, c0v.y, c0v.z, c0v.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int je = j + e;
+        if (je < tile.j1) {
+          const float c = cs[e] - hs[e];
+          const unsigned sel = (bits >> (je & 31)) & 1u;   // 4 atoms share a word
+          const unsigned long long k2 = sel ? 0ull : pack_key(c, je);
+          key = k2 > key ? k2 : key;
+        }
+      }
+    }
+    key = wave_max_u64(key);
+    if (lane == 0 && key) atomicMax(&I.key[t & 1], key);
+  }
+}
+
 // ============================================================ launchers
 template <typename TA>
 static hipError_t scan_dispatch(int lpa, const Inst* d, const ScanTile* tiles, int ntiles,
@@ -1235,6 +1499,101 @@ hipError_t set_max_lds(size_t bytes) {
       (const void*)cg_dots_kernel<8, 1>, (const void*)cg_dots_kernel<16, 1>,
       (const void*)cg_dots_kernel<32, 1>, (const void*)cg_dots_kernel<64, 1>,
       (const void*)qr_refine_kernel};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename TA>
+static hipError_t ypass_dispatch(int lpa, const Inst* d, const ScanTile* tiles, int ntiles,
+                                 size_t lds, hipStream_t s) {
+  const dim3 g(ntiles), b(kPassThreads);
+  switch (lpa) {
+    case 4: hipLaunchKernelGGL((ypass_kernel<TA, 4>), g, b, lds, s, d, tiles); break;
+    case 8: hipLaunchKernelGGL((ypass_kernel<TA, 8>), g, b, lds, s, d, tiles); break;
+    case 16: hipLaunchKernelGGL((ypass_kernel<TA, 16>), g, b, lds, s, d, tiles); break;
+    case 32: hipLaunchKernelGGL((ypass_kernel<TA, 32>), g, b, lds, s, d, tiles); break;
+    default: hipLaunchKernelGGL((ypass_kernel<TA, 64>), g, b, lds, s, d, tiles); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ypass(int bf16, int lpa, const Inst* d, const ScanTile* tiles, int ntiles,
+                        size_t lds, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  return bf16 ? ypass_dispatch<uint16_t>(lpa, d, tiles, ntiles, lds, s)
+              : ypass_dispatch<float>(lpa, d, tiles, ntiles, lds, s);
+}
+
+template <typename TA, int LPA>
+static hipError_t coef_pass_lpa(int coef, const Inst* dc, int nact, const Inst* d,
+                                const ScanTile* tiles, int ntiles, int t, int T, float b1,
+                                float b2, float lr_rel, float eps_rel, size_t lds,
+                                hipStream_t s) {
+  const dim3 g(nact + ntiles), b(kPassThreads);
+  switch (coef) {
+    case COEF_ADAM_REG:
+      hipLaunchKernelGGL((coef_pass_kernel<TA, LPA, COEF_ADAM_REG>), g, b, lds, s, dc, nact, d,
+                         tiles, t, T, b1, b2, lr_rel, eps_rel);
+      break;
+    case COEF_ADAM_GLOBAL:
+      hipLaunchKernelGGL((coef_pass_kernel<TA, LPA, COEF_ADAM_GLOBAL>), g, b, lds, s, dc, nact, d,
+                         tiles, t, T, b1, b2, lr_rel, eps_rel);
+      break;
+    default:
+      hipLaunchKernelGGL((coef_pass_kernel<TA, LPA, COEF_OMP>), g, b, lds, s, dc, nact, d, tiles,
+                         t, T, b1, b2, lr_rel, eps_rel);
+      break;
+  }
+  return hipGetLastError();
+}
+
+template <typename TA>
+static hipError_t coef_pass_dispatch(int lpa, int coef, const Inst* dc, int nact, const Inst* d,
+                                     const ScanTile* tiles, int ntiles, int t, int T, float b1,
+                                     float b2, float lr, float ep, size_t lds, hipStream_t s) {
+  switch (lpa) {
+    case 4: return coef_pass_lpa<TA, 4>(coef, dc, nact, d, tiles, ntiles, t, T, b1, b2, lr, ep, lds, s);
+    case 8: return coef_pass_lpa<TA, 8>(coef, dc, nact, d, tiles, ntiles, t, T, b1, b2, lr, ep, lds, s);
+    case 16: return coef_pass_lpa<TA, 16>(coef, dc, nact, d, tiles, ntiles, t, T, b1, b2, lr, ep, lds, s);
+    case 32: return coef_pass_lpa<TA, 32>(coef, dc, nact, d, tiles, ntiles, t, T, b1, b2, lr, ep, lds, s);
+    default: return coef_pass_lpa<TA, 64>(coef, dc, nact, d, tiles, ntiles, t, T, b1, b2, lr, ep, lds, s);
+  }
+}
+
+hipError_t launch_coef_pass(int bf16, int lpa, int omp, const Inst* dc, int nact, const Inst* d,
+                            const ScanTile* tiles, int ntiles, int t, int T, float beta1,
+                            float beta2, float lr_rel, float eps_rel, size_t lds, hipStream_t s) {
+  if (nact + ntiles <= 0) return hipSuccess;
+  const int coef = omp ? COEF_OMP : (t + 1 <= kRegRows ? COEF_ADAM_REG : COEF_ADAM_GLOBAL);
+  return bf16 ? coef_pass_dispatch<uint16_t>(lpa, coef, dc, nact, d, tiles, ntiles, t, T, beta1,
+                                             beta2, lr_rel, eps_rel, lds, s)
+              : coef_pass_dispatch<float>(lpa, coef, dc, nact, d, tiles, ntiles, t, T, beta1,
+                                          beta2, lr_rel, eps_rel, lds, s);
+}
+
+hipError_t launch_cscan(const Inst* d, const ScanTile* tiles, int ntiles, int t, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(cscan_kernel, dim3(ntiles), dim3(kCscanThreads), 0, s, d, tiles, t);
+  return hipGetLastError();
+}
+
+hipError_t set_max_lds_pass(size_t bytes) {
+  const void* fns[] = {
+      (const void*)ypass_kernel<float, 4>, (const void*)ypass_kernel<float, 8>,
+      (const void*)ypass_kernel<float, 16>, (const void*)ypass_kernel<float, 32>,
+      (const void*)ypass_kernel<float, 64>, (const void*)ypass_kernel<uint16_t, 4>,
+      (const void*)ypass_kernel<uint16_t, 8>, (const void*)ypass_kernel<uint16_t, 16>,
+      (const void*)ypass_kernel<uint16_t, 32>, (const void*)ypass_kernel<uint16_t, 64>,
+#define CP(TA, L) (const void*)coef_pass_kernel<TA, L, COEF_ADAM_REG>, \
+                  (const void*)coef_pass_kernel<TA, L, COEF_ADAM_GLOBAL>, \
+                  (const void*)coef_pass_kernel<TA, L, COEF_OMP>
+      CP(float, 4), CP(float, 8), CP(float, 16), CP(float, 32), CP(float, 64),
+      CP(uint16_t, 4), CP(uint16_t, 8), CP(uint16_t, 16), CP(uint16_t, 32), CP(uint16_t, 64)
+#undef CP
+  };
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;

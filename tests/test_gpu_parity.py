@@ -21,9 +21,15 @@ from tests.gpu_helpers import (PARAMS, FP32_DELTA, FP32_U, BF16_DELTA, BF16_U, d
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def solvers():
-    s = {"clomp": C.Solver(0, method="clomp"), "omp": C.Solver(0, method="omp")}
+FLOWS = {"resid": C.FLAG_RESIDUAL_FLOW, "corr": C.FLAG_CORR_FLOW}
+
+
+@pytest.fixture(scope="module", params=sorted(FLOWS))
+def solvers(request):
+    """CLOMP and OMP handles, under each of the two schedules."""
+    fl = FLOWS[request.param]
+    s = {"clomp": C.Solver(0, method="clomp", flags=fl),
+         "omp": C.Solver(0, method="omp", flags=fl)}
     yield s
     for v in s.values():
         v.close()
