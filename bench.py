@@ -1,17 +1,24 @@
 """Benchmark: CLOMP signals/s on one MI355X next to plain GPU OMP on the same
-instance, with the scan kernel's roofline and the FP64 CPU oracle timed on the
-host.
+instances, with the roofline of the dominant kernel and the FP64 CPU oracle
+timed on the host.
 
-Workload (default): one large 1-D signal, n=16384 atoms, m=4096 measurements
-(sampling rate 0.25), k=256, A iid N(0, 1/m) stored float32, non-zeros
-+-(1+|N(0,1)|), y = A s + N(0, 1e-4); batch of one, so every greedy iteration
-streams the whole 268 MB dictionary through the scan (HBM-bound GEMV).
+Default workload (the headline): one large 1-D signal, n=16384 atoms, m=4096
+measurements (sampling rate 0.25), k=256, A iid N(0, 1/m) stored float32,
+non-zeros +-(1+|N(0,1)|), y = A s + N(0, 1e-4); batch of one, so every greedy
+iteration streams the whole 268 MB dictionary (HBM-bound).
 
-A step is one full solve (k greedy iterations, refinement, FP64 residual norm)
-through the C ABI, inputs already resident in HBM.  W untimed warm-up steps,
-then K timed steps between device synchronisations.  Prints one JSON line.
+Other workloads (--workload): small1d (1000 signals n=256 m=64 k=8), image
+(256 columns sharing A, sampling rate 0.1/0.3/0.5), uneven (4096 signals of
+uneven size, BF16 bulk + FP32 master), flat (n=65536, m=19661, k=2048, BF16
+CLOMP vs FP32 OMP).
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+A step is one full solve of the workload's batch (k greedy iterations,
+refinement, FP64 residual norm) through the C ABI, inputs resident in HBM.
+W untimed warm-up steps, then K timed steps between device synchronisations.
+Prints one JSON line.
+
+    python bench.py [--workload large1d] [--steps K] [--warmup W] [--gpus 1]
+                    [--no-cpu-baseline] [--no-graph]
 """
 
 import argparse
@@ -34,10 +41,95 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="large1d",
+                    choices=["large1d", "small1d", "image", "uneven", "flat"])
+    ap.add_argument("--sr", type=float, default=0.3, help="image workload sampling rate")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--flow", default="auto", choices=["auto", "resid", "corr"],
+                    help="schedule: library default, residual, or correlation update")
     ap.add_argument("--profile-steps", type=int, default=2)
     return ap.parse_args()
+
+
+def f32(v):
+    return float(np.float32(v))
+
+
+def log(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------------ workloads
+def build_workload(args, torch, W):
+    """Returns dict(name, desc, cfg, clomp_items, omp_items, dtype, host)."""
+    dev = torch.device("cuda", 0)
+    if args.workload == "large1d":
+        sig = W.single_large(0)
+        it = dict(At=torch.from_numpy(sig.At).to(dev), m=sig.m,
+                  y=torch.from_numpy(sig.y).to(dev), k=sig.k)
+        return dict(name="large1d",
+                    desc="large 1-D signal: n=16384, m=4096, k=256, A iid N(0,1/m) float32, "
+                         "noise N(0,1e-4), batch 1",
+                    cfg=dict(n=sig.n, m=sig.m, k=sig.k, batch=1),
+                    clomp_items=[it], omp_items=[it], dtype="f32", host=[sig])
+    if args.workload == "small1d":
+        sigs = [W.single_small(i) for i in range(1000)]
+        items = [dict(At=torch.from_numpy(s.At).to(dev), m=s.m, y=torch.from_numpy(s.y).to(dev),
+                      k=s.k) for s in sigs]
+        return dict(name="small1d",
+                    desc="1000 single 1-D signals n=256, m=64, k=8, A iid N(0,1/m), noiseless, "
+                         "one batch",
+                    cfg=dict(n=256, m=64, k=8, batch=1000), clomp_items=items, omp_items=items,
+                    dtype="f32", host=sigs)
+    if args.workload == "image":
+        b = W.image_batch(args.sr)
+        At = torch.from_numpy(b.At).to(dev)
+        Y = torch.from_numpy(b.Y).to(dev)
+        items = [dict(At=At, m=b.m, y=Y[c], k=b.k) for c in range(Y.shape[0])]
+        return dict(name=f"image_sr{args.sr}",
+                    desc=f"256 columns of a synthetic 256x256 image sharing one Gaussian A, "
+                         f"sampling rate {args.sr} (m={b.m}), power-law k=32, float32",
+                    cfg=dict(n=b.n, m=b.m, k=b.k, batch=256, shared_A=True),
+                    clomp_items=items, omp_items=items, dtype="f32", host=b)
+    if args.workload == "uneven":
+        log("drawing the uneven batch on the device (4096 signals, ~89 GB)")
+        specs, items, supps, coefs = W.uneven_batch_device(4096, dev)
+        tot = sum(sp.n * sp.m for sp in specs)
+        return dict(name="uneven",
+                    desc="4096 signals, n log-uniform [512,8192], m/n U[0.1,0.5], k U[n/64,n/16], "
+                         "A iid N(0,1/m): BF16 bulk + FP32 master",
+                    cfg=dict(batch=4096, sum_mn=tot), clomp_items=items, omp_items=items,
+                    dtype="bf16", host=(specs, supps, coefs))
+    if args.workload == "flat":
+        log("drawing the flattened-image matrix on the device (5.2 GB FP32 + 2.6 GB BF16)")
+        Am, Ab, y, supp, s = W.flat_image_device(dev)
+        c_it = dict(At=Ab, m=W.FLAT_M, y=y, k=W.FLAT_K, At_master=Am)
+        o_it = dict(At=Am, m=W.FLAT_M, y=y, k=W.FLAT_K)
+        return dict(name="flat",
+                    desc="flattened 256x256 image as one signal: n=65536, m=19661, k=2048 "
+                         "power-law; BF16 CLOMP (FP32 refinement) vs FP32 OMP",
+                    cfg=dict(n=W.FLAT_N, m=W.FLAT_M, k=W.FLAT_K, batch=1),
+                    clomp_items=[c_it], omp_items=[o_it], dtype="bf16", host=(supp, s))
+    raise SystemExit(f"unknown workload {args.workload}")
+
+
+def roofline(p):
+    """Dominant launch of a profile (most total device time) and its achieved
+    algorithmic bandwidth."""
+    if p["launches"]["pass"] > 0 and p["ms"]["pass"] >= p["ms"]["scan"]:
+        name = "coef_pass_kernel (Adam/OMP block + pass h = A^T a_j over A)"
+        nl, ms, byt = p["launches"]["pass"], p["ms"]["pass"], p["pass_bytes"]
+    else:
+        name = ("cscan/ypass kernels (c = c0 - H s, argmax)" if p["launches"]["pass"] > 0
+                else "scan_reg_kernel (c = A^T r, |c|, argmax)")
+        nl, ms, byt = max(1, p["launches"]["scan"]), p["ms"]["scan"], p["scan_bytes"]
+    k_ms = ms / nl
+    bpl = byt / nl
+    ach = bpl / (k_ms * 1e-3) / 1e9
+    return {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": None, "avg_launch_us": 1e3 * k_ms,
+            "bytes_per_launch": bpl, "launches": nl}
 
 
 def main():
@@ -51,105 +143,54 @@ def main():
     from paper_2501_11592_amd import clomp as C
     from paper_2501_11592_amd import workloads as W
 
-    print("bench: generating the large 1-D workload (n=16384 m=4096 k=256)", file=sys.stderr,
-          flush=True)
-    sig = W.single_large(0)
-    dev = torch.device("cuda", 0)
-    At = torch.from_numpy(sig.At).to(dev)
-    y = torch.from_numpy(sig.y).to(dev)
-    stream = torch.cuda.Stream(dev)
-    flags = 0 if args.no_graph else C.FLAG_GRAPH
+    log(f"workload {args.workload}")
+    wl = build_workload(args, torch, W)
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream(torch.device("cuda", 0))
+    flow_flag = {"auto": 0, "resid": C.FLAG_RESIDUAL_FLOW, "corr": C.FLAG_CORR_FLOW}[args.flow]
+    flags = (0 if args.no_graph else C.FLAG_GRAPH) | flow_flag
     solvers = {m: C.Solver(0, method=m, flags=flags) for m in ("clomp", "omp")}
-
-    def step(method):
-        return solvers[method].solve(At, sig.m, y, sig.k, stream=stream)
+    items = {"clomp": wl["clomp_items"], "omp": wl["omp_items"]}
+    count = len(items["clomp"])
 
     timings, outs = {}, {}
     for method in ("clomp", "omp"):
-        print(f"bench: {method} warmup {args.warmup}", file=sys.stderr, flush=True)
+        log(f"{method} warmup {args.warmup}")
         for _ in range(args.warmup):
-            step(method)
+            solvers[method].solve_batch(items[method], stream=stream)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            out = step(method)
+            out = solvers[method].solve_batch(items[method], stream=stream)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         timings[method] = dt / args.steps
         outs[method] = out
-        print(f"bench: {method} {1e3 * dt / args.steps:.3f} ms/solve", file=sys.stderr, flush=True)
+        log(f"{method} {1e3 * dt / args.steps:.3f} ms/step")
 
     # live per-phase timing with HIP events on the launch stream (no graph)
     prof = {}
     for method in ("clomp", "omp"):
-        ps = C.Solver(0, method=method, flags=C.FLAG_PROFILE)
-        ps.solve(At, sig.m, y, sig.k, stream=stream)
+        ps = C.Solver(0, method=method, flags=C.FLAG_PROFILE | flow_flag)
+        ps.solve_batch(items[method], stream=stream)
         torch.cuda.synchronize()
         ps.profile_reset()
         for _ in range(args.profile_steps):
-            ps.solve(At, sig.m, y, sig.k, stream=stream)
+            ps.solve_batch(items[method], stream=stream)
         torch.cuda.synchronize()
         prof[method] = ps.profile_read()
         ps.close()
 
-    # accuracy against the FP64 oracle
-    golden = os.path.join(ROOT, "tests", "golden", "large1d_oracle.json")
-    gold = json.load(open(golden)) if os.path.exists(golden) else None
-    acc = {}
-    cpu = None
-    if not args.no_cpu_baseline:
-        from oracle import clomp_fp64, ClompParams
-        from threadpoolctl import threadpool_info
-        f32 = lambda v: float(np.float32(v))
-        params = ClompParams(inner_steps=32, lr_rel=f32(0.05), beta1=f32(0.9),
-                             beta2=f32(0.999), eps_rel=f32(1e-8))
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-        print("bench: timing the FP64 oracle (one full CLOMP solve of this signal)",
-              file=sys.stderr, flush=True)
-        t0 = time.perf_counter()
-        ref = clomp_fp64(sig.A, sig.y, sig.k, params)
-        cdt = time.perf_counter() - t0
-        cpu = {"value": 1.0 / cdt, "unit": "signals/s", "cores": int(threads), "kind": "oracle",
-               "sample": "one full solve of the benchmark signal (n=16384, m=4096, k=256) by "
-                         "the FP64 CLOMP oracle (NumPy/SciPy BLAS)",
-               "seconds": cdt, "host_cpus": os.cpu_count()}
-        ref_sets = {"clomp": (ref.support, ref.x)}
-    else:
-        ref_sets = {}
-    if gold is not None:
-        for method in ("clomp", "omp"):
-            x = np.zeros(sig.n)
-            x[gold[method]["support"]] = gold[method]["x_support"]
-            ref_sets.setdefault(method, (gold[method]["support"], x))
-    for method, (supp, xr) in ref_sets.items():
-        o = outs[method]
-        xs = o["x"].cpu().numpy().astype(np.float64)
-        sg = o["support"][: int(o["n_selected"])].cpu().tolist()
-        acc[method] = {"rel_err": float(np.linalg.norm(xs - xr) / np.linalg.norm(xr)),
-                       "support_identical": sg == list(supp),
-                       "support_set_equal": sorted(sg) == sorted(supp),
-                       "truth_rel_err": float(np.linalg.norm(xs - sig.s) / np.linalg.norm(sig.s))}
+    acc, cpu = {}, None
+    if wl["name"] == "large1d":
+        acc, cpu = accuracy_large1d(args, wl, outs)
+    elif wl["name"] == "small1d" and not args.no_cpu_baseline:
+        acc, cpu = accuracy_batch_sample(wl, outs, n_sample=200)
 
-    p = prof["clomp"]
-    if p["launches"]["pass"] > 0:
-        # correlation-update schedule: the dominant launch streams A while its
-        # first block runs the Adam steps
-        kname = "coef_pass_kernel (Adam block + pass h = A^T a_j)"
-        nl = p["launches"]["pass"]
-        k_ms = p["ms"]["pass"] / nl
-        bytes_per_launch = p["pass_bytes"] / nl
-    else:
-        kname = "scan_reg_kernel (c = A^T r, |c|, argmax)"
-        nl = max(1, p["launches"]["scan"])
-        k_ms = p["ms"]["scan"] / nl
-        bytes_per_launch = p["scan_bytes"] / nl
-    scan_ms = k_ms
-    achieved = bytes_per_launch / (k_ms * 1e-3) / 1e9
-    value = 1.0 / timings["clomp"]
-    ok = all(a["rel_err"] <= 1e-3 for a in acc.values()) if acc else None
+    st = {m: outs[m].status.cpu().numpy() for m in outs}
     line = {
         "metric": METRIC,
-        "value": value,
+        "value": count / timings["clomp"],
         "unit": "signals/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -158,28 +199,96 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": wl["dtype"],
         "data": "synthetic",
-        "config": {"workload": "large 1-D signal: n=16384, m=4096, k=256, A iid N(0,1/m) "
-                               "float32, noise N(0,1e-4), batch 1",
-                   "n": sig.n, "m": sig.m, "k": sig.k, "batch": 1, "method": "clomp",
-                   "inner_steps": 32, "graph": not args.no_graph},
-        "omp": {"value": 1.0 / timings["omp"], "unit": "signals/s",
-                "ms_per_step": 1e3 * timings["omp"]},
+        "config": dict(workload=wl["desc"], method="clomp", inner_steps=32,
+                       graph=not args.no_graph, flow=args.flow, **wl["cfg"]),
+        "omp": {"value": count / timings["omp"], "unit": "signals/s",
+                "ms_per_step": 1e3 * timings["omp"],
+                "dtype": "f32" if wl["name"] == "flat" else wl["dtype"]},
         "clomp_vs_omp": timings["omp"] / timings["clomp"],
         "accuracy": acc,
-        "accuracy_gate_1e-3": ok,
-        "phase_ms_per_solve": {m: {k: v / args.profile_steps for k, v in prof[m]["ms"].items()}
-                               for m in prof},
-        "roofline": {"kernel": kname,
-                     "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "avg_launch_us": 1e3 * scan_ms, "bytes_per_launch": bytes_per_launch},
+        "accuracy_gate_1e-3": (all(a["rel_err"] <= 1e-3 for a in acc.values()) if acc else None),
+        "status_flags_nonzero": {m: int((st[m] != 0).sum()) for m in st},
+        "phase_ms_per_step": {m: {k: v / args.profile_steps for k, v in prof[m]["ms"].items()}
+                              for m in prof},
+        "roofline": roofline(prof["clomp"]),
+        "roofline_omp": roofline(prof["omp"]),
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
     for s in solvers.values():
         s.close()
+
+
+def _threads():
+    from threadpoolctl import threadpool_info
+    return int(max([p.get("num_threads", 1) for p in threadpool_info()] or [1]))
+
+
+def accuracy_large1d(args, wl, outs):
+    """rel.err against the FP64 oracle; the oracle solve is also the CPU
+    baseline (one full solve of the benchmark signal, about 15 s)."""
+    from oracle import clomp_fp64, ClompParams
+    sig = wl["host"][0]
+    golden = os.path.join(ROOT, "tests", "golden", "large1d_oracle.json")
+    gold = json.load(open(golden)) if os.path.exists(golden) else None
+    refs, cpu = {}, None
+    if not args.no_cpu_baseline:
+        params = ClompParams(inner_steps=32, lr_rel=f32(0.05), beta1=f32(0.9),
+                             beta2=f32(0.999), eps_rel=f32(1e-8))
+        log("timing the FP64 oracle (one full CLOMP solve of this signal)")
+        t0 = time.perf_counter()
+        ref = clomp_fp64(sig.A, sig.y, sig.k, params)
+        cdt = time.perf_counter() - t0
+        cpu = {"value": 1.0 / cdt, "unit": "signals/s", "cores": _threads(), "kind": "oracle",
+               "sample": "one full solve of the benchmark signal (n=16384, m=4096, k=256) by the "
+                         "FP64 CLOMP oracle (NumPy/SciPy BLAS)",
+               "seconds": cdt, "host_cpus": os.cpu_count()}
+        refs["clomp"] = (ref.support, ref.x)
+    if gold is not None:
+        for method in ("clomp", "omp"):
+            x = np.zeros(sig.n)
+            x[gold[method]["support"]] = gold[method]["x_support"]
+            refs.setdefault(method, (gold[method]["support"], x))
+    acc = {}
+    for method, (supp, xr) in refs.items():
+        o = outs[method]
+        xs = o.x[0].cpu().numpy().astype(np.float64)
+        sg = o.support[0][: int(o.n_selected[0])].cpu().tolist()
+        acc[method] = {"rel_err": float(np.linalg.norm(xs - xr) / np.linalg.norm(xr)),
+                       "support_identical": sg == list(supp),
+                       "support_set_equal": sorted(sg) == sorted(supp),
+                       "truth_rel_err": float(np.linalg.norm(xs - sig.s) / np.linalg.norm(sig.s))}
+    return acc, cpu
+
+
+def accuracy_batch_sample(wl, outs, n_sample):
+    """rel.err of a sample of a host-generated batch against the oracle, and
+    the oracle's rate on that sample as the CPU baseline."""
+    from oracle import clomp_fp64, omp_fp64, ClompParams
+    params = ClompParams(inner_steps=32, lr_rel=f32(0.05), beta1=f32(0.9), beta2=f32(0.999),
+                         eps_rel=f32(1e-8))
+    sigs = wl["host"][:n_sample]
+    errs = {"clomp": [], "omp": []}
+    same = {"clomp": 0, "omp": 0}
+    t0 = time.perf_counter()
+    refs = [clomp_fp64(s.A, s.y, s.k, params) for s in sigs]
+    cdt = time.perf_counter() - t0
+    orefs = [omp_fp64(s.A, s.y, s.k) for s in sigs]
+    for method, rr in (("clomp", refs), ("omp", orefs)):
+        o = outs[method]
+        for i, r in enumerate(rr):
+            xs = o.x[i].cpu().numpy().astype(np.float64)
+            errs[method].append(np.linalg.norm(xs - r.x) / np.linalg.norm(r.x))
+            same[method] += o.support[i][: int(o.n_selected[i])].cpu().tolist() == r.support
+    acc = {m: {"rel_err": float(np.max(errs[m])), "rel_err_median": float(np.median(errs[m])),
+               "support_identical_fraction": same[m] / len(sigs), "sample": len(sigs)}
+           for m in errs}
+    cpu = {"value": len(sigs) / cdt, "unit": "signals/s", "cores": _threads(), "kind": "oracle",
+           "sample": f"{len(sigs)} of the 1000 signals, FP64 CLOMP oracle", "seconds": cdt,
+           "host_cpus": os.cpu_count()}
+    return acc, cpu
 
 
 if __name__ == "__main__":

@@ -1480,6 +1480,20 @@ hipError_t launch_finalize(const Inst* d, int count, int check_cg, hipStream_t s
   return hipGetLastError();
 }
 
+// Allow each kernel `bytes` of LDS in total: its dynamic ceiling is `bytes`
+// minus the kernel's own static LDS.
+static hipError_t raise_dynamic_lds(const void* const* fns, size_t nf, size_t bytes) {
+  for (size_t i = 0; i < nf; ++i) {
+    hipFuncAttributes at;
+    hipError_t e = hipFuncGetAttributes(&at, fns[i]);
+    if (e != hipSuccess) return e;
+    const size_t dyn = bytes > at.sharedSizeBytes ? bytes - at.sharedSizeBytes : 0;
+    e = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t set_max_lds(size_t bytes) {
   // Raise the dynamic-LDS ceiling of the kernels that stage vectors.
   const void* fns[] = {
@@ -1499,11 +1513,7 @@ hipError_t set_max_lds(size_t bytes) {
       (const void*)cg_dots_kernel<8, 1>, (const void*)cg_dots_kernel<16, 1>,
       (const void*)cg_dots_kernel<32, 1>, (const void*)cg_dots_kernel<64, 1>,
       (const void*)qr_refine_kernel};
-  for (const void* f : fns) {
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  return raise_dynamic_lds(fns, sizeof(fns) / sizeof(fns[0]), bytes);
 }
 
 template <typename TA>
@@ -1594,11 +1604,7 @@ hipError_t set_max_lds_pass(size_t bytes) {
       CP(uint16_t, 4), CP(uint16_t, 8), CP(uint16_t, 16), CP(uint16_t, 32), CP(uint16_t, 64)
 #undef CP
   };
-  for (const void* f : fns) {
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  return raise_dynamic_lds(fns, sizeof(fns) / sizeof(fns[0]), bytes);
 }
 
 }  // namespace clomp

@@ -217,3 +217,57 @@ def device_gaussian_atoms(n, m, lda, seed, device, chunk_atoms=4096):
                           dtype=torch.float32)
         At[j0:j1, :m] = blk * scale
     return At
+
+
+# ------------------------------------------------------------ device batches
+def uneven_batch_device(count=4096, device="cuda"):
+    """The uneven batch drawn on the device: per instance an FP32 master
+    (lda rounded to 32) and its bfloat16 copy (lda rounded to 64), packed in two
+    flat buffers; y = A s computed from the master in float64 on the device.
+    Returns (specs, items, supports, coefficient dicts)."""
+    import torch
+    specs = uneven_specs(count)
+    lda32 = [pad_lda(sp.m, 4) for sp in specs]
+    lda16 = [pad_lda(sp.m, 2) for sp in specs]
+    tot32 = sum(sp.n * l for sp, l in zip(specs, lda32))
+    tot16 = sum(sp.n * l for sp, l in zip(specs, lda16))
+    buf32 = torch.empty(tot32, dtype=torch.float32, device=device)
+    buf16 = torch.empty(tot16, dtype=torch.bfloat16, device=device)
+    items, supports, coefs = [], [], []
+    o32 = o16 = 0
+    for i, sp in enumerate(specs):
+        n, m, k = sp.n, sp.m, sp.k
+        Am = buf32[o32:o32 + n * lda32[i]].view(n, lda32[i])
+        Ab = buf16[o16:o16 + n * lda16[i]].view(n, lda16[i])
+        o32 += n * lda32[i]
+        o16 += n * lda16[i]
+        gen = torch.Generator(device=device)
+        gen.manual_seed(torch_seed_for(4, i))
+        Am.zero_()
+        Am[:, :m] = torch.randn((n, m), generator=gen, device=device) * (1.0 / math.sqrt(m))
+        Ab.zero_()
+        Ab[:, :m] = Am[:, :m].to(torch.bfloat16)
+        g = rng_for(4, i, 2)
+        supp = np.sort(g.choice(n, size=k, replace=False))
+        s = g.standard_normal(k)
+        st = torch.as_tensor(s, device=device)
+        idx = torch.as_tensor(supp, device=device)
+        y = (Am[idx, :m].double().T @ st).float().contiguous()
+        items.append(dict(At=Ab, m=m, y=y, k=k, At_master=Am))
+        supports.append(supp)
+        coefs.append(s)
+    return specs, items, supports, coefs
+
+
+def flat_image_device(device="cuda", n=FLAT_N, m=FLAT_M, k=FLAT_K):
+    """The flattened 256 x 256 image: A iid N(0, 1/m) drawn on the device as an
+    FP32 master and a bfloat16 copy; power-law coefficients truncated to k;
+    noiseless y = A s from the master in float64."""
+    import torch
+    supp, s = flat_image_coeffs(n, k)
+    Am = device_gaussian_atoms(n, m, pad_lda(m, 4), torch_seed_for(5, 0), device)
+    Ab = torch.zeros((n, pad_lda(m, 2)), dtype=torch.bfloat16, device=device)
+    Ab[:, :m] = Am[:, :m].to(torch.bfloat16)
+    idx = torch.as_tensor(supp, device=device)
+    y = (Am[idx, :m].double().T @ torch.as_tensor(s[supp], device=device)).float().contiguous()
+    return Am, Ab, y, supp, s
