@@ -82,10 +82,10 @@ typedef enum {
  * same values the reference oracle uses:
  *   method       CLOMP (default) or plain OMP
  *   inner_steps  T, Adam steps per selected atom (default 32)
- *   lr_rel       learning rate lr = lr_rel * sigma, sigma = max_j |a_j^T y|
- *                (default 0.05)
- *   beta1/beta2  Adam moment decays (0.9 / 0.999); eps = eps_rel * sigma
- *                (eps_rel default 1e-8)
+ *   lr_rel       learning rate of iteration t: lr_t = lr_rel * |c_j|, the
+ *                correlation of the atom selected at t (default 0.05)
+ *   beta1/beta2  Adam moment decays (0.9 / 0.999); eps = eps_rel * sigma with
+ *                sigma = max_j |a_j^T y| (eps_rel default 1e-8)
  *   resid_tol    must be 0 (early stopping on ||r|| is not served)
  *   refine_iters maximum CGLS iterations of the final refinement for supports
  *                too large for the in-LDS QR (0: library default)

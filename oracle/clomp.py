@@ -31,9 +31,13 @@ Readings fixed here (the paper is silent on all of them):
     distinct atoms);
   * optimiser Adam (beta1 = 0.9, beta2 = 0.999), one global step counter per
     instance, state (s, m, v) starts at zero;
-  * lr = lr_rel * sigma and eps = eps_rel * sigma with sigma = max_j |a_j^T y|
-    (the first correlation), so a power-of-two scaling of y scales every
-    iterate by the same power of two;
+  * the learning rate follows the residual: at iteration t, lr_t = lr_rel *
+    |c_j| with c_j the correlation of the atom just selected, and
+    eps = eps_rel * sigma with sigma = max_j |a_j^T y| (the first correlation);
+    both scale with y, so a power-of-two scaling of y scales every iterate by
+    the same power of two.  (A constant lr cannot resolve coefficients several
+    decades below the largest one within T steps: Adam's step has the size of
+    lr whatever the gradient's magnitude.)
   * loss scale 1/2 ||A(mask*s) - y||^2 (see grad.py).
 
 inner='exact' replaces step (iv) by the least-squares s-forward, which turns the
@@ -57,7 +61,7 @@ from .omp import (SolveResult, argmax_unselected, ST_NAN, ST_K_CAPPED,
 @dataclass(frozen=True)
 class ClompParams:
     inner_steps: int = 32      # T: Adam steps per selected atom
-    lr_rel: float = 0.05       # lr = lr_rel * sigma
+    lr_rel: float = 0.05       # lr_t = lr_rel * |c_j| of the atom selected at t
     beta1: float = 0.9
     beta2: float = 0.999
     eps_rel: float = 1e-8      # eps = eps_rel * sigma
@@ -99,11 +103,11 @@ def clomp_fp64(A, y, k, params=ClompParams(), inner="adam", A_refine=None):
                 break
         # (ii) residual injection and argmax selection
         c = A.T @ r
+        j, gap, nonfinite = argmax_unselected(c, S)
         if t == 0:
             sigma = float(np.max(np.abs(c)))
-            lr = params.lr_rel * sigma
             eps = params.eps_rel * sigma
-        j, gap, nonfinite = argmax_unselected(c, S)
+        lr = params.lr_rel * float(abs(c[j]))
         if nonfinite:
             status |= ST_NAN
         gaps.append(gap)

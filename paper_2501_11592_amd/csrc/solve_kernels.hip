@@ -302,11 +302,12 @@ __global__ __launch_bounds__(kBlock) void gram_kernel(const Inst* __restrict__ i
     *I.nsel = t + 1;
     const float cj = key_value(key);
     if (!(cj <= 3.402823466e38f)) atomicOr(I.status, ST_NAN);
+    // step size follows the selected correlation; eps is fixed by the first
     if (t == 0) {
       I.st->sigma = cj;
-      I.st->lr = lr_rel * cj;
       I.st->eps = eps_rel * cj;
     }
+    I.st->lr = lr_rel * cj;
   }
 }
 
@@ -391,11 +392,12 @@ __global__ __launch_bounds__(kBlock) void gram_reg_kernel(const Inst* __restrict
     *I.nsel = t + 1;
     const float cj = key_value(key);
     if (!(cj <= 3.402823466e38f)) atomicOr(I.status, ST_NAN);
+    // step size follows the selected correlation; eps is fixed by the first
     if (t == 0) {
       I.st->sigma = cj;
-      I.st->lr = lr_rel * cj;
       I.st->eps = eps_rel * cj;
     }
+    I.st->lr = lr_rel * cj;
   }
 }
 
@@ -1163,9 +1165,9 @@ __global__ __launch_bounds__(kPassThreads) void coef_pass_kernel(
       if (!(cj <= 3.402823466e38f)) atomicOr(I.status, ST_NAN);
       if (t == 0) {
         I.st->sigma = cj;
-        I.st->lr = lr_rel * cj;
         I.st->eps = eps_rel * cj;
       }
+      I.st->lr = lr_rel * cj;   // step size follows the selected correlation
       I.key[(t + 1) & 1] = 0ull;   // slot of the next scan
     }
     __syncthreads();

@@ -125,7 +125,7 @@ def test_uneven_bf16_batch_with_master(solvers, method):
         ident += kind == "identical"
         assert int(out.n_selected[i]) == min(s.k, s.m, s.n)
     print(f"{method}: identical {ident}/{len(sigs)}")
-    assert ident >= 1     # the oracle calls 5 (CLOMP) / 3 (OMP) of these well separated
+    assert ident >= 1     # the oracle calls 7 (CLOMP) / 3 (OMP) of these well separated
 
 
 def test_edge_cases(solvers):

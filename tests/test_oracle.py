@@ -272,7 +272,8 @@ def test_clomp_first_adam_step_closed_form():
 def test_clomp_matches_autograd_and_torch_adam_rendering():
     """Independent rendering of the paper's CLOMP with framework pieces: s is a
     torch parameter of n entries, the forward is A (mask * s), the loss is
-    1/2 ||y' - y||^2, backward by autograd, update by torch.optim.Adam."""
+    1/2 ||y' - y||^2, backward by autograd, update by torch.optim.Adam with a
+    per-iteration learning rate 0.05 |c_j|."""
     torch = pytest.importorskip("torch")
     for seed in range(3):
         A, y, _, _ = gaussian_instance(seed, 16, 48, 4)
@@ -294,6 +295,8 @@ def test_clomp_matches_autograd_and_torch_adam_rendering():
                     sig = float(c.abs().max())
                     opt = torch.optim.Adam([s], lr=0.05 * sig, betas=(0.9, 0.999),
                                            eps=1e-8 * sig, foreach=False)
+                # learning-rate schedule: lr follows the selected correlation
+                opt.param_groups[0]["lr"] = 0.05 * abs(float(c[j]))
                 mask[j] = 1.0
                 S.append(j)
             for _ in range(12):
