@@ -49,7 +49,25 @@ def parse():
     ap.add_argument("--flow", default="auto", choices=["auto", "resid", "corr"],
                     help="schedule: library default, residual, or correlation update")
     ap.add_argument("--profile-steps", type=int, default=2)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run 5 device copies of 1 GiB (reference for HBM counters)")
     return ap.parse_args()
+
+
+def copy_calibration(torch):
+    """Five plain device-to-device copies of 1 GiB: 1 GiB read and 1 GiB
+    written per copy kernel, the reference for scaling FETCH_SIZE/WRITE_SIZE."""
+    n = (1 << 30) // 4
+    src = torch.randn(n, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 5
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n,
+                      "ms_per_copy": 1e3 * dt, "GBps_read_plus_write": 8 * n / dt / 1e9}))
 
 
 def f32(v):
@@ -114,6 +132,31 @@ def build_workload(args, torch, W):
     raise SystemExit(f"unknown workload {args.workload}")
 
 
+def kernel_digest():
+    """Digest of the device code behind the dominant kernels (coefficient
+    bodies, the pass and scan kernels of the correlation-update schedule and
+    the shared device header)."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2501_11592_amd", "csrc", "solve_kernels.hip")).read()
+    hdr = open(os.path.join(ROOT, "paper_2501_11592_amd", "csrc", "dev_common.h")).read()
+    mark = "// ============================================================ "
+    def region(a, b):
+        return src[src.index(mark + a):src.index(mark + b)]
+    text = region("Adam (CLOMP)", "rows kernels") + \
+        region("correlation-update schedule", "launchers") + hdr
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel's device code has changed since it was measured."""
+    f = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
+    if not os.path.exists(f) or not kernel.startswith("coef_pass"):
+        return None
+    d = json.load(open(f))
+    return d["traffic_bytes_per_launch"] if d.get("kernel_digest") == kernel_digest() else None
+
+
 def roofline(p):
     """Dominant launch of a profile (most total device time) and its achieved
     algorithmic bandwidth."""
@@ -140,6 +183,9 @@ def main():
               "design notes)", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
     from paper_2501_11592_amd import clomp as C
     from paper_2501_11592_amd import workloads as W
 
@@ -216,6 +262,7 @@ def main():
         "roofline_omp": roofline(prof["omp"]),
         "cpu_baseline": cpu,
     }
+    line["roofline"]["traffic"] = measured_traffic(wl["name"], line["roofline"]["kernel"])
     print(json.dumps(line), flush=True)
     for s in solvers.values():
         s.close()

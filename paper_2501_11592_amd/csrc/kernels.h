@@ -33,6 +33,8 @@ hipError_t launch_qr(const Inst* d, const int* list, int nlist, size_t lds_bytes
 hipError_t launch_norm(const Inst* d, const RowTile* tiles, int ntiles, int tmax, hipStream_t s);
 hipError_t launch_finalize(const Inst* d, int count, int check_cg, hipStream_t s);
 hipError_t set_max_lds(size_t bytes);
+// Events the next single-kernel launch records around itself (profiling).
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
 
 // correlation-update schedule (few large signals)
 hipError_t launch_ypass(int bf16, int lpa, const Inst* d, const ScanTile* tiles, int ntiles,

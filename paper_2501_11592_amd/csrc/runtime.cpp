@@ -459,20 +459,35 @@ hipEvent_t pool_event(clomp_ctx* h) {
   return h->ev_pool[h->ev_used++];
 }
 
-// Bracket one phase launch with events when profiling.
+// Time one phase when profiling.  Single-kernel phases hand both events to
+// the launch (recorded by the kernel's own dispatch); multi-kernel phases are
+// bracketed by events recorded on the stream.
 struct PhaseScope {
   clomp_ctx* h;
   int phase;
   hipStream_t st;
-  hipEvent_t a = nullptr;
-  PhaseScope(clomp_ctx* h_, int p, hipStream_t s) : h(h_), phase(p), st(s) {
-    if (h->profiling && (a = pool_event(h))) (void)hipEventRecord(a, st);
+  bool single;
+  hipEvent_t a = nullptr, b = nullptr;
+  PhaseScope(clomp_ctx* h_, int p, hipStream_t s, bool single_kernel = true)
+      : h(h_), phase(p), st(s), single(single_kernel) {
+    if (!h->profiling) return;
+    a = pool_event(h);
+    b = pool_event(h);
+    if (!a || !b) {
+      a = b = nullptr;
+      return;
+    }
+    if (single)
+      set_launch_events(a, b);
+    else
+      (void)hipEventRecord(a, st);
   }
   ~PhaseScope() {
     if (!a) return;
-    hipEvent_t b = pool_event(h);
-    if (!b) return;
-    (void)hipEventRecord(b, st);
+    if (single)
+      set_launch_events(nullptr, nullptr);
+    else
+      (void)hipEventRecord(b, st);
     h->recs.push_back({phase, a, b});
   }
 };
@@ -553,7 +568,7 @@ clomp_status_t launch_all(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st)
   const int lds_cap = (h->lds_limit - 1024) / 4;
 
   {
-    PhaseScope ps(h, PH_INIT, st);
+    PhaseScope ps(h, PH_INIT, st, false);
     HIP_TRY(launch_init(d_insts, count, st), "init");
   }
   if (P.hflow) {
@@ -620,7 +635,7 @@ clomp_status_t launch_all(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st)
   // refinement
   const int ncg = (int)P.cg_list.size();
   {
-  PhaseScope ref_scope(h, PH_REFINE, st);
+  PhaseScope ref_scope(h, PH_REFINE, st, false);
   HIP_TRY(launch_qr(d_insts, d_qr, (int)P.qr_list.size(), P.qr_lds, st), "qr");
   if (ncg > 0) {
     const float tol = prm.refine_tol > 0.f ? prm.refine_tol : 1e-6f;
@@ -644,7 +659,7 @@ clomp_status_t launch_all(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st)
     }
   }
   }
-  PhaseScope ps(h, PH_NORM, st);
+  PhaseScope ps(h, PH_NORM, st, false);
   HIP_TRY(launch_norm(d_insts, d_rows, (int)P.rows.size(), P.kmax, st), "norm");
   HIP_TRY(launch_finalize(d_insts, count, ncg > 0, st), "finalize");
   return CLOMP_OK;

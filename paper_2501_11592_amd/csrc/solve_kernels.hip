@@ -17,10 +17,29 @@
 // Every kernel uses 256-thread workgroups; reductions run in a fixed order,
 // so results are bit-reproducible.
 
+#include <hip/hip_ext.h>
+
 #include "dev_common.h"
 #include "kernels.h"
 
 namespace clomp {
+
+// Profiling: when set, the next launch records these events itself
+// (hipExtLaunchKernelGGL), so their interval is exactly that kernel's run.
+thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
+void set_launch_events(hipEvent_t start, hipEvent_t stop) {
+  g_ev_start = start;
+  g_ev_stop = stop;
+}
+
+#define CLOMP_LAUNCH(kern, grid, block, shm, strm, ...)                                   \
+  do {                                                                                     \
+    if (g_ev_start)                                                                        \
+      hipExtLaunchKernelGGL(kern, grid, block, shm, strm, g_ev_start, g_ev_stop, 0,         \
+                            __VA_ARGS__);                                                  \
+    else                                                                                   \
+      hipLaunchKernelGGL(kern, grid, block, shm, strm, __VA_ARGS__);                       \
+  } while (0)
 
 // ============================================================ init
 // One workgroup per instance: zero the outputs and the per-instance state,
@@ -1272,23 +1291,34 @@ __global__ __launch_bounds__(kCscanThreads) void cscan_kernel(const Inst* __rest
 }
 
 // ============================================================ launchers
+// A launcher with nothing to launch still records pending profiling events,
+// so every recorded interval is valid (and empty).
+static hipError_t nothing_to_launch(hipStream_t s) {
+  if (g_ev_start) {
+    hipError_t e = hipEventRecord(g_ev_start, s);
+    if (e == hipSuccess) e = hipEventRecord(g_ev_stop, s);
+    return e;
+  }
+  return hipSuccess;
+}
+
 template <typename TA>
 static hipError_t scan_dispatch(int lpa, const Inst* d, const ScanTile* tiles, int ntiles,
                                 int r_lds_floats, int reverse, hipStream_t s) {
   const size_t lds = (size_t)r_lds_floats * sizeof(float);
   const int flag = r_lds_floats > 0;
   switch (lpa) {
-    case 4: hipLaunchKernelGGL((scan_kernel<TA, 4>), dim3(ntiles), dim3(kBlock), lds, s, d, tiles, flag, reverse); break;
-    case 8: hipLaunchKernelGGL((scan_kernel<TA, 8>), dim3(ntiles), dim3(kBlock), lds, s, d, tiles, flag, reverse); break;
-    case 16: hipLaunchKernelGGL((scan_kernel<TA, 16>), dim3(ntiles), dim3(kBlock), lds, s, d, tiles, flag, reverse); break;
-    case 32: hipLaunchKernelGGL((scan_kernel<TA, 32>), dim3(ntiles), dim3(kBlock), lds, s, d, tiles, flag, reverse); break;
-    default: hipLaunchKernelGGL((scan_kernel<TA, 64>), dim3(ntiles), dim3(kBlock), lds, s, d, tiles, flag, reverse); break;
+    case 4: CLOMP_LAUNCH((scan_kernel<TA, 4>), dim3(ntiles), dim3(kBlock), lds, s, d, tiles, flag, reverse); break;
+    case 8: CLOMP_LAUNCH((scan_kernel<TA, 8>), dim3(ntiles), dim3(kBlock), lds, s, d, tiles, flag, reverse); break;
+    case 16: CLOMP_LAUNCH((scan_kernel<TA, 16>), dim3(ntiles), dim3(kBlock), lds, s, d, tiles, flag, reverse); break;
+    case 32: CLOMP_LAUNCH((scan_kernel<TA, 32>), dim3(ntiles), dim3(kBlock), lds, s, d, tiles, flag, reverse); break;
+    default: CLOMP_LAUNCH((scan_kernel<TA, 64>), dim3(ntiles), dim3(kBlock), lds, s, d, tiles, flag, reverse); break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_init(const Inst* d, int count, hipStream_t s) {
-  hipLaunchKernelGGL(init_kernel, dim3(count), dim3(kBlock), 0, s, d);
+  CLOMP_LAUNCH(init_kernel, dim3(count), dim3(kBlock), 0, s, d);
   return hipGetLastError();
 }
 
@@ -1297,11 +1327,11 @@ static hipError_t scan_reg_dispatch(int nch, const Inst* d, const ScanTile* tile
                                     int reverse, hipStream_t s) {
   const dim3 g(ntiles), b(kBlock);
   switch (nch) {
-    case 1: hipLaunchKernelGGL((scan_reg_kernel<TA, LPA, 1>), g, b, 0, s, d, tiles, reverse); break;
-    case 2: hipLaunchKernelGGL((scan_reg_kernel<TA, LPA, 2>), g, b, 0, s, d, tiles, reverse); break;
-    case 4: hipLaunchKernelGGL((scan_reg_kernel<TA, LPA, 4>), g, b, 0, s, d, tiles, reverse); break;
-    case 8: hipLaunchKernelGGL((scan_reg_kernel<TA, LPA, 8>), g, b, 0, s, d, tiles, reverse); break;
-    default: hipLaunchKernelGGL((scan_reg_kernel<TA, LPA, 16>), g, b, 0, s, d, tiles, reverse); break;
+    case 1: CLOMP_LAUNCH((scan_reg_kernel<TA, LPA, 1>), g, b, 0, s, d, tiles, reverse); break;
+    case 2: CLOMP_LAUNCH((scan_reg_kernel<TA, LPA, 2>), g, b, 0, s, d, tiles, reverse); break;
+    case 4: CLOMP_LAUNCH((scan_reg_kernel<TA, LPA, 4>), g, b, 0, s, d, tiles, reverse); break;
+    case 8: CLOMP_LAUNCH((scan_reg_kernel<TA, LPA, 8>), g, b, 0, s, d, tiles, reverse); break;
+    default: CLOMP_LAUNCH((scan_reg_kernel<TA, LPA, 16>), g, b, 0, s, d, tiles, reverse); break;
   }
   return hipGetLastError();
 }
@@ -1323,11 +1353,11 @@ static hipError_t gram_reg_dispatch(int nch, const Inst* d, int nact, int t, int
                                     float lr_rel, float eps_rel, hipStream_t s) {
   const dim3 g(nact * nblk), b(kBlock);
   switch (nch) {
-    case 1: hipLaunchKernelGGL((gram_reg_kernel<TA, LPA, 1>), g, b, 0, s, d, t, nblk, D, lr_rel, eps_rel); break;
-    case 2: hipLaunchKernelGGL((gram_reg_kernel<TA, LPA, 2>), g, b, 0, s, d, t, nblk, D, lr_rel, eps_rel); break;
-    case 4: hipLaunchKernelGGL((gram_reg_kernel<TA, LPA, 4>), g, b, 0, s, d, t, nblk, D, lr_rel, eps_rel); break;
-    case 8: hipLaunchKernelGGL((gram_reg_kernel<TA, LPA, 8>), g, b, 0, s, d, t, nblk, D, lr_rel, eps_rel); break;
-    default: hipLaunchKernelGGL((gram_reg_kernel<TA, LPA, 16>), g, b, 0, s, d, t, nblk, D, lr_rel, eps_rel); break;
+    case 1: CLOMP_LAUNCH((gram_reg_kernel<TA, LPA, 1>), g, b, 0, s, d, t, nblk, D, lr_rel, eps_rel); break;
+    case 2: CLOMP_LAUNCH((gram_reg_kernel<TA, LPA, 2>), g, b, 0, s, d, t, nblk, D, lr_rel, eps_rel); break;
+    case 4: CLOMP_LAUNCH((gram_reg_kernel<TA, LPA, 4>), g, b, 0, s, d, t, nblk, D, lr_rel, eps_rel); break;
+    case 8: CLOMP_LAUNCH((gram_reg_kernel<TA, LPA, 8>), g, b, 0, s, d, t, nblk, D, lr_rel, eps_rel); break;
+    default: CLOMP_LAUNCH((gram_reg_kernel<TA, LPA, 16>), g, b, 0, s, d, t, nblk, D, lr_rel, eps_rel); break;
   }
   return hipGetLastError();
 }
@@ -1346,21 +1376,21 @@ static hipError_t gram_reg_lpa(int lpa, int nch, const Inst* d, int nact, int t,
 
 hipError_t launch_scan_reg(int bf16, int lpa, int nch, const Inst* d, const ScanTile* tiles,
                            int ntiles, int reverse, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
+  if (ntiles <= 0) return nothing_to_launch(s);
   return bf16 ? scan_reg_lpa<uint16_t>(lpa, nch, d, tiles, ntiles, reverse, s)
               : scan_reg_lpa<float>(lpa, nch, d, tiles, ntiles, reverse, s);
 }
 
 hipError_t launch_gram_reg(int bf16, int lpa, int nch, const Inst* d, int nact, int t, int nblk,
                            int D, float lr_rel, float eps_rel, hipStream_t s) {
-  if (nact <= 0) return hipSuccess;
+  if (nact <= 0) return nothing_to_launch(s);
   return bf16 ? gram_reg_lpa<uint16_t>(lpa, nch, d, nact, t, nblk, D, lr_rel, eps_rel, s)
               : gram_reg_lpa<float>(lpa, nch, d, nact, t, nblk, D, lr_rel, eps_rel, s);
 }
 
 hipError_t launch_scan(int bf16, int lpa, const Inst* d, const ScanTile* tiles, int ntiles,
                        int r_lds_floats, int reverse, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
+  if (ntiles <= 0) return nothing_to_launch(s);
   return bf16 ? scan_dispatch<uint16_t>(lpa, d, tiles, ntiles, r_lds_floats, reverse, s)
               : scan_dispatch<float>(lpa, d, tiles, ntiles, r_lds_floats, reverse, s);
 }
@@ -1372,78 +1402,78 @@ static hipError_t gram_dispatch(int lpa, const Inst* d, int nact, int t, int nbl
   const int flag = v_lds_floats > 0;
   const dim3 g(nact * nblk), b(kBlock);
   switch (lpa) {
-    case 4: hipLaunchKernelGGL((gram_kernel<TA, 4>), g, b, lds, s, d, t, nblk, D, flag, lr_rel, eps_rel); break;
-    case 8: hipLaunchKernelGGL((gram_kernel<TA, 8>), g, b, lds, s, d, t, nblk, D, flag, lr_rel, eps_rel); break;
-    case 16: hipLaunchKernelGGL((gram_kernel<TA, 16>), g, b, lds, s, d, t, nblk, D, flag, lr_rel, eps_rel); break;
-    case 32: hipLaunchKernelGGL((gram_kernel<TA, 32>), g, b, lds, s, d, t, nblk, D, flag, lr_rel, eps_rel); break;
-    default: hipLaunchKernelGGL((gram_kernel<TA, 64>), g, b, lds, s, d, t, nblk, D, flag, lr_rel, eps_rel); break;
+    case 4: CLOMP_LAUNCH((gram_kernel<TA, 4>), g, b, lds, s, d, t, nblk, D, flag, lr_rel, eps_rel); break;
+    case 8: CLOMP_LAUNCH((gram_kernel<TA, 8>), g, b, lds, s, d, t, nblk, D, flag, lr_rel, eps_rel); break;
+    case 16: CLOMP_LAUNCH((gram_kernel<TA, 16>), g, b, lds, s, d, t, nblk, D, flag, lr_rel, eps_rel); break;
+    case 32: CLOMP_LAUNCH((gram_kernel<TA, 32>), g, b, lds, s, d, t, nblk, D, flag, lr_rel, eps_rel); break;
+    default: CLOMP_LAUNCH((gram_kernel<TA, 64>), g, b, lds, s, d, t, nblk, D, flag, lr_rel, eps_rel); break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_gram(int bf16, int lpa, const Inst* d, int nact, int t, int nblk, int D,
                        int v_lds_floats, float lr_rel, float eps_rel, hipStream_t s) {
-  if (nact <= 0) return hipSuccess;
+  if (nact <= 0) return nothing_to_launch(s);
   return bf16 ? gram_dispatch<uint16_t>(lpa, d, nact, t, nblk, D, v_lds_floats, lr_rel, eps_rel, s)
               : gram_dispatch<float>(lpa, d, nact, t, nblk, D, v_lds_floats, lr_rel, eps_rel, s);
 }
 
 hipError_t launch_adam(const Inst* d, int nact, int t, int T, float beta1, float beta2,
                        hipStream_t s) {
-  if (nact <= 0) return hipSuccess;
+  if (nact <= 0) return nothing_to_launch(s);
   if (t + 1 <= kRegRows)
-    hipLaunchKernelGGL(adam_reg_kernel, dim3(nact), dim3(64 * ((t + 16) / 16)), 0, s, d, t, T,
+    CLOMP_LAUNCH(adam_reg_kernel, dim3(nact), dim3(64 * ((t + 16) / 16)), 0, s, d, t, T,
                        beta1, beta2);
   else
-    hipLaunchKernelGGL(adam_kernel, dim3(nact), dim3(kBlock), (size_t)(t + 1) * sizeof(float), s,
+    CLOMP_LAUNCH(adam_kernel, dim3(nact), dim3(kBlock), (size_t)(t + 1) * sizeof(float), s,
                        d, t, T, beta1, beta2);
   return hipGetLastError();
 }
 
 hipError_t launch_omp(const Inst* d, int nact, int t, hipStream_t s) {
-  if (nact <= 0) return hipSuccess;
-  hipLaunchKernelGGL(omp_ginv_kernel, dim3(nact), dim3(kOmpThreads),
+  if (nact <= 0) return nothing_to_launch(s);
+  CLOMP_LAUNCH(omp_ginv_kernel, dim3(nact), dim3(kOmpThreads),
                      (size_t)6 * (t + 1) * sizeof(float), s, d, t);
   return hipGetLastError();
 }
 
 hipError_t launch_resid(int bf16, const Inst* d, const RowTile* tiles, int ntiles, int t,
                         hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
+  if (ntiles <= 0) return nothing_to_launch(s);
   const size_t lds = ((size_t)2 * (t + 1) + 4 * 64) * sizeof(float);
   if (bf16)
-    hipLaunchKernelGGL((rows_kernel<uint16_t, ROW_RESID>), dim3(ntiles), dim3(kBlock), lds, s, d,
+    CLOMP_LAUNCH((rows_kernel<uint16_t, ROW_RESID>), dim3(ntiles), dim3(kBlock), lds, s, d,
                        tiles, t, 0, 0.f);
   else
-    hipLaunchKernelGGL((rows_kernel<float, ROW_RESID>), dim3(ntiles), dim3(kBlock), lds, s, d,
+    CLOMP_LAUNCH((rows_kernel<float, ROW_RESID>), dim3(ntiles), dim3(kBlock), lds, s, d,
                        tiles, t, 0, 0.f);
   return hipGetLastError();
 }
 
 hipError_t launch_cg_rows(int mode, const Inst* d, const RowTile* tiles, int ntiles, int tmax,
                           int it, float tol2, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
+  if (ntiles <= 0) return nothing_to_launch(s);
   const size_t lds = ((size_t)2 * (tmax + 1) + 4 * 64) * sizeof(float);
   if (mode == 0)
-    hipLaunchKernelGGL((rows_kernel<float, ROW_CG_R0>), dim3(ntiles), dim3(kBlock), lds, s, d,
+    CLOMP_LAUNCH((rows_kernel<float, ROW_CG_R0>), dim3(ntiles), dim3(kBlock), lds, s, d,
                        tiles, tmax, it, tol2);
   else
-    hipLaunchKernelGGL((rows_kernel<float, ROW_CG_Q>), dim3(ntiles), dim3(kBlock), lds, s, d,
+    CLOMP_LAUNCH((rows_kernel<float, ROW_CG_Q>), dim3(ntiles), dim3(kBlock), lds, s, d,
                        tiles, tmax, it, tol2);
   return hipGetLastError();
 }
 
 hipError_t launch_cg_dots(int mode, int lpa, const Inst* d, const int* list, int nlist, int tmax,
                           int nblk, int D, int m_pad_max, int it, hipStream_t s) {
-  if (nlist <= 0) return hipSuccess;
+  if (nlist <= 0) return nothing_to_launch(s);
   const size_t lds = (size_t)m_pad_max * sizeof(float);
   const dim3 g(nlist * nblk), b(kBlock);
 #define CG_DOTS_CASE(L)                                                                     \
   case L:                                                                                   \
     if (mode == 0)                                                                          \
-      hipLaunchKernelGGL((cg_dots_kernel<L, 0>), g, b, lds, s, d, list, tmax, nblk, D, it); \
+      CLOMP_LAUNCH((cg_dots_kernel<L, 0>), g, b, lds, s, d, list, tmax, nblk, D, it); \
     else                                                                                    \
-      hipLaunchKernelGGL((cg_dots_kernel<L, 1>), g, b, lds, s, d, list, tmax, nblk, D, it); \
+      CLOMP_LAUNCH((cg_dots_kernel<L, 1>), g, b, lds, s, d, list, tmax, nblk, D, it); \
     break;
   switch (lpa) {
     CG_DOTS_CASE(4)
@@ -1458,27 +1488,27 @@ hipError_t launch_cg_dots(int mode, int lpa, const Inst* d, const int* list, int
 }
 
 hipError_t launch_copy_s(const Inst* d, const int* list, int nlist, hipStream_t s) {
-  if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(copy_s_kernel, dim3(nlist), dim3(kBlock), 0, s, d, list);
+  if (nlist <= 0) return nothing_to_launch(s);
+  CLOMP_LAUNCH(copy_s_kernel, dim3(nlist), dim3(kBlock), 0, s, d, list);
   return hipGetLastError();
 }
 
 hipError_t launch_qr(const Inst* d, const int* list, int nlist, size_t lds_bytes, hipStream_t s) {
-  if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(qr_refine_kernel, dim3(nlist), dim3(kBlock), lds_bytes, s, d, list);
+  if (nlist <= 0) return nothing_to_launch(s);
+  CLOMP_LAUNCH(qr_refine_kernel, dim3(nlist), dim3(kBlock), lds_bytes, s, d, list);
   return hipGetLastError();
 }
 
 hipError_t launch_norm(const Inst* d, const RowTile* tiles, int ntiles, int tmax, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
+  if (ntiles <= 0) return nothing_to_launch(s);
   const size_t lds = (size_t)2 * (tmax + 1) * sizeof(float);
-  hipLaunchKernelGGL(norm_rows_kernel, dim3(ntiles), dim3(kBlock), lds, s, d, tiles);
+  CLOMP_LAUNCH(norm_rows_kernel, dim3(ntiles), dim3(kBlock), lds, s, d, tiles);
   return hipGetLastError();
 }
 
 hipError_t launch_finalize(const Inst* d, int count, int check_cg, hipStream_t s) {
-  if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(finalize_kernel, dim3(count), dim3(kBlock), 0, s, d, check_cg);
+  if (count <= 0) return nothing_to_launch(s);
+  CLOMP_LAUNCH(finalize_kernel, dim3(count), dim3(kBlock), 0, s, d, check_cg);
   return hipGetLastError();
 }
 
@@ -1523,18 +1553,18 @@ static hipError_t ypass_dispatch(int lpa, const Inst* d, const ScanTile* tiles, 
                                  size_t lds, hipStream_t s) {
   const dim3 g(ntiles), b(kPassThreads);
   switch (lpa) {
-    case 4: hipLaunchKernelGGL((ypass_kernel<TA, 4>), g, b, lds, s, d, tiles); break;
-    case 8: hipLaunchKernelGGL((ypass_kernel<TA, 8>), g, b, lds, s, d, tiles); break;
-    case 16: hipLaunchKernelGGL((ypass_kernel<TA, 16>), g, b, lds, s, d, tiles); break;
-    case 32: hipLaunchKernelGGL((ypass_kernel<TA, 32>), g, b, lds, s, d, tiles); break;
-    default: hipLaunchKernelGGL((ypass_kernel<TA, 64>), g, b, lds, s, d, tiles); break;
+    case 4: CLOMP_LAUNCH((ypass_kernel<TA, 4>), g, b, lds, s, d, tiles); break;
+    case 8: CLOMP_LAUNCH((ypass_kernel<TA, 8>), g, b, lds, s, d, tiles); break;
+    case 16: CLOMP_LAUNCH((ypass_kernel<TA, 16>), g, b, lds, s, d, tiles); break;
+    case 32: CLOMP_LAUNCH((ypass_kernel<TA, 32>), g, b, lds, s, d, tiles); break;
+    default: CLOMP_LAUNCH((ypass_kernel<TA, 64>), g, b, lds, s, d, tiles); break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_ypass(int bf16, int lpa, const Inst* d, const ScanTile* tiles, int ntiles,
                         size_t lds, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
+  if (ntiles <= 0) return nothing_to_launch(s);
   return bf16 ? ypass_dispatch<uint16_t>(lpa, d, tiles, ntiles, lds, s)
               : ypass_dispatch<float>(lpa, d, tiles, ntiles, lds, s);
 }
@@ -1547,15 +1577,15 @@ static hipError_t coef_pass_lpa(int coef, const Inst* dc, int nact, const Inst* 
   const dim3 g(nact + ntiles), b(kPassThreads);
   switch (coef) {
     case COEF_ADAM_REG:
-      hipLaunchKernelGGL((coef_pass_kernel<TA, LPA, COEF_ADAM_REG>), g, b, lds, s, dc, nact, d,
+      CLOMP_LAUNCH((coef_pass_kernel<TA, LPA, COEF_ADAM_REG>), g, b, lds, s, dc, nact, d,
                          tiles, t, T, b1, b2, lr_rel, eps_rel);
       break;
     case COEF_ADAM_GLOBAL:
-      hipLaunchKernelGGL((coef_pass_kernel<TA, LPA, COEF_ADAM_GLOBAL>), g, b, lds, s, dc, nact, d,
+      CLOMP_LAUNCH((coef_pass_kernel<TA, LPA, COEF_ADAM_GLOBAL>), g, b, lds, s, dc, nact, d,
                          tiles, t, T, b1, b2, lr_rel, eps_rel);
       break;
     default:
-      hipLaunchKernelGGL((coef_pass_kernel<TA, LPA, COEF_OMP>), g, b, lds, s, dc, nact, d, tiles,
+      CLOMP_LAUNCH((coef_pass_kernel<TA, LPA, COEF_OMP>), g, b, lds, s, dc, nact, d, tiles,
                          t, T, b1, b2, lr_rel, eps_rel);
       break;
   }
@@ -1578,7 +1608,7 @@ static hipError_t coef_pass_dispatch(int lpa, int coef, const Inst* dc, int nact
 hipError_t launch_coef_pass(int bf16, int lpa, int omp, const Inst* dc, int nact, const Inst* d,
                             const ScanTile* tiles, int ntiles, int t, int T, float beta1,
                             float beta2, float lr_rel, float eps_rel, size_t lds, hipStream_t s) {
-  if (nact + ntiles <= 0) return hipSuccess;
+  if (nact + ntiles <= 0) return nothing_to_launch(s);
   const int coef = omp ? COEF_OMP : (t + 1 <= kRegRows ? COEF_ADAM_REG : COEF_ADAM_GLOBAL);
   return bf16 ? coef_pass_dispatch<uint16_t>(lpa, coef, dc, nact, d, tiles, ntiles, t, T, beta1,
                                              beta2, lr_rel, eps_rel, lds, s)
@@ -1587,8 +1617,8 @@ hipError_t launch_coef_pass(int bf16, int lpa, int omp, const Inst* dc, int nact
 }
 
 hipError_t launch_cscan(const Inst* d, const ScanTile* tiles, int ntiles, int t, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(cscan_kernel, dim3(ntiles), dim3(kCscanThreads), 0, s, d, tiles, t);
+  if (ntiles <= 0) return nothing_to_launch(s);
+  CLOMP_LAUNCH(cscan_kernel, dim3(ntiles), dim3(kCscanThreads), 0, s, d, tiles, t);
   return hipGetLastError();
 }
 
