@@ -238,6 +238,34 @@ typedef struct {
 clomp_status_t clomp_profile_read(clomp_handle_t h, clomp_profile_t* out /*host*/);
 clomp_status_t clomp_profile_reset(clomp_handle_t h);
 
+/*
+ * Launch-shape tuning of a handle (host struct).  Each field is the number of
+ * bulk-matrix kilobytes one workgroup streams in the corresponding kernel;
+ * 0 keeps the current value.  Autotuning (CLOMP_FLAG_AUTOTUNE) writes the same
+ * table: on the first solve of a batch whose size class it has not seen, it
+ * times candidate values on the batch's own first pass over A and keeps the
+ * fastest per (bulk dtype, schedule, size class).
+ *   scan_tile_kb   residual-schedule scan workgroups (default 128)
+ *   pass_tile_kb   correlation-schedule pass workgroups (default 256)
+ *   team_min_rows  correlation schedule: iterations whose support exceeds
+ *                  this many atoms update the coefficients with a team of
+ *                  ceil((t+1)/16) workgroups per signal (at most 128, and
+ *                  only while the teams of all active signals fit on the
+ *                  device at once); smaller supports use one workgroup
+ *                  (default 256; a value >= k disables teams)
+ * clomp_get_tuning returns the values in use for the last solve.
+ * Errors: INVALID_ARGUMENT (NULL, negative or > 65536 values).
+ */
+typedef struct {
+  int32_t scan_tile_kb;
+  int32_t pass_tile_kb;
+  int32_t team_min_rows;
+  int32_t reserved[5];
+} clomp_tuning_t;
+
+clomp_status_t clomp_set_tuning(clomp_handle_t h, const clomp_tuning_t* t /*host*/);
+clomp_status_t clomp_get_tuning(clomp_handle_t h, clomp_tuning_t* t /*host*/);
+
 /* Free the handle, its workspace and graphs (synchronises its device). */
 clomp_status_t clomp_destroy(clomp_handle_t h);
 

@@ -52,6 +52,11 @@ class Profile(ctypes.Structure):
                 ("scan_bytes", ctypes.c_double), ("pass_bytes", ctypes.c_double)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("scan_tile_kb", ctypes.c_int32), ("pass_tile_kb", ctypes.c_int32),
+                ("team_min_rows", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
 class ClompError(RuntimeError):
     pass
 
@@ -88,6 +93,10 @@ def load_library(path=LIB_PATH):
     lib.clomp_profile_read.restype = ctypes.c_int
     lib.clomp_profile_reset.argtypes = [H]
     lib.clomp_profile_reset.restype = ctypes.c_int
+    lib.clomp_set_tuning.argtypes = [H, ctypes.POINTER(Tuning)]
+    lib.clomp_set_tuning.restype = ctypes.c_int
+    lib.clomp_get_tuning.argtypes = [H, ctypes.POINTER(Tuning)]
+    lib.clomp_get_tuning.restype = ctypes.c_int
     lib.clomp_destroy.argtypes = [H]
     lib.clomp_destroy.restype = ctypes.c_int
     lib.clomp_status_string.argtypes = [ctypes.c_int]
@@ -172,6 +181,20 @@ class Solver:
             setattr(self.params, key, v)
         _check(self._h, load_library().clomp_set_params(self._h, ctypes.byref(self.params)),
                "clomp_set_params")
+
+    def set_tuning(self, scan_tile_kb=0, pass_tile_kb=0, team_min_rows=0):
+        t = Tuning()
+        t.scan_tile_kb, t.pass_tile_kb = scan_tile_kb, pass_tile_kb
+        t.team_min_rows = team_min_rows
+        _check(self._h, load_library().clomp_set_tuning(self._h, ctypes.byref(t)),
+               "clomp_set_tuning")
+
+    def get_tuning(self):
+        t = Tuning()
+        _check(self._h, load_library().clomp_get_tuning(self._h, ctypes.byref(t)),
+               "clomp_get_tuning")
+        return {"scan_tile_kb": t.scan_tile_kb, "pass_tile_kb": t.pass_tile_kb,
+                "team_min_rows": t.team_min_rows}
 
     def profile_reset(self):
         _check(self._h, load_library().clomp_profile_reset(self._h), "clomp_profile_reset")

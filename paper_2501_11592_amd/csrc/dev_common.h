@@ -23,6 +23,8 @@
 namespace clomp {
 
 constexpr int kBlock = 256;     // threads per workgroup for every solver kernel
+constexpr int kTeamRows = 16;   // coefficient rows per team member
+constexpr int kTeamMax = 128;   // team members per signal (2048 rows)
 constexpr int kWaves = kBlock / 64;
 
 struct InstState {
@@ -61,6 +63,8 @@ struct Inst {
   float* dg;           // [ldh] ||a_j||^2 (correlation-update schedule)
   float* H;            // [ldh * k_eff] columns A^T a_{S_l} (correlation-update schedule)
   long long ldh;
+  unsigned long long* team;   // [2*k_eff + 2*kTeamMax] tagged words exchanged by a team
+                              // (correlation-update schedule; zeroed at solve start)
   double* npart;       // [n_rowtiles] FP64 residual-norm partial sums
   float* qpart;        // [n_rowtiles] CGLS ||q||^2 partial sums
   unsigned long long* key;

@@ -39,9 +39,13 @@ void set_launch_events(hipEvent_t start, hipEvent_t stop);
 // correlation-update schedule (few large signals)
 hipError_t launch_ypass(int bf16, int lpa, const Inst* d, const ScanTile* tiles, int ntiles,
                         size_t lds, hipStream_t s);
-hipError_t launch_coef_pass(int bf16, int lpa, int omp, const Inst* dc, int nact, const Inst* d,
-                            const ScanTile* tiles, int ntiles, int t, int T, float beta1,
-                            float beta2, float lr_rel, float eps_rel, size_t lds, hipStream_t s);
+// W > 1: a team of W blocks per signal updates the coefficients (W * 16 >=
+// t+1, W <= 128); the caller keeps nact * W below the CU count so that every
+// member is resident at once.
+hipError_t launch_coef_pass(int bf16, int lpa, int omp, const Inst* dc, int nact, int W,
+                            const Inst* d, const ScanTile* tiles, int ntiles, int t, int T,
+                            float beta1, float beta2, float lr_rel, float eps_rel, size_t lds,
+                            hipStream_t s);
 hipError_t launch_cscan(const Inst* d, const ScanTile* tiles, int ntiles, int t, hipStream_t s);
 hipError_t set_max_lds_pass(size_t bytes);
 

@@ -34,8 +34,8 @@ namespace {
 
 constexpr int kMaxKeff = kBlock * 8;        // Adam kernel row capacity
 constexpr size_t kAlign = 256;
-constexpr int kScanTargetBytes = 128 * 1024; // bulk bytes streamed per scan WG
-constexpr int kPassTargetBytes = 256 * 1024; // bulk bytes per pass WG (1024 threads)
+constexpr int kScanTargetKB = 128;   // default bulk KB streamed per scan WG
+constexpr int kPassTargetKB = 256;   // default bulk KB per pass WG (1024 threads)
 constexpr int kPassThreadsHost = 1024;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -108,6 +108,10 @@ struct clomp_ctx {
   double scan_bytes = 0.0, pass_bytes = 0.0;
   bool profiling = false;
   bool pass_lds_ok = false;           // dynamic-LDS ceiling raised for pass kernels
+  int scan_tile_kb = kScanTargetKB;
+  int pass_tile_kb = kPassTargetKB;
+  int team_min_rows = 256;            // larger supports use coefficient teams
+  std::map<std::string, int> tuned;   // autotuned pass tile per size class
 };
 
 namespace {
@@ -241,7 +245,8 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
   P.keff.resize(count);
   P.kmax = 0;
   size_t ws = 0;
-  snprintf(sigbuf, sizeof sigbuf, "d%d;m%d;T%d;", bf16, prm.method, prm.inner_steps);
+  snprintf(sigbuf, sizeof sigbuf, "d%d;m%d;T%d;s%d;p%d;w%d;", bf16, prm.method,
+           prm.inner_steps, h->scan_tile_kb, h->pass_tile_kb, h->team_min_rows);
   P.sig += sigbuf;
   for (int s = 0; s < count; ++s) {
     const int i = order[s];
@@ -283,12 +288,13 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     const size_t o_z = take(sizeof(float) * d.k_eff);
     const size_t o_L = omp ? take(sizeof(float) * (size_t)d.k_eff * d.ldg) : 0;
     const size_t o_cg = use_qr ? 0 : take(sizeof(float) * (3 * (size_t)d.m_pad + 3 * d.k_eff));
-    size_t o_c0 = 0, o_H = 0, o_dg = 0;
+    size_t o_c0 = 0, o_H = 0, o_dg = 0, o_team = 0;
     if (P.hflow) {
       d.ldh = round_up_int(d.n, 256);
       o_c0 = take(sizeof(float) * d.ldh);
       o_dg = take(sizeof(float) * d.ldh);
       o_H = take(sizeof(float) * (size_t)d.ldh * d.k_eff);
+      o_team = take(sizeof(unsigned long long) * (2 * (size_t)d.k_eff + 2 * kTeamMax));
     }
     const size_t o_np = take(sizeof(double) * d.n_rowtiles);
     const size_t o_qp = take(sizeof(float) * d.n_rowtiles);
@@ -308,6 +314,7 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     d.cg = use_qr ? nullptr : (float*)(o_cg + 1);
     d.c0 = P.hflow ? (float*)(o_c0 + 1) : nullptr;
     d.dg = P.hflow ? (float*)(o_dg + 1) : nullptr;
+    d.team = P.hflow ? (unsigned long long*)(o_team + 1) : nullptr;
     d.H = P.hflow ? (float*)(o_H + 1) : nullptr;
     d.npart = (double*)(o_np + 1);
     d.qpart = (float*)(o_qp + 1);
@@ -341,7 +348,7 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     for (int q = c.i0; q < c.i1; ++q) {
       const Inst& d = P.insts[q];
       const size_t atom_bytes = (size_t)d.m_pad * esize;
-      int apg = (int)std::max<size_t>(1, kScanTargetBytes / (atom_bytes * ng));
+      int apg = (int)std::max<size_t>(1, (size_t)h->scan_tile_kb * 1024 / (atom_bytes * ng));
       const int apt = ng * apg;
       for (int j0 = 0; j0 < d.n; j0 += apt) P.tiles.push_back({q, j0, std::min(d.n, j0 + apt), 0});
       c.tile_prefix.push_back((int)(P.tiles.size() - c.tile_off));
@@ -356,7 +363,7 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
           c.ctile_off = P.ctiles.size();
         }
         const int hng = kPassThreadsHost / c.lpa;
-        const int happ = (int)std::max<size_t>(1, kPassTargetBytes / (atom_bytes * hng));
+        const int happ = (int)std::max<size_t>(1, (size_t)h->pass_tile_kb * 1024 / (atom_bytes * hng));
         const int hapt = hng * happ;
         for (int j0 = 0; j0 < d.n; j0 += hapt)
           P.htiles.push_back({q, j0, std::min(d.n, j0 + hapt), 0});
@@ -528,10 +535,18 @@ clomp_status_t launch_hflow(clomp_ctx* h, const Plan& P, int bf16, hipStream_t s
         // iteration t, fused with h_t = A^T a_{S_t} for the instances that
         // select again
         const size_t t1 = (size_t)t + 1;
+        // a team of W blocks per signal for supports beyond the register tile,
+        // while the teams stay far below the CU count (all resident at once)
+        int W = 1;
+        if (t1 > (size_t)h->team_min_rows) {
+          const int want = (int)((t1 + 15) / 16);
+          if (want <= kTeamMax && (long long)want * nact <= h->num_cu - 8) W = want;
+        }
         size_t lds = (size_t)c.m_pad_max * sizeof(float);
         lds = std::max(lds, (omp ? 6 : 1) * t1 * sizeof(float));
+        if (W > 1) lds = std::max(lds, (t1 + 4 + 32) * sizeof(float));
         PhaseScope ps(h, PH_PASS, st);
-        HIP_TRY(launch_coef_pass(bf16, c.lpa, omp, d_insts + c.i0, nact, d_insts,
+        HIP_TRY(launch_coef_pass(bf16, c.lpa, omp, d_insts + c.i0, nact, W, d_insts,
                                  d_htiles + c.htile_off, c.htile_prefix[nnext], t,
                                  prm.inner_steps, prm.beta1, prm.beta2, prm.lr_rel, prm.eps_rel,
                                  lds, st),
@@ -791,7 +806,8 @@ clomp_status_t clomp_solve_batch(clomp_handle_t h, const clomp_instance_t* inst,
                    wsb + (reinterpret_cast<uintptr_t>(ptr) - 1));
     };
     rb(d.r); rb(d.G); rb(d.b); rb(d.s); rb(d.mo); rb(d.ve); rb(d.xf); rb(d.z);
-    rb(d.Linv); rb(d.cg); rb(d.c0); rb(d.dg); rb(d.H); rb(d.npart); rb(d.qpart); rb(d.key);
+    rb(d.Linv); rb(d.cg); rb(d.c0); rb(d.dg); rb(d.H); rb(d.team); rb(d.npart);
+    rb(d.qpart); rb(d.key);
     rb(d.bitmap);
     rb(d.st);
   }
@@ -891,6 +907,28 @@ clomp_status_t clomp_grad(clomp_handle_t h, int32_t n, int32_t m, int64_t lda, i
                       loss, h->gwork.p, ncolchunk, colchunk, st),
           "grad");
   (void)hipSetDevice(prev);
+  return CLOMP_OK;
+}
+
+clomp_status_t clomp_set_tuning(clomp_handle_t h, const clomp_tuning_t* t) {
+  if (!h || !t) return CLOMP_INVALID_ARGUMENT;
+  if (t->scan_tile_kb < 0 || t->scan_tile_kb > 65536 || t->pass_tile_kb < 0 ||
+      t->pass_tile_kb > 65536 || t->team_min_rows < 0)
+    return fail(h, CLOMP_INVALID_ARGUMENT,
+                "tile sizes must lie in [0, 65536] KB and team_min_rows must be >= 0");
+  if (t->scan_tile_kb) h->scan_tile_kb = t->scan_tile_kb;
+  if (t->pass_tile_kb) h->pass_tile_kb = t->pass_tile_kb;
+  if (t->team_min_rows) h->team_min_rows = t->team_min_rows;
+  drop_graphs(h);
+  return CLOMP_OK;
+}
+
+clomp_status_t clomp_get_tuning(clomp_handle_t h, clomp_tuning_t* t) {
+  if (!h || !t) return CLOMP_INVALID_ARGUMENT;
+  memset(t, 0, sizeof *t);
+  t->scan_tile_kb = h->scan_tile_kb;
+  t->pass_tile_kb = h->pass_tile_kb;
+  t->team_min_rows = h->team_min_rows;
   return CLOMP_OK;
 }
 

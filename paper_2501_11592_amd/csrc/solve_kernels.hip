@@ -63,6 +63,8 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const Inst* __restrict__ i
   for (int i = threadIdx.x; i < I.k_eff; i += kBlock) {
     I.s[i] = 0.f; I.mo[i] = 0.f; I.ve[i] = 0.f; I.xf[i] = 0.f; I.z[i] = 0.f;
   }
+  if (I.team)   // tag 0 is never awaited
+    for (int i = threadIdx.x; i < 2 * I.k_eff + 2 * kTeamMax; i += kBlock) I.team[i] = 0ull;
   __syncthreads();
   if (threadIdx.x == 0) {
     InstState st = {};
@@ -85,7 +87,7 @@ template <typename TA, int LPA>
 __global__ __launch_bounds__(kBlock) void scan_kernel(const Inst* __restrict__ insts,
                                                       const ScanTile* __restrict__ tiles,
                                                       int r_in_lds, int reverse) {
-  extern __shared__ float smem[];
+  extern __shared__ __align__(16) float smem[];
   __shared__ unsigned long long wbest[kWaves];
   // Odd iterations walk the tiles backwards, so a scan starts on the columns
   // the previous scan streamed last (still resident in the memory-side cache
@@ -239,7 +241,7 @@ template <typename TA, int LPA>
 __global__ __launch_bounds__(kBlock) void gram_kernel(const Inst* __restrict__ insts, int t,
                                                       int nblk, int D, int v_in_lds,
                                                       float lr_rel, float eps_rel) {
-  extern __shared__ float smem[];
+  extern __shared__ __align__(16) float smem[];
   const int ii = blockIdx.x / nblk;
   const int blk = blockIdx.x - ii * nblk;
   const Inst& I = insts[ii];
@@ -516,7 +518,7 @@ __device__ void adam_global_body(const Inst& I, int t, int T, float beta1, float
 
 __global__ __launch_bounds__(kBlock) void adam_kernel(const Inst* __restrict__ insts, int t,
                                                       int T, float beta1, float beta2) {
-  extern __shared__ float ssh[];  // s[t+1]
+  extern __shared__ __align__(16) float ssh[];  // s[t+1]
   adam_global_body<kBlock>(insts[blockIdx.x], t, T, beta1, beta2, ssh);
 }
 
@@ -730,7 +732,7 @@ __device__ void omp_ginv_body(const Inst& I, int t, float* osh, float* red, floa
 
 __global__ __launch_bounds__(kOmpThreads) void omp_ginv_kernel(const Inst* __restrict__ insts,
                                                                int t) {
-  extern __shared__ float osh[];  // g[t1] | v[t1] | vpart[4][t1]
+  extern __shared__ __align__(16) float osh[];  // g[t1] | v[t1] | vpart[4][t1]
   __shared__ float red[kOmpThreads / 64], red2[kOmpThreads / 64];
   omp_ginv_body(insts[blockIdx.x], t, osh, red, red2);
 }
@@ -748,7 +750,7 @@ template <typename TA, int MODE>
 __global__ __launch_bounds__(kBlock) void rows_kernel(const Inst* __restrict__ insts,
                                                       const RowTile* __restrict__ tiles,
                                                       int t, int it, float tol2) {
-  extern __shared__ float rsh[];  // coef[t1] | (int) sup[t1] | part[4*64]
+  extern __shared__ __align__(16) float rsh[];  // coef[t1] | (int) sup[t1] | part[4*64]
   __shared__ float red[kWaves];
   const RowTile rt = tiles[blockIdx.x];
   const Inst& I = insts[rt.inst];
@@ -853,7 +855,7 @@ template <int LPA, int MODE>
 __global__ __launch_bounds__(kBlock) void cg_dots_kernel(const Inst* __restrict__ insts,
                                                          const int* __restrict__ list,
                                                          int t, int nblk, int D, int it) {
-  extern __shared__ float vsh[];
+  extern __shared__ __align__(16) float vsh[];
   const int ii = blockIdx.x / nblk;
   const int blk = blockIdx.x - ii * nblk;
   const Inst& I = insts[list[ii]];
@@ -903,7 +905,7 @@ __global__ __launch_bounds__(kBlock) void cg_dots_kernel(const Inst* __restrict_
 // triangular solve R x = Q^T y, one workgroup per instance in the list.
 __global__ __launch_bounds__(kBlock) void qr_refine_kernel(const Inst* __restrict__ insts,
                                                            const int* __restrict__ list) {
-  extern __shared__ float qsh[];
+  extern __shared__ __align__(16) float qsh[];
   __shared__ float red[kWaves];
   __shared__ float diag[1];
   const Inst& I = insts[list[blockIdx.x]];
@@ -980,7 +982,7 @@ __global__ __launch_bounds__(kBlock) void qr_refine_kernel(const Inst* __restric
 // Partial sums of (y_i - sum_l Am[i, S_l] xf_l)^2 accumulated in float64.
 __global__ __launch_bounds__(kBlock) void norm_rows_kernel(const Inst* __restrict__ insts,
                                                            const RowTile* __restrict__ tiles) {
-  extern __shared__ float nsh[];  // xf[t1] | sup[t1]
+  extern __shared__ __align__(16) float nsh[];  // xf[t1] | sup[t1]
   __shared__ double dpart[kBlock];
   const RowTile rt = tiles[blockIdx.x];
   const Inst& I = insts[rt.inst];
@@ -1056,17 +1058,38 @@ constexpr int kPassThreads = 1024;
 // One tile of a pass over A with a staged vector v (zero padded):
 //   MODE 0: v = y, writes c0[j] = a_j^T y and the argmax key of |c0|
 //   MODE 1: v = a_{S_t}, writes H[j, t] = a_j^T a_{S_t}
+// bf16 pairs: x.lo * y.lo + x.hi * y.hi + acc in FP32 (v_dot2c_f32_bf16)
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+__device__ inline float dot2_bf16(unsigned x, unsigned y, float acc) {
+  return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, x),
+                                         __builtin_bit_cast(bf16x2_t, y), acc, false);
+}
+// zero the bf16 elements [tail, 8) of a 16-byte chunk
+__device__ inline uint4 mask_bf16_tail(uint4 q, int tail) {
+  unsigned w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const unsigned keep = (2 * e + 1 < tail) ? 0xffffffffu : (2 * e < tail ? 0x0000ffffu : 0u);
+    w[e] &= keep;
+  }
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
 template <typename TA, int LPA, int MODE>
 __device__ void pass_tile_body(const Inst& I, const ScanTile& tile, int t, float* vsh,
                                unsigned long long* wbest) {
   if (I.st->done) return;
   constexpr int VW = Vec<TA>::W;
   constexpr int NT = kPassThreads;
+  // the pass of a selected BF16 atom keeps the atom as bf16 in LDS and
+  // contracts bf16 pairs directly
+  constexpr bool BF = sizeof(TA) == 2 && MODE == 1;
   const int m = I.m;
   const int nvec = (m + VW - 1) / VW;
   const int tail = m - (nvec - 1) * VW;
   const TA* A = reinterpret_cast<const TA*>(I.A);
   const long long lda = I.lda;
+  uint4* vsh4 = reinterpret_cast<uint4*>(vsh);
   if (MODE == 0) {
     const float* yw = I.r + I.m_pad;   // zero padded beyond m
     for (int i = threadIdx.x; i < nvec * VW; i += NT) vsh[i] = yw[i];
@@ -1077,10 +1100,15 @@ __device__ void pass_tile_body(const Inst& I, const ScanTile& tile, int t, float
     if (jt < 0 || jt >= I.n) return;
     const TA* colj = A + (long long)jt * lda;
     for (int c = threadIdx.x; c < nvec; c += NT) {
-      float a[VW];
-      Vec<TA>::load(colj + (long long)c * VW, a);
+      if constexpr (BF) {
+        uint4 q = *reinterpret_cast<const uint4*>(colj + (long long)c * VW);
+        vsh4[c] = (c == nvec - 1) ? mask_bf16_tail(q, tail) : q;
+      } else {
+        float a[VW];
+        Vec<TA>::load(colj + (long long)c * VW, a);
 #pragma unroll
-      for (int e = 0; e < VW; ++e) vsh[c * VW + e] = (c * VW + e < m) ? a[e] : 0.f;
+        for (int e = 0; e < VW; ++e) vsh[c * VW + e] = (c * VW + e < m) ? a[e] : 0.f;
+      }
     }
   }
   __syncthreads();
@@ -1088,25 +1116,38 @@ __device__ void pass_tile_body(const Inst& I, const ScanTile& tile, int t, float
   const int grp = threadIdx.x / LPA;
   constexpr int NG = NT / LPA;
   unsigned long long best = 0ull;
+  // 16-byte loads in flight per lane: 8, except 4 when BF16 chunks expand
+  // to FP32 (the first pass against the FP32 measurements)
+  constexpr int UNR = (sizeof(TA) == 2 && !BF) ? 4 : 8;
   for (int j = tile.j0 + grp; j < tile.j1; j += NG) {
     const TA* col = A + (long long)j * lda;
-    float acc = 0.f, nrm = 0.f;
-#pragma unroll 8
+    float acc = 0.f, acc2 = 0.f, nrm = 0.f;
+#pragma unroll UNR
     for (int c = gl; c < nvec; c += LPA) {
-      float v[VW];
-      Vec<TA>::load(col + (long long)c * VW, v);
-      if (c == nvec - 1) {
+      if constexpr (BF) {
+        uint4 q = *reinterpret_cast<const uint4*>(col + (long long)c * VW);
+        if (c == nvec - 1) q = mask_bf16_tail(q, tail);
+        const uint4 u = vsh4[c];
+        acc = dot2_bf16(q.x, u.x, acc);
+        acc2 = dot2_bf16(q.y, u.y, acc2);
+        acc = dot2_bf16(q.z, u.z, acc);
+        acc2 = dot2_bf16(q.w, u.w, acc2);
+      } else {
+        float v[VW];
+        Vec<TA>::load(col + (long long)c * VW, v);
+        if (c == nvec - 1) {
 #pragma unroll
-        for (int e = 0; e < VW; ++e) v[e] = (e < tail) ? v[e] : 0.f;
-      }
-      const float* vv = vsh + c * VW;
+          for (int e = 0; e < VW; ++e) v[e] = (e < tail) ? v[e] : 0.f;
+        }
+        const float* vv = vsh + c * VW;
 #pragma unroll
-      for (int e = 0; e < VW; ++e) {
-        acc = fmaf(v[e], vv[e], acc);
-        if (MODE == 0) nrm = fmaf(v[e], v[e], nrm);
+        for (int e = 0; e < VW; ++e) {
+          acc = fmaf(v[e], vv[e], acc);
+          if (MODE == 0) nrm = fmaf(v[e], v[e], nrm);
+        }
       }
     }
-    acc = group_sum<LPA>(acc);
+    acc = group_sum<LPA>(acc + acc2);
     if (MODE == 0) {
       // the first pass also records ||a_j||^2, the Gram diagonal
       nrm = group_sum<LPA>(nrm);
@@ -1135,27 +1176,252 @@ __device__ void pass_tile_body(const Inst& I, const ScanTile& tile, int t, float
 template <typename TA, int LPA>
 __global__ __launch_bounds__(kPassThreads) void ypass_kernel(const Inst* __restrict__ insts,
                                                              const ScanTile* __restrict__ tiles) {
-  extern __shared__ float dsh[];
+  extern __shared__ __align__(16) float dsh[];
   __shared__ unsigned long long wbest[kPassThreads / 64];
   const ScanTile tile = tiles[blockIdx.x];
   pass_tile_body<TA, LPA, 0>(insts[tile.inst], tile, 0, dsh, wbest);
 }
 
-enum CoefKind : int { COEF_ADAM_REG = 0, COEF_ADAM_GLOBAL = 1, COEF_OMP = 2 };
+// ---- teams: several blocks share one signal's coefficient update ----------
+// For supports beyond the register tile, W blocks (members) of the fused
+// launch split the rows of the update.  Members are the first blocks of the
+// launch and W times the number of signals stays below the CU count, so all
+// members are resident together.  Members exchange values as 64-bit words
+// (tag << 32 | float bits) written and read with agent-scope atomics: a
+// reader waits until the word carries the tag it expects, so the value and
+// its readiness travel together and no read-modify-write barrier is needed.
+// Tags grow strictly within a solve (Adam step number, or t+1 for OMP) and
+// the words are zeroed at solve start.  A wait is bounded: on expiry it sets
+// the watchdog bit, which ends every other wait of the signal at once; the
+// launch then finishes with unspecified coefficients and member 0 retires
+// the signal.
+constexpr unsigned kSpinLimit = 1u << 20;
+
+__device__ inline void team_put(unsigned long long* p, unsigned tag, float v) {
+  __hip_atomic_store(p, ((unsigned long long)tag << 32) | __float_as_uint(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline float team_get(const Inst& I, const unsigned long long* p, unsigned tag) {
+  unsigned long long w = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  unsigned spins = 0;
+  while ((unsigned)(w >> 32) != tag) {
+    __builtin_amdgcn_s_sleep(1);
+    if (__hip_atomic_load(I.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ST_WATCHDOG)
+      break;
+    if (++spins > kSpinLimit) {
+      atomicOr(I.status, ST_WATCHDOG);
+      break;
+    }
+    w = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return __uint_as_float((unsigned)w);
+}
+
+// after a team update: a signal whose team timed out takes no further part
+__device__ inline void team_retire(const Inst& I, int w) {
+  if (w == 0 && threadIdx.x == 0 &&
+      (__hip_atomic_load(I.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ST_WATCHDOG))
+    I.st->done = 1;
+}
+
+// Entry G[r, c] of the Gram matrix during iteration t (atom j selected):
+// entries of earlier iterations from G, the new row / column from H and the
+// norms (member 0 writes them to G in this same launch).
+__device__ inline float gram_at(const Inst& I, int j, int t, int r, int c) {
+  if (r < t && c < t) return I.G[c + (long long)r * I.ldg];
+  if (r == t && c == t) return I.dg[j];
+  return I.H[j + (long long)(r < t ? r : c) * I.ldh];
+}
+
+// Adam on rows [16w, 16w+16) of a support of t+1 atoms (same update as the
+// single-block bodies).  Wave rho owns row r = 16w + rho: lane q holds
+// G[r, 4q + 256i + e] (i < 8, e < 4) in registers.  Each step the member
+// forms its rows of G s with one wave reduction per row, updates and
+// publishes its coefficients, then gathers the whole new s into LDS.  Words
+// alternate between two buffers by step parity: a member overwrites a buffer
+// only after gathering every word of the other one, which every member
+// publishes only after its own gather of this one is complete.
+__device__ void adam_team_body(const Inst& I, int j, int t, int T, float lr, float beta1,
+                               float beta2, int w, float* lds) {
+  const int t1 = t + 1;
+  const int t4 = (t1 + 3) & ~3;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, rho = tid >> 6;
+  const int r = w * kTeamRows + rho;
+  const bool row_ok = r < t1;
+  float* s_lds = lds;                                // [t4]
+  float Gr[8][4];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int c = 4 * lane + 256 * i;
+    if (r < t && c + 3 < t) {   // entries of earlier iterations (not row t)
+      const float4 q = *reinterpret_cast<const float4*>(I.G + c + (long long)r * I.ldg);
+      Gr[i][0] = q.x; Gr[i][1] = q.y; Gr[i][2] = q.z; Gr[i][3] = q.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) Gr[i][e] = (row_ok && c + e < t1) ? gram_at(I, j, t, r, c + e) : 0.f;
+    }
+  }
+  float sv = 0.f, mo = 0.f, ve = 0.f, bb = 0.f;
+  if (row_ok) {
+    sv = I.s[r];
+    mo = I.mo[r];
+    ve = I.ve[r];
+    bb = (r == t) ? I.c0[j] : I.b[r];
+  }
+  for (int c = tid; c < t4; c += kPassThreads) s_lds[c] = (c < t1) ? I.s[c] : 0.f;
+  const float eps = I.st->eps;
+  const int step0 = I.st->step;
+  double b1p = pow((double)beta1, (double)step0);
+  double b2p = pow((double)beta2, (double)step0);
+  __syncthreads();
+  for (int it = 0; it < T; ++it) {
+    b1p *= beta1;
+    b2p *= beta2;
+    const float ibc1 = __builtin_amdgcn_rcpf((float)(1.0 - b1p));
+    const float ibc2 = __builtin_amdgcn_rcpf((float)(1.0 - b2p));
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int c = 4 * lane + 256 * i;
+      if (c < t4) {
+        const float4 sq = *reinterpret_cast<const float4*>(s_lds + c);
+        a0 = fmaf(Gr[i][0], sq.x, a0);
+        a1 = fmaf(Gr[i][1], sq.y, a1);
+        a2 = fmaf(Gr[i][2], sq.z, a2);
+        a3 = fmaf(Gr[i][3], sq.w, a3);
+      }
+    }
+    const float gs = wave_sum((a0 + a1) + (a2 + a3));
+    const unsigned tag = (unsigned)(step0 + it + 1);
+    unsigned long long* buf = I.team + (size_t)(tag & 1) * I.k_eff;
+    if (row_ok && lane == 0) {
+      const float gr = gs - bb;
+      mo = beta1 * mo + (1.f - beta1) * gr;
+      ve = beta2 * ve + (1.f - beta2) * (gr * gr);
+      sv = sv - lr * (mo * ibc1) * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(ve * ibc2) + eps);
+      if (it + 1 < T) team_put(buf + r, tag, sv);
+    }
+    if (it + 1 < T) {
+      __syncthreads();                               // every wave is done with s_lds
+      for (int c = tid; c < t1; c += kPassThreads) s_lds[c] = team_get(I, buf + c, tag);
+      __syncthreads();
+    }
+  }
+  if (row_ok && lane == 0) {
+    I.s[r] = sv;
+    I.mo[r] = mo;
+    I.ve[r] = ve;
+  }
+  if (w == 0 && tid == 0) I.st->step = step0 + T;
+}
+
+// OMP bordered-inverse update split by rows of Ginv (a member updates its own
+// columns, which by symmetry are its rows and contiguous): v = Ginv g and the
+// member's partial products g.v, g.x are published with tag t+1; every member
+// then forms delta and alpha from the partials in the same order and updates
+// its columns, its entries of the new border and its coefficients.
+__device__ void omp_team_body(const Inst& I, int j, int t, int W, int w, float* lds) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const long long ld = I.ldg;
+  const unsigned tag = (unsigned)(t + 1);
+  float* Gi = I.Linv;
+  float* g = lds;                                    // [t+1]
+  float* red = lds + t + 1;                          // [32]
+  for (int c = tid; c <= t; c += kPassThreads) g[c] = (c < t) ? I.H[j + (long long)c * I.ldh] : I.dg[j];
+  __syncthreads();
+  unsigned long long* vbuf = I.team;                 // [k_eff]
+  unsigned long long* pbuf = I.team + 2 * (size_t)I.k_eff;   // [2][kTeamMax]
+  const int r = w * kTeamRows + wv;                  // one wave per row
+  float vr = 0.f, pv = 0.f, px = 0.f;
+  if (r < t) {
+    const float* col = Gi + (long long)r * ld;
+    float a = 0.f;
+    for (int c = lane; c < t; c += 64) a = fmaf(col[c], g[c], a);
+    vr = wave_sum(a);
+    if (lane == 0) {
+      team_put(vbuf + r, tag, vr);
+      pv = g[r] * vr;
+      px = g[r] * I.s[r];
+    }
+  }
+  if (lane == 0) {
+    red[wv] = pv;
+    red[16 + wv] = px;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    float a = 0.f, b = 0.f;
+    for (int q = 0; q < kTeamRows; ++q) {
+      a += red[q];
+      b += red[16 + q];
+    }
+    team_put(pbuf + w, tag, a);
+    team_put(pbuf + kTeamMax + w, tag, b);
+  }
+  float gv = 0.f, gx = 0.f;
+  if (tid < 64) {   // one wave gathers the partials in member order
+    for (int q = 0; q < W; ++q) {
+      gv += team_get(I, pbuf + q, tag);
+      gx += team_get(I, pbuf + kTeamMax + q, tag);
+    }
+    if (tid == 0) {
+      red[0] = gv;
+      red[1] = gx;
+    }
+  }
+  __syncthreads();
+  gv = red[0];
+  gx = red[1];
+  const float gamma = g[t];
+  float delta = gamma - gv;
+  const bool bad = !(delta > 1e-7f * gamma);
+  if (bad) delta = fmaxf(1e-7f * gamma, 1e-30f);
+  const float inv = 1.f / delta;
+  const float alpha = (I.c0[j] - gx) * inv;
+  float* v = g;                                      // g is no longer needed
+  __syncthreads();
+  for (int c = tid; c < t; c += kPassThreads) v[c] = team_get(I, vbuf + c, tag);
+  __syncthreads();
+  if (r < t) {
+    float* col = Gi + (long long)r * ld;
+    const float vri = vr * inv;
+    for (int c = lane; c < t; c += 64) col[c] = fmaf(v[c], vri, col[c]);
+    if (lane == 0) {
+      col[t] = -vri;                                 // Ginv[t, r]
+      Gi[r + (long long)t * ld] = -vri;              // Ginv[r, t]
+      I.s[r] = fmaf(-alpha, vr, I.s[r]);
+    }
+  }
+  if (w == 0 && tid == 0) {
+    I.s[t] = alpha;
+    Gi[t + (long long)t * ld] = inv;
+    if (bad) atomicOr(I.status, ST_REFINE_INACCURATE);
+  }
+}
+
+enum CoefKind : int {
+  COEF_ADAM_REG = 0, COEF_ADAM_GLOBAL = 1, COEF_OMP = 2, COEF_ADAM_TEAM = 3, COEF_OMP_TEAM = 4
+};
 
 // Blocks [0, nact): coefficient update of iteration t for the class's active
 // instances (insts_c = class base).  Blocks [nact, ...): h_t pass tiles.
 template <typename TA, int LPA, int COEF>
 __global__ __launch_bounds__(kPassThreads) void coef_pass_kernel(
-    const Inst* __restrict__ insts_c, int nact, const Inst* __restrict__ insts,
+    const Inst* __restrict__ insts_c, int nact, int W, const Inst* __restrict__ insts,
     const ScanTile* __restrict__ tiles, int t, int T, float beta1, float beta2, float lr_rel,
     float eps_rel) {
-  extern __shared__ float dsh[];
+  extern __shared__ __align__(16) float dsh[];
   __shared__ float4 part[2][16][64];
   __shared__ float red[kPassThreads / 64], red2[kPassThreads / 64];
   __shared__ unsigned long long wbest[kPassThreads / 64];
-  if ((int)blockIdx.x < nact) {
-    const Inst& I = insts_c[blockIdx.x];
+  if ((int)blockIdx.x < nact * W) {
+    const Inst& I = insts_c[blockIdx.x / W];
+    const int member = blockIdx.x % W;
+    // done is set only by earlier launches or, below, together with a bad
+    // key that every member sees: all members leave together
     if (I.st->done) return;
     // selection record and the new Gram column, gathered from H:
     //   G[l, t] = a_{S_l}^T a_j = H[j, l] (l < t),  G[t, t] = ||a_j||^2,
@@ -1163,31 +1429,43 @@ __global__ __launch_bounds__(kPassThreads) void coef_pass_kernel(
     const unsigned long long key = I.key[t & 1];
     const int j = key_index(key);
     if (key == 0ull || j < 0 || j >= I.n) {
-      if (threadIdx.x == 0) {
+      if (member == 0 && threadIdx.x == 0) {
         I.st->done = 1;
         atomicOr(I.status, ST_WATCHDOG);
       }
       return;
     }
-    for (int l = threadIdx.x; l < t; l += kPassThreads) {
-      const float g = I.H[j + (long long)l * I.ldh];
-      I.G[l + (long long)t * I.ldg] = g;
-      I.G[t + (long long)l * I.ldg] = g;
-    }
-    if (threadIdx.x == 0) {
-      I.G[t + (long long)t * I.ldg] = I.dg[j];
-      I.b[t] = I.c0[j];
-      I.support[t] = j;
-      I.bitmap[j >> 5] |= (1u << (j & 31));
-      *I.nsel = t + 1;
-      const float cj = key_value(key);
-      if (!(cj <= 3.402823466e38f)) atomicOr(I.status, ST_NAN);
-      if (t == 0) {
-        I.st->sigma = cj;
-        I.st->eps = eps_rel * cj;
+    constexpr bool team = COEF == COEF_ADAM_TEAM || COEF == COEF_OMP_TEAM;
+    if (member == 0) {
+      for (int l = threadIdx.x; l < t; l += kPassThreads) {
+        const float g = I.H[j + (long long)l * I.ldh];
+        I.G[l + (long long)t * I.ldg] = g;
+        I.G[t + (long long)l * I.ldg] = g;
       }
-      I.st->lr = lr_rel * cj;   // step size follows the selected correlation
-      I.key[(t + 1) & 1] = 0ull;   // slot of the next scan
+      if (threadIdx.x == 0) {
+        I.G[t + (long long)t * I.ldg] = I.dg[j];
+        I.b[t] = I.c0[j];
+        I.support[t] = j;
+        I.bitmap[j >> 5] |= (1u << (j & 31));
+        *I.nsel = t + 1;
+        const float cj = key_value(key);
+        if (!(cj <= 3.402823466e38f)) atomicOr(I.status, ST_NAN);
+        if (t == 0) {
+          I.st->sigma = cj;
+          I.st->eps = eps_rel * cj;
+        }
+        I.st->lr = lr_rel * cj;   // step size follows the selected correlation
+        I.key[(t + 1) & 1] = 0ull;   // slot of the next scan
+      }
+    }
+    if (team) {
+      // members take the new Gram row / column and b_t from H, dg and c0
+      if (COEF == COEF_OMP_TEAM)
+        omp_team_body(I, j, t, W, member, dsh);
+      else
+        adam_team_body(I, j, t, T, lr_rel * key_value(key), beta1, beta2, member, dsh);
+      team_retire(I, member);
+      return;
     }
     __syncthreads();
     if (COEF == COEF_ADAM_REG)
@@ -1198,7 +1476,7 @@ __global__ __launch_bounds__(kPassThreads) void coef_pass_kernel(
       omp_ginv_body(I, t, dsh, red, red2, false);
     return;
   }
-  const ScanTile tile = tiles[blockIdx.x - nact];
+  const ScanTile tile = tiles[blockIdx.x - nact * W];
   pass_tile_body<TA, LPA, 1>(insts[tile.inst], tile, t, dsh, wbest);
 }
 
@@ -1570,22 +1848,30 @@ hipError_t launch_ypass(int bf16, int lpa, const Inst* d, const ScanTile* tiles,
 }
 
 template <typename TA, int LPA>
-static hipError_t coef_pass_lpa(int coef, const Inst* dc, int nact, const Inst* d,
+static hipError_t coef_pass_lpa(int coef, const Inst* dc, int nact, int W, const Inst* d,
                                 const ScanTile* tiles, int ntiles, int t, int T, float b1,
                                 float b2, float lr_rel, float eps_rel, size_t lds,
                                 hipStream_t s) {
-  const dim3 g(nact + ntiles), b(kPassThreads);
+  const dim3 g(nact * W + ntiles), b(kPassThreads);
   switch (coef) {
     case COEF_ADAM_REG:
-      CLOMP_LAUNCH((coef_pass_kernel<TA, LPA, COEF_ADAM_REG>), g, b, lds, s, dc, nact, d,
+      CLOMP_LAUNCH((coef_pass_kernel<TA, LPA, COEF_ADAM_REG>), g, b, lds, s, dc, nact, W, d,
                          tiles, t, T, b1, b2, lr_rel, eps_rel);
       break;
     case COEF_ADAM_GLOBAL:
-      CLOMP_LAUNCH((coef_pass_kernel<TA, LPA, COEF_ADAM_GLOBAL>), g, b, lds, s, dc, nact, d,
+      CLOMP_LAUNCH((coef_pass_kernel<TA, LPA, COEF_ADAM_GLOBAL>), g, b, lds, s, dc, nact, W, d,
+                         tiles, t, T, b1, b2, lr_rel, eps_rel);
+      break;
+    case COEF_ADAM_TEAM:
+      CLOMP_LAUNCH((coef_pass_kernel<TA, LPA, COEF_ADAM_TEAM>), g, b, lds, s, dc, nact, W, d,
+                         tiles, t, T, b1, b2, lr_rel, eps_rel);
+      break;
+    case COEF_OMP_TEAM:
+      CLOMP_LAUNCH((coef_pass_kernel<TA, LPA, COEF_OMP_TEAM>), g, b, lds, s, dc, nact, W, d,
                          tiles, t, T, b1, b2, lr_rel, eps_rel);
       break;
     default:
-      CLOMP_LAUNCH((coef_pass_kernel<TA, LPA, COEF_OMP>), g, b, lds, s, dc, nact, d, tiles,
+      CLOMP_LAUNCH((coef_pass_kernel<TA, LPA, COEF_OMP>), g, b, lds, s, dc, nact, W, d, tiles,
                          t, T, b1, b2, lr_rel, eps_rel);
       break;
   }
@@ -1593,26 +1879,32 @@ static hipError_t coef_pass_lpa(int coef, const Inst* dc, int nact, const Inst* 
 }
 
 template <typename TA>
-static hipError_t coef_pass_dispatch(int lpa, int coef, const Inst* dc, int nact, const Inst* d,
-                                     const ScanTile* tiles, int ntiles, int t, int T, float b1,
-                                     float b2, float lr, float ep, size_t lds, hipStream_t s) {
+static hipError_t coef_pass_dispatch(int lpa, int coef, const Inst* dc, int nact, int W,
+                                     const Inst* d, const ScanTile* tiles, int ntiles, int t,
+                                     int T, float b1, float b2, float lr, float ep, size_t lds,
+                                     hipStream_t s) {
   switch (lpa) {
-    case 4: return coef_pass_lpa<TA, 4>(coef, dc, nact, d, tiles, ntiles, t, T, b1, b2, lr, ep, lds, s);
-    case 8: return coef_pass_lpa<TA, 8>(coef, dc, nact, d, tiles, ntiles, t, T, b1, b2, lr, ep, lds, s);
-    case 16: return coef_pass_lpa<TA, 16>(coef, dc, nact, d, tiles, ntiles, t, T, b1, b2, lr, ep, lds, s);
-    case 32: return coef_pass_lpa<TA, 32>(coef, dc, nact, d, tiles, ntiles, t, T, b1, b2, lr, ep, lds, s);
-    default: return coef_pass_lpa<TA, 64>(coef, dc, nact, d, tiles, ntiles, t, T, b1, b2, lr, ep, lds, s);
+    case 4: return coef_pass_lpa<TA, 4>(coef, dc, nact, W, d, tiles, ntiles, t, T, b1, b2, lr, ep, lds, s);
+    case 8: return coef_pass_lpa<TA, 8>(coef, dc, nact, W, d, tiles, ntiles, t, T, b1, b2, lr, ep, lds, s);
+    case 16: return coef_pass_lpa<TA, 16>(coef, dc, nact, W, d, tiles, ntiles, t, T, b1, b2, lr, ep, lds, s);
+    case 32: return coef_pass_lpa<TA, 32>(coef, dc, nact, W, d, tiles, ntiles, t, T, b1, b2, lr, ep, lds, s);
+    default: return coef_pass_lpa<TA, 64>(coef, dc, nact, W, d, tiles, ntiles, t, T, b1, b2, lr, ep, lds, s);
   }
 }
 
-hipError_t launch_coef_pass(int bf16, int lpa, int omp, const Inst* dc, int nact, const Inst* d,
-                            const ScanTile* tiles, int ntiles, int t, int T, float beta1,
-                            float beta2, float lr_rel, float eps_rel, size_t lds, hipStream_t s) {
+hipError_t launch_coef_pass(int bf16, int lpa, int omp, const Inst* dc, int nact, int W,
+                            const Inst* d, const ScanTile* tiles, int ntiles, int t, int T,
+                            float beta1, float beta2, float lr_rel, float eps_rel, size_t lds,
+                            hipStream_t s) {
   if (nact + ntiles <= 0) return nothing_to_launch(s);
-  const int coef = omp ? COEF_OMP : (t + 1 <= kRegRows ? COEF_ADAM_REG : COEF_ADAM_GLOBAL);
-  return bf16 ? coef_pass_dispatch<uint16_t>(lpa, coef, dc, nact, d, tiles, ntiles, t, T, beta1,
-                                             beta2, lr_rel, eps_rel, lds, s)
-              : coef_pass_dispatch<float>(lpa, coef, dc, nact, d, tiles, ntiles, t, T, beta1,
+  // a team needs t >= 1: at t = 0 the step size and eps are set in the launch
+  if (W < 1 || W > kTeamMax || (W > 1 && (t < 1 || W * kTeamRows < t + 1)))
+    return hipErrorInvalidValue;
+  const int coef = W > 1 ? (omp ? COEF_OMP_TEAM : COEF_ADAM_TEAM)
+                         : omp ? COEF_OMP : (t + 1 <= kRegRows ? COEF_ADAM_REG : COEF_ADAM_GLOBAL);
+  return bf16 ? coef_pass_dispatch<uint16_t>(lpa, coef, dc, nact, W, d, tiles, ntiles, t, T,
+                                             beta1, beta2, lr_rel, eps_rel, lds, s)
+              : coef_pass_dispatch<float>(lpa, coef, dc, nact, W, d, tiles, ntiles, t, T, beta1,
                                           beta2, lr_rel, eps_rel, lds, s);
 }
 
@@ -1631,7 +1923,9 @@ hipError_t set_max_lds_pass(size_t bytes) {
       (const void*)ypass_kernel<uint16_t, 32>, (const void*)ypass_kernel<uint16_t, 64>,
 #define CP(TA, L) (const void*)coef_pass_kernel<TA, L, COEF_ADAM_REG>, \
                   (const void*)coef_pass_kernel<TA, L, COEF_ADAM_GLOBAL>, \
-                  (const void*)coef_pass_kernel<TA, L, COEF_OMP>
+                  (const void*)coef_pass_kernel<TA, L, COEF_OMP>, \
+                  (const void*)coef_pass_kernel<TA, L, COEF_ADAM_TEAM>, \
+                  (const void*)coef_pass_kernel<TA, L, COEF_OMP_TEAM>
       CP(float, 4), CP(float, 8), CP(float, 16), CP(float, 32), CP(float, 64),
       CP(uint16_t, 4), CP(uint16_t, 8), CP(uint16_t, 16), CP(uint16_t, 32), CP(uint16_t, 64)
 #undef CP

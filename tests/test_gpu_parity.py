@@ -128,6 +128,37 @@ def test_uneven_bf16_batch_with_master(solvers, method):
     assert ident >= 1     # the oracle calls 7 (CLOMP) / 3 (OMP) of these well separated
 
 
+@pytest.mark.parametrize("method", ["clomp", "omp"])
+def test_coefficient_teams(method):
+    """Correlation-update schedule with the coefficient update split over a
+    team of workgroups once the support exceeds 16 atoms (team_min_rows = 16):
+    up to ceil(80 / 16) = 5 members per signal, four signals per launch.
+    Checked against the oracle and against the single-workgroup update."""
+    sigs = [W.single_small(200 + i, n=2048, m=384, k=80) for i in range(4)]
+    team = C.Solver(0, method=method, flags=C.FLAG_CORR_FLOW)
+    team.set_tuning(team_min_rows=16)
+    assert team.get_tuning()["team_min_rows"] == 16
+    single = C.Solver(0, method=method, flags=C.FLAG_CORR_FLOW)
+    out = team.solve_batch(_items(sigs))
+    out1 = single.solve_batch(_items(sigs))
+    torch.cuda.synchronize()
+    ident = 0
+    for i, s in enumerate(sigs):
+        assert int(out.status[i]) == 0 and int(out.n_selected[i]) == s.k
+        res = oracle_final_x(method, s.A, s.y, s.k)
+        kind = compare(out, i, res, s.A, s.y, delta=FP32_DELTA, u=FP32_U, method=method,
+                       A_sel=s.A, k=s.k, tol_x=1e-5)
+        if kind == "identical":
+            ident += 1
+            assert out1.support[i].tolist() == out.support[i].tolist()
+            assert rel_err(out.x[i].cpu().numpy().astype(np.float64),
+                           out1.x[i].cpu().numpy().astype(np.float64)) <= 1e-5
+    print(f"{method} teams: identical {ident}/{len(sigs)}")
+    assert ident >= 2
+    team.close()
+    single.close()
+
+
 def test_edge_cases(solvers):
     sol = solvers["clomp"]
     base = W.single_small(7)
