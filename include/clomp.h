@@ -63,8 +63,11 @@ typedef enum {
 #define CLOMP_FLAG_GRAPH 1u          /* capture the launch sequence of a batch
                                         shape into a HIP graph and replay it on
                                         later calls with the same shape        */
-#define CLOMP_FLAG_NO_FUSED_SMALL 2u /* never use the one-workgroup-per-signal
-                                        kernel (for testing the general path)  */
+#define CLOMP_FLAG_NO_FUSED_SMALL 2u /* never use the fused small-signal
+                                        loop (one workgroup runs a signal's
+                                        whole greedy loop with its dictionary
+                                        in LDS when k_eff <= 64 and it fits);
+                                        for testing the iterated kernels      */
 #define CLOMP_FLAG_AUTOTUNE 4u       /* time the scan-kernel candidates on the
                                         first call for each size class         */
 #define CLOMP_FLAG_PROFILE 8u        /* record HIP events around every phase
@@ -217,7 +220,9 @@ clomp_status_t clomp_grad(clomp_handle_t h, int32_t n, int32_t m, int64_t lda,
  * c0 - H s and argmax), 1 gram (selection record and new Gram column),
  * 2 coef (Adam or the OMP update), 3 resid (r = y - A_S s), 4 refine (QR or
  * CGLS), 5 norm (FP64 residual norm and output scatter), 6 init, 7 pass
- * (correlation schedule: coefficient update fused with the pass over A).
+ * (correlation schedule: coefficient update fused with the pass over A),
+ * 8 fused (the whole greedy loop of the signals served by the fused
+ * small-signal kernel).
  *   ms[p]        summed device time between HIP events recorded on the launch
  *                stream immediately before and after each launch of phase p
  *   launches[p]  number of launches of phase p
@@ -226,13 +231,16 @@ clomp_status_t clomp_grad(clomp_handle_t h, int32_t n, int32_t m, int64_t lda,
  *                a scan of H at iteration t
  *   pass_bytes   algorithmic bytes of phase-7 launches: m*n*elem + 4n per
  *                active instance (the bulk columns and the new column of H)
+ *   fused_bytes  algorithmic bytes of phase-8 launches: m*n*elem + 4m per
+ *                signal (its dictionary and y, each read once)
  * Synchronises on the recorded events.  Errors: INVALID_ARGUMENT, DEVICE_ERROR.
  */
 typedef struct {
-  double ms[8];
-  int64_t launches[8];
+  double ms[12];        /* phases 0..8; 9..11 reserved (zero) */
+  int64_t launches[12];
   double scan_bytes;
   double pass_bytes;
+  double fused_bytes;
 } clomp_profile_t;
 
 clomp_status_t clomp_profile_read(clomp_handle_t h, clomp_profile_t* out /*host*/);

@@ -13,6 +13,8 @@ import ctypes
 import os
 from dataclasses import dataclass
 
+import numpy as np
+
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -23,7 +25,7 @@ METHOD_CLOMP, METHOD_OMP = 0, 1
 ST_NAN, ST_K_CAPPED, ST_ZERO_Y, ST_REFINE_INACCURATE, ST_WATCHDOG = 1, 2, 4, 8, 32
 FLAG_GRAPH, FLAG_NO_FUSED_SMALL, FLAG_AUTOTUNE, FLAG_PROFILE = 1, 2, 4, 8
 FLAG_RESIDUAL_FLOW, FLAG_CORR_FLOW = 16, 32
-PHASES = ("scan", "gram", "coef", "resid", "refine", "norm", "init", "pass")
+PHASES = ("scan", "gram", "coef", "resid", "refine", "norm", "init", "pass", "fused")
 
 STATUS_NAMES = {0: "CLOMP_OK", 1: "CLOMP_INVALID_ARGUMENT", 2: "CLOMP_OUT_OF_MEMORY",
                 3: "CLOMP_DEVICE_ERROR", 4: "CLOMP_NOT_SUPPORTED"}
@@ -47,14 +49,34 @@ class Instance(ctypes.Structure):
                 ("status", ctypes.c_void_p)]
 
 
+# numpy view of clomp_instance_t, for packing large batches without a
+# per-field ctypes assignment
+INSTANCE_NP = np.dtype([(name, np.int32 if ct is ctypes.c_int32 else
+                         np.int64 if ct is ctypes.c_int64 else np.uint64)
+                        for name, ct in Instance._fields_])
+assert INSTANCE_NP.itemsize == ctypes.sizeof(Instance)
+
+
 class Profile(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_int64 * 8),
-                ("scan_bytes", ctypes.c_double), ("pass_bytes", ctypes.c_double)]
+    _fields_ = [("ms", ctypes.c_double * 12), ("launches", ctypes.c_int64 * 12),
+                ("scan_bytes", ctypes.c_double), ("pass_bytes", ctypes.c_double),
+                ("fused_bytes", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):
     _fields_ = [("scan_tile_kb", ctypes.c_int32), ("pass_tile_kb", ctypes.c_int32),
                 ("team_min_rows", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
+@dataclass
+class PreparedBatch:
+    arr: np.ndarray          # packed clomp_instance_t descriptors
+    count: int
+    dtype: int
+    result: "BatchResult"
+    items: list              # inputs, kept alive with the batch
+    stream: object
+    outputs: tuple
 
 
 class ClompError(RuntimeError):
@@ -206,56 +228,83 @@ class Solver:
                "clomp_profile_read")
         return {"ms": {PHASES[i]: p.ms[i] for i in range(len(PHASES))},
                 "launches": {PHASES[i]: int(p.launches[i]) for i in range(len(PHASES))},
-                "scan_bytes": p.scan_bytes, "pass_bytes": p.pass_bytes}
+                "scan_bytes": p.scan_bytes, "pass_bytes": p.pass_bytes,
+                "fused_bytes": p.fused_bytes}
 
     # ------------------------------------------------------------------ solve
-    def solve_batch(self, items, stream=None):
-        """items: list of dicts with keys At (n, lda) float32|bfloat16 cuda tensor,
-        m, y (m,) float32, k, optional At_master (n, lda_master) float32.
-        Outputs are allocated here and returned as views of packed tensors."""
+    def prepare(self, items, stream=None):
+        """Pack the descriptors of a batch and allocate its outputs once (on the
+        launch stream).  items: list of dicts with keys At (n, lda) float32 |
+        bfloat16 cuda tensor, m, y (m,) float32, k, optional At_master
+        (n, lda_master) float32.  `run` launches the batch; every run rewrites
+        the same outputs."""
         count = len(items)
-        if count == 0:
-            return BatchResult([], [], *(torch.empty(0, device=self.device),) * 3)
-        dt = dtype_code(items[0]["At"])
-        ns = [int(it["At"].shape[0]) for it in items]
-        ks = [int(it["k"]) for it in items]
+        dt = dtype_code(items[0]["At"]) if count else 0
+        if any(dtype_code(it["At"]) != dt for it in items):
+            raise ClompError("all instances of a batch must share the bulk dtype")
         dev = self.device
-        x_all = torch.empty(sum(ns), dtype=torch.float32, device=dev)
-        sup_all = torch.empty(sum(ks), dtype=torch.int32, device=dev)
-        nsel = torch.empty(count, dtype=torch.int32, device=dev)
-        rnorm = torch.empty(count, dtype=torch.float64, device=dev)
-        status = torch.empty(count, dtype=torch.int32, device=dev)
-        arr = (Instance * count)()
-        xs, sups = [], []
-        xo = so = 0
-        for i, it in enumerate(items):
-            At = it["At"]
-            if dtype_code(At) != dt:
-                raise ClompError("all instances of a batch must share the bulk dtype")
-            Am = it.get("At_master")
-            d = arr[i]
-            d.n, d.m, d.k = ns[i], int(it["m"]), ks[i]
-            d.lda = int(At.stride(0))
-            d.lda_master = int(Am.stride(0)) if Am is not None else 0
-            d.A = At.data_ptr()
-            d.A_master = Am.data_ptr() if Am is not None else None
-            d.y = it["y"].data_ptr()
-            xs.append(x_all[xo:xo + ns[i]])
-            sups.append(sup_all[so:so + ks[i]])
-            d.x = x_all.data_ptr() + 4 * xo
-            d.support = sup_all.data_ptr() + 4 * so
-            d.n_selected = nsel.data_ptr() + 4 * i
-            d.resid_norm = rnorm.data_ptr() + 8 * i
-            d.status = status.data_ptr() + 4 * i
-            xo += ns[i]
-            so += ks[i]
         st = stream if stream is not None else torch.cuda.current_stream(dev)
-        rc = load_library().clomp_solve_batch(self._h, arr, count, dt,
-                                              ctypes.c_void_p(st.cuda_stream))
+        ns = np.fromiter((it["At"].shape[0] for it in items), np.int64, count)
+        ks = np.fromiter((it["k"] for it in items), np.int64, count)
+        xoff = np.concatenate(([0], np.cumsum(ns))).astype(np.int64)
+        soff = np.concatenate(([0], np.cumsum(ks))).astype(np.int64)
+        with torch.cuda.stream(st):
+            x_all = torch.empty(int(xoff[-1]), dtype=torch.float32, device=dev)
+            sup_all = torch.empty(int(soff[-1]), dtype=torch.int32, device=dev)
+            nsel = torch.empty(count, dtype=torch.int32, device=dev)
+            rnorm = torch.empty(count, dtype=torch.float64, device=dev)
+            status = torch.empty(count, dtype=torch.int32, device=dev)
+        arr = np.zeros(count, dtype=INSTANCE_NP)
+        if count:
+            arr["n"], arr["k"] = ns, ks
+            arr["m"] = [int(it["m"]) for it in items]
+            arr["lda"] = [it["At"].stride(0) for it in items]
+            arr["A"] = [it["At"].data_ptr() for it in items]
+            masters = [it.get("At_master") for it in items]
+            arr["lda_master"] = [a.stride(0) if a is not None else 0 for a in masters]
+            arr["A_master"] = [a.data_ptr() if a is not None else 0 for a in masters]
+            arr["y"] = [it["y"].data_ptr() for it in items]
+            arr["x"] = x_all.data_ptr() + 4 * xoff[:-1]
+            arr["support"] = sup_all.data_ptr() + 4 * soff[:-1]
+            idx = np.arange(count, dtype=np.int64)
+            arr["n_selected"] = nsel.data_ptr() + 4 * idx
+            arr["resid_norm"] = rnorm.data_ptr() + 8 * idx
+            arr["status"] = status.data_ptr() + 4 * idx
+        xs = [x_all[a:b] for a, b in zip(xoff[:-1].tolist(), xoff[1:].tolist())]
+        sups = [sup_all[a:b] for a, b in zip(soff[:-1].tolist(), soff[1:].tolist())]
+        return PreparedBatch(arr, count, dt, BatchResult(xs, sups, nsel, rnorm, status),
+                             list(items), st, (x_all, sup_all, nsel, rnorm, status))
+
+    def run(self, prep, stream=None):
+        """Launch a prepared batch on `stream` (default: the stream it was
+        prepared on); returns its BatchResult (the prepared output tensors)."""
+        dev = self.device
+        st = stream if stream is not None else prep.stream
+        if prep.count == 0:
+            return prep.result
+        rc = load_library().clomp_solve_batch(
+            self._h, prep.arr.ctypes.data_as(ctypes.POINTER(Instance)), prep.count, prep.dtype,
+            ctypes.c_void_p(st.cuda_stream))
         _check(self._h, rc, "clomp_solve_batch")
-        # keep inputs alive until the queued work is done
-        self._keep = items
-        return BatchResult(xs, sups, nsel, rnorm, status)
+        if st != torch.cuda.current_stream(dev):
+            # tensors the caller may drop must outlive the queued work on `st`
+            seen = set()
+            for it in prep.items:
+                for key in ("At", "At_master", "y"):
+                    t = it.get(key)
+                    if t is not None and id(t) not in seen:
+                        seen.add(id(t))
+                        t.record_stream(st)
+            for t in prep.outputs:
+                t.record_stream(st)
+        self._keep = prep
+        return prep.result
+
+    def solve_batch(self, items, stream=None):
+        """prepare + run for a one-off batch."""
+        if len(items) == 0:
+            return BatchResult([], [], *(torch.empty(0, device=self.device),) * 3)
+        return self.run(self.prepare(items, stream), stream)
 
     def solve(self, At, m, y, k, At_master=None, stream=None):
         r = self.solve_batch([dict(At=At, m=m, y=y, k=k, At_master=At_master)], stream)

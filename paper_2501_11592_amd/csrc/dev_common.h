@@ -25,6 +25,17 @@ namespace clomp {
 constexpr int kBlock = 256;     // threads per workgroup for every solver kernel
 constexpr int kTeamRows = 16;   // coefficient rows per team member
 constexpr int kTeamMax = 128;   // team members per signal (2048 rows)
+constexpr int kSmallMaxK = 64;  // fused small-signal loop: k_eff bound (one wave)
+
+// Fused small-signal loop: row stride of the LDS Gram / inverse-Gram matrix
+// and the dynamic LDS of one signal (G | A as FP32, odd leading dimension |
+// r | y | selection bitmap).
+__host__ __device__ inline int small_ldq(int ke) { return ((ke + 3) & ~3) + 4; }
+__host__ __device__ inline size_t small_lds_bytes(int n, int m, int ke) {
+  const size_t al = ((size_t)n * (size_t)(m | 1) + 3) & ~(size_t)3;
+  const size_t m4 = (size_t)((m + 3) & ~3);
+  return 4 * ((size_t)ke * small_ldq(ke) + al + 2 * m4 + (size_t)((n + 31) / 32));
+}
 constexpr int kWaves = kBlock / 64;
 
 struct InstState {

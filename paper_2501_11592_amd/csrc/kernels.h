@@ -36,6 +36,13 @@ hipError_t set_max_lds(size_t bytes);
 // Events the next single-kernel launch records around itself (profiling).
 void set_launch_events(hipEvent_t start, hipEvent_t stop);
 
+// Fused greedy loop of the signals list[0..count): one 256-thread workgroup
+// per signal with its dictionary in LDS (k_eff <= kSmallMaxK, dynamic LDS of
+// small_lds_bytes for the largest signal).
+hipError_t launch_small(int bf16, int omp, const Inst* d, const int* list, int count, int T,
+                        float beta1, float beta2, float lr_rel, float eps_rel, size_t lds,
+                        hipStream_t s);
+
 // correlation-update schedule (few large signals)
 hipError_t launch_ypass(int bf16, int lpa, const Inst* d, const ScanTile* tiles, int ntiles,
                         size_t lds, hipStream_t s);

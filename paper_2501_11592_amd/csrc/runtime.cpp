@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -70,6 +71,10 @@ struct Plan {
   size_t qr_lds = 0;
   int kmax = 0, cg_tmax = 0, cg_mpad_max = 0, cg_lpa = 64;
   bool hflow = false;                 // correlation-update schedule
+  int nbig = 0;                       // sorted instances [0, nbig) use the iterated kernels;
+                                      // [nbig, count) run the fused small-signal loop
+  std::vector<int> small_list;
+  size_t small_lds = 0, off_small = 0;
   std::vector<ScanTile> htiles;       // pass tiles (1024-thread workgroups)
   std::vector<ScanTile> ctiles;       // 64-atom tiles of the H scan
   size_t off_htiles = 0, off_ctiles = 0;
@@ -105,13 +110,14 @@ struct clomp_ctx {
   size_t ev_used = 0;
   struct Rec { int phase; hipEvent_t a, b; };
   std::vector<Rec> recs;
-  double scan_bytes = 0.0, pass_bytes = 0.0;
+  double scan_bytes = 0.0, pass_bytes = 0.0, fused_bytes = 0.0;
   bool profiling = false;
   bool pass_lds_ok = false;           // dynamic-LDS ceiling raised for pass kernels
   int scan_tile_kb = kScanTargetKB;
   int pass_tile_kb = kPassTargetKB;
   int team_min_rows = 256;            // larger supports use coefficient teams
-  std::map<std::string, int> tuned;   // autotuned pass tile per size class
+  int last_scan_kb = kScanTargetKB, last_pass_kb = kPassTargetKB;   // of the last solve
+  std::map<std::string, int> tuned;   // autotuned tile size per size class
 };
 
 namespace {
@@ -203,7 +209,8 @@ int pick_lpa(int m, int vw) {
 }
 
 // Build the plan (host tables + workspace layout) for one batch.
-void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16, Plan& P) {
+void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16, Plan& P,
+                int scan_kb, int pass_kb) {
   const clomp_params_t& prm = h->params;
   const bool omp = prm.method == CLOMP_METHOD_OMP;
   const int vw = bf16 ? 8 : 4;
@@ -213,22 +220,33 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
   // order: by class (lpa desc), then k_eff desc, then input index
   std::vector<int> order(count);
   std::vector<int> lpa(count), keff(count);
+  std::vector<char> fused(count, 0);
+  const bool allow_fused = !(prm.flags & CLOMP_FLAG_NO_FUSED_SMALL);
   for (int i = 0; i < count; ++i) {
     order[i] = i;
     lpa[i] = pick_lpa(inst[i].m, vw);
     keff[i] = std::min(inst[i].k, std::min(inst[i].m, inst[i].n));
+    // fused loop: k_eff within one wave and the signal's LDS image within the
+    // ceiling next to the kernel's 1.3 KB of static LDS
+    fused[i] = allow_fused && keff[i] <= kSmallMaxK &&
+               small_lds_bytes(inst[i].n, inst[i].m, keff[i]) + 2048 <= (size_t)h->lds_limit;
   }
+  // fused signals last; the rest by lane-width class, then k_eff descending
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (fused[a] != fused[b]) return fused[a] < fused[b];
     if (lpa[a] != lpa[b]) return lpa[a] > lpa[b];
     return keff[a] > keff[b];
   });
+  P.nbig = 0;
+  while (P.nbig < count && !fused[order[P.nbig]]) ++P.nbig;
   const int qr_limit_floats = ((int)std::min<size_t>((size_t)h->lds_limit, 96 * 1024) - 1024) / 4;
   {
     // correlation-update schedule: few signals, H within budget, the pass
     // kernel's staged vector within LDS next to its 33 KB of static LDS
     size_t hbytes = 0;
     int mpad_max = 0;
-    for (int i = 0; i < count; ++i) {
+    for (int s = 0; s < P.nbig; ++s) {
+      const int i = order[s];
       hbytes += sizeof(float) * (size_t)round_up_int(inst[i].n, 64) * keff[i];
       mpad_max = std::max(mpad_max, round_up_int(inst[i].m, 8));
     }
@@ -236,17 +254,17 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
                       (size_t)mpad_max * 4 + 34 * 1024 <= (size_t)h->lds_limit &&
                       hbytes <= (size_t)16 << 30;
     const uint32_t fl = prm.flags;
-    P.hflow = fits && !(fl & CLOMP_FLAG_RESIDUAL_FLOW) &&
-              ((fl & CLOMP_FLAG_CORR_FLOW) || count <= 8);
+    P.hflow = P.nbig > 0 && fits && !(fl & CLOMP_FLAG_RESIDUAL_FLOW) &&
+              ((fl & CLOMP_FLAG_CORR_FLOW) || P.nbig <= 8);
   }
-  snprintf(sigbuf, sizeof sigbuf, "h%d;", (int)P.hflow);
+  snprintf(sigbuf, sizeof sigbuf, "h%d;f%d;", (int)P.hflow, count - P.nbig);
   P.sig += sigbuf;
   P.insts.resize(count);
   P.keff.resize(count);
   P.kmax = 0;
   size_t ws = 0;
   snprintf(sigbuf, sizeof sigbuf, "d%d;m%d;T%d;s%d;p%d;w%d;", bf16, prm.method,
-           prm.inner_steps, h->scan_tile_kb, h->pass_tile_kb, h->team_min_rows);
+           prm.inner_steps, scan_kb, pass_kb, h->team_min_rows);
   P.sig += sigbuf;
   for (int s = 0; s < count; ++s) {
     const int i = order[s];
@@ -289,7 +307,8 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     const size_t o_L = omp ? take(sizeof(float) * (size_t)d.k_eff * d.ldg) : 0;
     const size_t o_cg = use_qr ? 0 : take(sizeof(float) * (3 * (size_t)d.m_pad + 3 * d.k_eff));
     size_t o_c0 = 0, o_H = 0, o_dg = 0, o_team = 0;
-    if (P.hflow) {
+    const bool hf = P.hflow && s < P.nbig;
+    if (hf) {
       d.ldh = round_up_int(d.n, 256);
       o_c0 = take(sizeof(float) * d.ldh);
       o_dg = take(sizeof(float) * d.ldh);
@@ -312,10 +331,10 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     d.z = (float*)(o_z + 1);
     d.Linv = omp ? (float*)(o_L + 1) : nullptr;
     d.cg = use_qr ? nullptr : (float*)(o_cg + 1);
-    d.c0 = P.hflow ? (float*)(o_c0 + 1) : nullptr;
-    d.dg = P.hflow ? (float*)(o_dg + 1) : nullptr;
-    d.team = P.hflow ? (unsigned long long*)(o_team + 1) : nullptr;
-    d.H = P.hflow ? (float*)(o_H + 1) : nullptr;
+    d.c0 = hf ? (float*)(o_c0 + 1) : nullptr;
+    d.dg = hf ? (float*)(o_dg + 1) : nullptr;
+    d.team = hf ? (unsigned long long*)(o_team + 1) : nullptr;
+    d.H = hf ? (float*)(o_H + 1) : nullptr;
     d.npart = (double*)(o_np + 1);
     d.qpart = (float*)(o_qp + 1);
     d.key = (unsigned long long*)(o_key + 1);
@@ -334,11 +353,11 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
   P.classes.clear();
   P.tiles.clear();
   P.rows.clear();
-  for (int s = 0; s < count;) {
+  for (int s = 0; s < P.nbig;) {
     Class c;
     c.lpa = lpa[order[s]];
     c.i0 = s;
-    while (s < count && lpa[order[s]] == c.lpa) ++s;
+    while (s < P.nbig && lpa[order[s]] == c.lpa) ++s;
     c.i1 = s;
     c.tile_prefix.push_back(0);
     c.row_prefix.push_back(0);
@@ -348,7 +367,7 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     for (int q = c.i0; q < c.i1; ++q) {
       const Inst& d = P.insts[q];
       const size_t atom_bytes = (size_t)d.m_pad * esize;
-      int apg = (int)std::max<size_t>(1, (size_t)h->scan_tile_kb * 1024 / (atom_bytes * ng));
+      int apg = (int)std::max<size_t>(1, (size_t)scan_kb * 1024 / (atom_bytes * ng));
       const int apt = ng * apg;
       for (int j0 = 0; j0 < d.n; j0 += apt) P.tiles.push_back({q, j0, std::min(d.n, j0 + apt), 0});
       c.tile_prefix.push_back((int)(P.tiles.size() - c.tile_off));
@@ -363,7 +382,7 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
           c.ctile_off = P.ctiles.size();
         }
         const int hng = kPassThreadsHost / c.lpa;
-        const int happ = (int)std::max<size_t>(1, (size_t)h->pass_tile_kb * 1024 / (atom_bytes * hng));
+        const int happ = (int)std::max<size_t>(1, (size_t)pass_kb * 1024 / (atom_bytes * hng));
         const int hapt = hng * happ;
         for (int j0 = 0; j0 < d.n; j0 += hapt)
           P.htiles.push_back({q, j0, std::min(d.n, j0 + hapt), 0});
@@ -384,6 +403,16 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
       c.nch = (nch * vw <= 64) ? nch : 0;   // at most 64 floats of r per lane
     }
     P.classes.push_back(std::move(c));
+  }
+  // fused signals: row tiles (for the norm) and the launch list
+  P.small_list.clear();
+  P.small_lds = 0;
+  for (int q = P.nbig; q < count; ++q) {
+    const Inst& d = P.insts[q];
+    for (int tt = 0; tt < d.n_rowtiles; ++tt)
+      P.rows.push_back({q, tt * 64, std::min(d.m, tt * 64 + 64), tt});
+    P.small_list.push_back(q);
+    P.small_lds = std::max(P.small_lds, small_lds_bytes(d.n, d.m, d.k_eff));
   }
   // refinement lists
   P.qr_list.clear();
@@ -424,6 +453,7 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
   P.off_cgrows = place(sizeof(RowTile) * P.cg_rows.size());
   P.off_htiles = place(sizeof(ScanTile) * P.htiles.size());
   P.off_ctiles = place(sizeof(ScanTile) * P.ctiles.size());
+  P.off_small = place(sizeof(int) * P.small_list.size());
   P.table_bytes = std::max<size_t>(off, kAlign);
 }
 
@@ -455,7 +485,9 @@ void drop_graphs(clomp_ctx* h) {
   h->graphs.clear();
 }
 
-enum Phase { PH_SCAN = 0, PH_GRAM, PH_COEF, PH_RESID, PH_REFINE, PH_NORM, PH_INIT, PH_PASS };
+enum Phase {
+  PH_SCAN = 0, PH_GRAM, PH_COEF, PH_RESID, PH_REFINE, PH_NORM, PH_INIT, PH_PASS, PH_FUSED
+};
 
 hipEvent_t pool_event(clomp_ctx* h) {
   if (h->ev_used == h->ev_pool.size()) {
@@ -586,6 +618,19 @@ clomp_status_t launch_all(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st)
     PhaseScope ps(h, PH_INIT, st, false);
     HIP_TRY(launch_init(d_insts, count, st), "init");
   }
+  if (!P.small_list.empty()) {
+    const int* d_small = reinterpret_cast<const int*>(tb + P.off_small);
+    PhaseScope ps(h, PH_FUSED, st);
+    HIP_TRY(launch_small(bf16, omp, d_insts, d_small, (int)P.small_list.size(),
+                         prm.inner_steps, prm.beta1, prm.beta2, prm.lr_rel, prm.eps_rel,
+                         P.small_lds, st),
+            "small");
+    if (h->profiling) {
+      const double esz = bf16 ? 2.0 : 4.0;
+      for (int q : P.small_list)
+        h->fused_bytes += (double)P.insts[q].m * P.insts[q].n * esz + 4.0 * P.insts[q].m;
+    }
+  }
   if (P.hflow) {
     clomp_status_t hs = launch_hflow(h, P, bf16, st);
     if (hs != CLOMP_OK) return hs;
@@ -678,6 +723,170 @@ clomp_status_t launch_all(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st)
   HIP_TRY(launch_norm(d_insts, d_rows, (int)P.rows.size(), P.kmax, st), "norm");
   HIP_TRY(launch_finalize(d_insts, count, ncg > 0, st), "finalize");
   return CLOMP_OK;
+}
+
+// Workspace (grow-only; growth invalidates captured graphs), descriptors
+// rebased onto it, and the descriptor / tile tables uploaded on `st` through
+// pinned staging.
+clomp_status_t stage_plan(clomp_ctx* h, Plan& P, hipStream_t st) {
+  clomp_status_t s = CLOMP_OK;
+  // workspace and tables (grow-only; growth invalidates captured graphs)
+  bool g1 = false, g2 = false;
+  if ((s = ensure(h, h->ws, P.ws_bytes, &g1)) != CLOMP_OK) return s;
+  if ((s = ensure(h, h->tables, P.table_bytes, &g2)) != CLOMP_OK) return s;
+  if (g1 || g2) drop_graphs(h);
+  // rebase workspace offsets
+  char* wsb = reinterpret_cast<char*>(h->ws.p);
+  for (Inst& d : P.insts) {
+    auto rb = [&](auto*& ptr) {
+      if (ptr) ptr = reinterpret_cast<std::remove_reference_t<decltype(ptr)>>(
+                   wsb + (reinterpret_cast<uintptr_t>(ptr) - 1));
+    };
+    rb(d.r); rb(d.G); rb(d.b); rb(d.s); rb(d.mo); rb(d.ve); rb(d.xf); rb(d.z);
+    rb(d.Linv); rb(d.cg); rb(d.c0); rb(d.dg); rb(d.H); rb(d.team); rb(d.npart);
+    rb(d.qpart); rb(d.key);
+    rb(d.bitmap);
+    rb(d.st);
+  }
+  // stage tables in pinned memory and upload on the stream
+  if (h->pinned_bytes < P.table_bytes) {
+    if (h->pinned) {
+      HIP_TRY(hipEventSynchronize(h->staging_free), "hipEventSynchronize");
+      (void)hipHostFree(h->pinned);
+      h->pinned = nullptr;
+    }
+    const size_t want = align_up(P.table_bytes * 2, 1 << 16);
+    if (hipHostMalloc(&h->pinned, want, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      h->pinned = nullptr;
+      h->pinned_bytes = 0;
+      return fail(h, CLOMP_OUT_OF_MEMORY, "pinned staging allocation failed");
+    }
+    h->pinned_bytes = want;
+  } else {
+    HIP_TRY(hipEventSynchronize(h->staging_free), "hipEventSynchronize");
+  }
+  char* hb = reinterpret_cast<char*>(h->pinned);
+  memcpy(hb + P.off_insts, P.insts.data(), sizeof(Inst) * P.insts.size());
+  if (!P.tiles.empty()) memcpy(hb + P.off_tiles, P.tiles.data(), sizeof(ScanTile) * P.tiles.size());
+  if (!P.rows.empty()) memcpy(hb + P.off_rows, P.rows.data(), sizeof(RowTile) * P.rows.size());
+  if (!P.qr_list.empty()) memcpy(hb + P.off_qr, P.qr_list.data(), sizeof(int) * P.qr_list.size());
+  if (!P.cg_list.empty()) memcpy(hb + P.off_cg, P.cg_list.data(), sizeof(int) * P.cg_list.size());
+  if (!P.cg_rows.empty())
+    memcpy(hb + P.off_cgrows, P.cg_rows.data(), sizeof(RowTile) * P.cg_rows.size());
+  if (!P.htiles.empty())
+    memcpy(hb + P.off_htiles, P.htiles.data(), sizeof(ScanTile) * P.htiles.size());
+  if (!P.ctiles.empty())
+    memcpy(hb + P.off_ctiles, P.ctiles.data(), sizeof(ScanTile) * P.ctiles.size());
+  if (!P.small_list.empty())
+    memcpy(hb + P.off_small, P.small_list.data(), sizeof(int) * P.small_list.size());
+  // the previous batch (possibly on another stream) must be done with the tables
+  if (h->have_work) HIP_TRY(hipStreamWaitEvent(st, h->work_done, 0), "hipStreamWaitEvent");
+  HIP_TRY(hipMemcpyAsync(h->tables.p, hb, P.table_bytes, hipMemcpyHostToDevice, st),
+          "upload tables");
+  HIP_TRY(hipEventRecord(h->staging_free, st), "hipEventRecord");
+
+  return CLOMP_OK;
+}
+
+// Autotuning (CLOMP_FLAG_AUTOTUNE): for each candidate tile size, the plan of
+// this batch is staged and its hot kernel is timed on the batch's own data -
+// the fused pass of iteration 0 (correlation schedule, after the first pass
+// has chosen the atom) or the scan of iteration 0 (residual schedule).  The
+// probes leave only state that the solve's init launch resets.
+std::string tune_key(const Plan& P, int bf16, int method, double bulk_bytes) {
+  char buf[96];
+  snprintf(buf, sizeof buf, "d%d;h%d;o%d;b%d;n%d", bf16, (int)P.hflow, method,
+           (int)std::floor(2.0 * std::log2(std::max(bulk_bytes, 1.0))),
+           (int)std::floor(std::log2((double)std::max(P.nbig, 1))));
+  return buf;
+}
+
+clomp_status_t probe_launch(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st, bool timed) {
+  const clomp_params_t& prm = h->params;
+  const bool omp = prm.method == CLOMP_METHOD_OMP;
+  char* tb = reinterpret_cast<char*>(h->tables.p);
+  const Inst* d_insts = reinterpret_cast<const Inst*>(tb + P.off_insts);
+  for (const Class& c : P.classes) {
+    const int nall = c.i1 - c.i0;
+    if (P.hflow) {
+      const ScanTile* d_htiles = reinterpret_cast<const ScanTile*>(tb + P.off_htiles);
+      const size_t lds = (size_t)c.m_pad_max * sizeof(float);
+      if (!timed) {
+        HIP_TRY(launch_ypass(bf16, c.lpa, d_insts, d_htiles + c.htile_off, c.htile_prefix[nall],
+                             lds, st),
+                "ypass");
+        continue;
+      }
+      int nnext = 0;
+      while (nnext < nall && P.keff[c.i0 + nnext] > 1) ++nnext;
+      HIP_TRY(launch_coef_pass(bf16, c.lpa, omp, d_insts + c.i0, nall, 1, d_insts,
+                               d_htiles + c.htile_off, c.htile_prefix[nnext], 0, prm.inner_steps,
+                               prm.beta1, prm.beta2, prm.lr_rel, prm.eps_rel,
+                               std::max(lds, (omp ? 6 : 1) * sizeof(float)), st),
+              "coef_pass");
+    } else {
+      if (!timed) continue;
+      const ScanTile* d_tiles = reinterpret_cast<const ScanTile*>(tb + P.off_tiles);
+      const int lds_cap = (h->lds_limit - 1024) / 4;
+      const int r_lds = (c.m_pad_max <= lds_cap) ? c.m_pad_max : 0;
+      if (c.nch > 0)
+        HIP_TRY(launch_scan_reg(bf16, c.lpa, c.nch, d_insts, d_tiles + c.tile_off,
+                                c.tile_prefix[nall], 0, st),
+                "scan");
+      else
+        HIP_TRY(launch_scan(bf16, c.lpa, d_insts, d_tiles + c.tile_off, c.tile_prefix[nall], r_lds,
+                            0, st),
+                "scan");
+    }
+  }
+  return CLOMP_OK;
+}
+
+clomp_status_t autotune(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
+                        hipStream_t st, bool hflow, int scan_kb, int pass_kb, int* best_kb) {
+  static const int kScanCand[] = {32, 64, 128, 256, 512};
+  static const int kPassCand[] = {128, 256, 512, 1024, 2048};
+  const int* cand = hflow ? kPassCand : kScanCand;
+  const int ncand = 5;
+  hipEvent_t a = nullptr, b = nullptr;
+  HIP_TRY(hipEventCreate(&a), "hipEventCreate");
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return hip_fail(h, hipGetLastError(), "hipEventCreate");
+  }
+  const bool was_profiling = h->profiling;
+  h->profiling = false;
+  clomp_status_t s = CLOMP_OK;
+  float best = 0.f;
+  *best_kb = hflow ? pass_kb : scan_kb;
+  for (int q = 0; q < ncand && s == CLOMP_OK; ++q) {
+    Plan P;
+    build_plan(h, inst, count, bf16, P, hflow ? scan_kb : cand[q], hflow ? cand[q] : pass_kb);
+    if ((s = stage_plan(h, P, st)) != CLOMP_OK) break;
+    char* tb = reinterpret_cast<char*>(h->tables.p);
+    hipError_t e = launch_init(reinterpret_cast<const Inst*>(tb + P.off_insts), count, st);
+    if (e != hipSuccess) { s = hip_fail(h, e, "init"); break; }
+    if ((s = probe_launch(h, P, bf16, st, false)) != CLOMP_OK) break;
+    if ((s = probe_launch(h, P, bf16, st, true)) != CLOMP_OK) break;   // warm
+    if ((e = hipEventRecord(a, st)) != hipSuccess) { s = hip_fail(h, e, "event"); break; }
+    for (int r = 0; r < 3 && s == CLOMP_OK; ++r) s = probe_launch(h, P, bf16, st, true);
+    if (s != CLOMP_OK) break;
+    if ((e = hipEventRecord(b, st)) != hipSuccess || (e = hipEventSynchronize(b)) != hipSuccess) {
+      s = hip_fail(h, e, "event");
+      break;
+    }
+    float ms = 0.f;
+    if ((e = hipEventElapsedTime(&ms, a, b)) != hipSuccess) { s = hip_fail(h, e, "event"); break; }
+    if (q == 0 || ms < best) {
+      best = ms;
+      *best_kb = cand[q];
+    }
+  }
+  h->profiling = was_profiling;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return s;
 }
 
 }  // namespace
@@ -787,65 +996,33 @@ clomp_status_t clomp_solve_batch(clomp_handle_t h, const clomp_instance_t* inst,
   HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
 
   Plan P;
-  build_plan(h, inst, count, bf16, P);
+  int scan_kb = h->scan_tile_kb, pass_kb = h->pass_tile_kb;
+  build_plan(h, inst, count, bf16, P, scan_kb, pass_kb);
+  if ((h->params.flags & CLOMP_FLAG_AUTOTUNE) && P.nbig > 0) {
+    double bulk = 0.0;
+    for (int q = 0; q < P.nbig; ++q)
+      bulk += (double)P.insts[q].m * P.insts[q].n * (bf16 ? 2.0 : 4.0);
+    const std::string key = tune_key(P, bf16, h->params.method, bulk);
+    auto it = h->tuned.find(key);
+    int kb = 0;
+    if (it != h->tuned.end()) {
+      kb = it->second;
+    } else {
+      if ((s = autotune(h, inst, count, bf16, st, P.hflow, scan_kb, pass_kb, &kb)) != CLOMP_OK)
+        return s;
+      h->tuned[key] = kb;
+    }
+    if (P.hflow) pass_kb = kb; else scan_kb = kb;
+    build_plan(h, inst, count, bf16, P, scan_kb, pass_kb);
+  }
+  h->last_scan_kb = scan_kb;
+  h->last_pass_kb = pass_kb;
   if ((size_t)P.cg_mpad_max * sizeof(float) + 1024 > (size_t)h->lds_limit)
     return fail(h, CLOMP_NOT_SUPPORTED,
                 "m = %d needs %zu bytes of LDS for the refinement; the device allows %d",
                 P.cg_mpad_max, (size_t)P.cg_mpad_max * sizeof(float), h->lds_limit);
 
-  // workspace and tables (grow-only; growth invalidates captured graphs)
-  bool g1 = false, g2 = false;
-  if ((s = ensure(h, h->ws, P.ws_bytes, &g1)) != CLOMP_OK) return s;
-  if ((s = ensure(h, h->tables, P.table_bytes, &g2)) != CLOMP_OK) return s;
-  if (g1 || g2) drop_graphs(h);
-  // rebase workspace offsets
-  char* wsb = reinterpret_cast<char*>(h->ws.p);
-  for (Inst& d : P.insts) {
-    auto rb = [&](auto*& ptr) {
-      if (ptr) ptr = reinterpret_cast<std::remove_reference_t<decltype(ptr)>>(
-                   wsb + (reinterpret_cast<uintptr_t>(ptr) - 1));
-    };
-    rb(d.r); rb(d.G); rb(d.b); rb(d.s); rb(d.mo); rb(d.ve); rb(d.xf); rb(d.z);
-    rb(d.Linv); rb(d.cg); rb(d.c0); rb(d.dg); rb(d.H); rb(d.team); rb(d.npart);
-    rb(d.qpart); rb(d.key);
-    rb(d.bitmap);
-    rb(d.st);
-  }
-  // stage tables in pinned memory and upload on the stream
-  if (h->pinned_bytes < P.table_bytes) {
-    if (h->pinned) {
-      HIP_TRY(hipEventSynchronize(h->staging_free), "hipEventSynchronize");
-      (void)hipHostFree(h->pinned);
-      h->pinned = nullptr;
-    }
-    const size_t want = align_up(P.table_bytes * 2, 1 << 16);
-    if (hipHostMalloc(&h->pinned, want, hipHostMallocDefault) != hipSuccess) {
-      (void)hipGetLastError();
-      h->pinned = nullptr;
-      h->pinned_bytes = 0;
-      return fail(h, CLOMP_OUT_OF_MEMORY, "pinned staging allocation failed");
-    }
-    h->pinned_bytes = want;
-  } else {
-    HIP_TRY(hipEventSynchronize(h->staging_free), "hipEventSynchronize");
-  }
-  char* hb = reinterpret_cast<char*>(h->pinned);
-  memcpy(hb + P.off_insts, P.insts.data(), sizeof(Inst) * P.insts.size());
-  if (!P.tiles.empty()) memcpy(hb + P.off_tiles, P.tiles.data(), sizeof(ScanTile) * P.tiles.size());
-  if (!P.rows.empty()) memcpy(hb + P.off_rows, P.rows.data(), sizeof(RowTile) * P.rows.size());
-  if (!P.qr_list.empty()) memcpy(hb + P.off_qr, P.qr_list.data(), sizeof(int) * P.qr_list.size());
-  if (!P.cg_list.empty()) memcpy(hb + P.off_cg, P.cg_list.data(), sizeof(int) * P.cg_list.size());
-  if (!P.cg_rows.empty())
-    memcpy(hb + P.off_cgrows, P.cg_rows.data(), sizeof(RowTile) * P.cg_rows.size());
-  if (!P.htiles.empty())
-    memcpy(hb + P.off_htiles, P.htiles.data(), sizeof(ScanTile) * P.htiles.size());
-  if (!P.ctiles.empty())
-    memcpy(hb + P.off_ctiles, P.ctiles.data(), sizeof(ScanTile) * P.ctiles.size());
-  // the previous batch (possibly on another stream) must be done with the tables
-  if (h->have_work) HIP_TRY(hipStreamWaitEvent(st, h->work_done, 0), "hipStreamWaitEvent");
-  HIP_TRY(hipMemcpyAsync(h->tables.p, hb, P.table_bytes, hipMemcpyHostToDevice, st),
-          "upload tables");
-  HIP_TRY(hipEventRecord(h->staging_free, st), "hipEventRecord");
+  if ((s = stage_plan(h, P, st)) != CLOMP_OK) return s;
 
   const bool use_graph = (h->params.flags & CLOMP_FLAG_GRAPH) != 0;
   h->profiling = !use_graph && (h->params.flags & CLOMP_FLAG_PROFILE) != 0;
@@ -916,8 +1093,9 @@ clomp_status_t clomp_set_tuning(clomp_handle_t h, const clomp_tuning_t* t) {
       t->pass_tile_kb > 65536 || t->team_min_rows < 0)
     return fail(h, CLOMP_INVALID_ARGUMENT,
                 "tile sizes must lie in [0, 65536] KB and team_min_rows must be >= 0");
-  if (t->scan_tile_kb) h->scan_tile_kb = t->scan_tile_kb;
-  if (t->pass_tile_kb) h->pass_tile_kb = t->pass_tile_kb;
+  if (t->scan_tile_kb) h->scan_tile_kb = h->last_scan_kb = t->scan_tile_kb;
+  if (t->pass_tile_kb) h->pass_tile_kb = h->last_pass_kb = t->pass_tile_kb;
+  h->tuned.clear();
   if (t->team_min_rows) h->team_min_rows = t->team_min_rows;
   drop_graphs(h);
   return CLOMP_OK;
@@ -926,8 +1104,8 @@ clomp_status_t clomp_set_tuning(clomp_handle_t h, const clomp_tuning_t* t) {
 clomp_status_t clomp_get_tuning(clomp_handle_t h, clomp_tuning_t* t) {
   if (!h || !t) return CLOMP_INVALID_ARGUMENT;
   memset(t, 0, sizeof *t);
-  t->scan_tile_kb = h->scan_tile_kb;
-  t->pass_tile_kb = h->pass_tile_kb;
+  t->scan_tile_kb = h->last_scan_kb;
+  t->pass_tile_kb = h->last_pass_kb;
   t->team_min_rows = h->team_min_rows;
   return CLOMP_OK;
 }
@@ -939,6 +1117,7 @@ clomp_status_t clomp_profile_reset(clomp_handle_t h) {
   h->ev_used = 0;
   h->scan_bytes = 0.0;
   h->pass_bytes = 0.0;
+  h->fused_bytes = 0.0;
   return CLOMP_OK;
 }
 
@@ -954,6 +1133,7 @@ clomp_status_t clomp_profile_read(clomp_handle_t h, clomp_profile_t* out) {
   }
   out->scan_bytes = h->scan_bytes;
   out->pass_bytes = h->pass_bytes;
+  out->fused_bytes = h->fused_bytes;
   return CLOMP_OK;
 }
 

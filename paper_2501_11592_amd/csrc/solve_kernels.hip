@@ -1041,6 +1041,244 @@ __global__ __launch_bounds__(kBlock) void copy_s_kernel(const Inst* __restrict__
   if (threadIdx.x == 0) I.st->cg_done = 0;
 }
 
+// ============================================================ fused small-signal loop
+// One workgroup runs the whole greedy loop of one signal whose dictionary fits
+// in LDS: A is converted to FP32 once (row j of the LDS image is atom j, with
+// an odd leading dimension so lanes reading consecutive atoms hit distinct
+// banks), then every iteration - correlation scan and argmax, selection
+// record, new Gram column, coefficient update, residual - stays on chip.  The
+// coefficient update runs in wave 0 with lane r owning row r (k_eff <= 64):
+// the T Adam steps (or the OMP bordered-inverse update) need no workgroup
+// barrier.  Arithmetic follows the per-iteration kernels; summation orders
+// differ.  The loop leaves s, b, the support and the state in the workspace
+// for the refinement and the FP64 norm.
+constexpr int kSmallThreads = 256;
+constexpr int kSmallWaves = kSmallThreads / 64;
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename TA, bool OMP>
+__global__ __launch_bounds__(kSmallThreads) void small_loop_kernel(
+    const Inst* __restrict__ insts, const int* __restrict__ list, int T, float beta1,
+    float beta2, float lr_rel, float eps_rel) {
+  extern __shared__ __align__(16) float sm[];
+  __shared__ unsigned long long wkey[kSmallWaves];
+  __shared__ __align__(16) float sbuf[2][kSmallMaxK];   // coefficients (ping-pong) / OMP v
+  __shared__ float gcol[kSmallMaxK + 2];   // G[l, t] (l < t), ||a_j||^2, a_j^T y
+  __shared__ float bsh[kSmallMaxK];
+  __shared__ int sup[kSmallMaxK];
+  const Inst& I = insts[list[blockIdx.x]];
+  if (I.st->done) return;   // y == 0: init has finished the signal
+  const int n = I.n, m = I.m, ke = I.k_eff;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int ldl = m | 1;
+  const int ldq = small_ldq(ke);
+  const int m4 = (m + 3) & ~3;
+  float* Gq = sm;                                   // [ke][ldq] G (CLOMP) or Ginv (OMP)
+  float* Al = Gq + (size_t)ke * ldq;                // [n][ldl]
+  float* r = Al + (((size_t)n * ldl + 3) & ~(size_t)3);   // [m4]
+  float* yl = r + m4;                               // [m4]
+  unsigned* bm = reinterpret_cast<unsigned*>(yl + m4);    // [ceil(n/32)]
+  // ---- stage A, y, and clear the state
+  {
+    constexpr int VW = Vec<TA>::W;
+    const int nvec = (m + VW - 1) / VW;
+    const TA* A = reinterpret_cast<const TA*>(I.A);
+    for (int q = tid; q < n * nvec; q += kSmallThreads) {
+      const int j = q / nvec, c = q - j * nvec;
+      float v[VW];
+      Vec<TA>::load(A + (long long)j * I.lda + (long long)c * VW, v);
+#pragma unroll
+      for (int e = 0; e < VW; ++e)
+        if (c * VW + e < m) Al[(size_t)j * ldl + c * VW + e] = v[e];
+    }
+  }
+  for (int i = tid; i < m4; i += kSmallThreads) {
+    const float v = (i < m) ? I.y[i] : 0.f;
+    r[i] = v;
+    yl[i] = v;
+  }
+  for (int q = tid; q < ke * ldq; q += kSmallThreads) Gq[q] = 0.f;
+  for (int q = tid; q < (n + 31) / 32; q += kSmallThreads) bm[q] = 0u;
+  if (tid < kSmallMaxK) {
+    sbuf[0][tid] = 0.f;
+    sbuf[1][tid] = 0.f;
+  }
+  __syncthreads();
+  float sv = 0.f, mo = 0.f, ve = 0.f;   // wave 0, lane r: coefficient r and its moments
+  float lr = 0.f, eps = 0.f, sigma = 0.f;
+  int step = 0, cur = 0, t = 0;
+  for (; t < ke; ++t) {
+    // ---- correlations of the unselected atoms and the argmax key
+    unsigned long long best = 0ull;
+    for (int j = tid; j < n; j += kSmallThreads) {
+      const float* a = Al + (size_t)j * ldl;
+      float a0 = 0.f, a1 = 0.f;
+      int i = 0;
+      for (; i + 1 < m; i += 2) {
+        a0 = fmaf(a[i], r[i], a0);
+        a1 = fmaf(a[i + 1], r[i + 1], a1);
+      }
+      if (i < m) a0 = fmaf(a[i], r[i], a0);
+      const unsigned selb = (bm[j >> 5] >> (j & 31)) & 1u;
+      const unsigned long long key = selb ? 0ull : pack_key(a0 + a1, j);
+      best = key > best ? key : best;
+    }
+    best = wave_max_u64(best);
+    if (lane == 0) wkey[w] = best;
+    __syncthreads();
+    unsigned long long key = wkey[0];
+#pragma unroll
+    for (int q = 1; q < kSmallWaves; ++q) key = wkey[q] > key ? wkey[q] : key;
+    const int j = key_index(key);
+    if (key == 0ull || j < 0 || j >= n) {
+      if (tid == 0) {
+        I.st->done = 1;
+        atomicOr(I.status, ST_WATCHDOG);
+      }
+      break;
+    }
+    const float cj = key_value(key);
+    if (t == 0) {
+      sigma = cj;
+      eps = eps_rel * cj;
+    }
+    lr = lr_rel * cj;   // step size follows the selected correlation
+    // ---- selection record and the new Gram column
+    if (tid == 0) {
+      I.support[t] = j;
+      *I.nsel = t + 1;
+      if (!(cj <= 3.402823466e38f)) atomicOr(I.status, ST_NAN);
+      bm[j >> 5] |= 1u << (j & 31);
+      sup[t] = j;
+    }
+    {
+      const float* aj = Al + (size_t)j * ldl;
+      for (int l = w; l < t + 2; l += kSmallWaves) {
+        const float* v = (l < t) ? Al + (size_t)sup[l] * ldl : (l == t ? aj : yl);
+        float acc = 0.f;
+        for (int i = lane; i < m; i += 64) acc = fmaf(aj[i], v[i], acc);
+        acc = wave_sum(acc);
+        if (lane == 0) gcol[l] = acc;
+      }
+    }
+    __syncthreads();
+    // ---- coefficient update (wave 0)
+    if (w == 0) {
+      const int t1 = t + 1;
+      if (!OMP) {
+        for (int c = lane; c <= t; c += 64) {
+          Gq[(size_t)t * ldq + c] = gcol[c];
+          Gq[(size_t)c * ldq + t] = gcol[c];
+        }
+        if (lane == 0) bsh[t] = gcol[t + 1];
+        wave_sync();
+        const float bb = (lane < t1) ? bsh[lane] : 0.f;
+        const float* grow = Gq + (size_t)(lane < ke ? lane : 0) * ldq;
+        double b1p = pow((double)beta1, (double)step);
+        double b2p = pow((double)beta2, (double)step);
+        int bufi = cur;
+        for (int it = 0; it < T; ++it) {
+          b1p *= beta1;
+          b2p *= beta2;
+          const float ibc1 = __builtin_amdgcn_rcpf((float)(1.0 - b1p));
+          const float ibc2 = __builtin_amdgcn_rcpf((float)(1.0 - b2p));
+          const float* sc = sbuf[bufi];
+          float acc[4] = {0.f, 0.f, 0.f, 0.f};
+          for (int c = 0; c < t1; c += 4) {
+            const float4 g4 = *reinterpret_cast<const float4*>(grow + c);
+            const float4 s4 = *reinterpret_cast<const float4*>(sc + c);
+            acc[0] = fmaf(g4.x, s4.x, acc[0]);
+            acc[1] = fmaf(g4.y, s4.y, acc[1]);
+            acc[2] = fmaf(g4.z, s4.z, acc[2]);
+            acc[3] = fmaf(g4.w, s4.w, acc[3]);
+          }
+          if (lane < t1) {
+            const float gr = ((acc[0] + acc[1]) + (acc[2] + acc[3])) - bb;
+            mo = beta1 * mo + (1.f - beta1) * gr;
+            ve = beta2 * ve + (1.f - beta2) * (gr * gr);
+            const float mh = mo * ibc1;
+            const float vh = ve * ibc2;
+            sv = sv - lr * mh * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(vh) + eps);
+            sbuf[bufi ^ 1][lane] = sv;
+          }
+          wave_sync();
+          bufi ^= 1;
+        }
+      } else {
+        // bordered inverse: v = Ginv g, delta = gamma - g.v,
+        // alpha = (b_t - g.x) / delta, x <- [x - alpha v; alpha]
+        const float* grow = Gq + (size_t)(lane < ke ? lane : 0) * ldq;
+        float vr = 0.f;
+        if (lane < t)
+          for (int c = 0; c < t; ++c) vr = fmaf(grow[c], gcol[c], vr);
+        const float gv = wave_sum(lane < t ? gcol[lane] * vr : 0.f);
+        const float gx = wave_sum(lane < t ? gcol[lane] * sv : 0.f);
+        const float gamma = gcol[t];
+        float delta = gamma - gv;
+        const bool bad = !(delta > 1e-7f * gamma);
+        if (bad) delta = fmaxf(1e-7f * gamma, 1e-30f);
+        const float inv = 1.f / delta;
+        const float alpha = (gcol[t + 1] - gx) * inv;
+        sbuf[0][lane] = (lane < t) ? vr : 0.f;
+        if (lane == 0) bsh[t] = gcol[t + 1];
+        wave_sync();
+        if (lane < t) {
+          float* row = Gq + (size_t)lane * ldq;
+          const float vi = vr * inv;
+          for (int c = 0; c < t; ++c) row[c] = fmaf(sbuf[0][c], vi, row[c]);
+          row[t] = -vi;
+          sv = fmaf(-alpha, vr, sv);
+        } else if (lane == t) {
+          float* row = Gq + (size_t)t * ldq;
+          for (int c = 0; c < t; ++c) row[c] = -sbuf[0][c] * inv;
+          row[t] = inv;
+          sv = alpha;
+        }
+        if (bad && lane == 0) atomicOr(I.status, ST_REFINE_INACCURATE);
+        if (lane < t1) sbuf[1][lane] = sv;
+      }
+    }
+    if (!OMP) step += T;
+    __syncthreads();
+    if (!OMP) cur ^= (T & 1);   // every thread tracks the buffer holding s
+    // ---- residual r = y - A_S s
+    {
+      const float* sc = sbuf[OMP ? 1 : cur];
+      for (int i = tid; i < m; i += kSmallThreads) {
+        float a0 = 0.f, a1 = 0.f;
+        int l = 0;
+        for (; l + 1 <= t; l += 2) {
+          a0 = fmaf(Al[(size_t)sup[l] * ldl + i], sc[l], a0);
+          a1 = fmaf(Al[(size_t)sup[l + 1] * ldl + i], sc[l + 1], a1);
+        }
+        if (l <= t) a0 = fmaf(Al[(size_t)sup[l] * ldl + i], sc[l], a0);
+        r[i] = yl[i] - (a0 + a1);
+      }
+    }
+    __syncthreads();
+  }
+  // ---- state for the refinement and the norm
+  if (w == 0 && lane < t) {
+    I.s[lane] = sv;
+    I.b[lane] = bsh[lane];
+    if (!OMP) {
+      I.mo[lane] = mo;
+      I.ve[lane] = ve;
+    }
+  }
+  if (tid == 0) {
+    I.st->sigma = sigma;
+    I.st->lr = lr;
+    I.st->eps = eps;
+    I.st->step = step;
+  }
+}
+
 // ============================================================ correlation-update schedule
 // For one (or a few) large signals the greedy loop is latency bound: the
 // Adam steps of an iteration are a serial chain on one CU while the scan
@@ -1476,7 +1714,12 @@ __global__ __launch_bounds__(kPassThreads) void coef_pass_kernel(
       omp_ginv_body(I, t, dsh, red, red2, false);
     return;
   }
-  const ScanTile tile = tiles[blockIdx.x - nact * W];
+  // odd iterations walk the tiles backwards: a pass starts on the columns
+  // the previous pass streamed last, which the memory-side cache may still
+  // hold when the dictionary is about the cache's size
+  const int ntl = (int)gridDim.x - nact * W;
+  const int ti = (int)blockIdx.x - nact * W;
+  const ScanTile tile = tiles[(t & 1) ? ntl - 1 - ti : ti];
   pass_tile_body<TA, LPA, 1>(insts[tile.inst], tile, t, dsh, wbest);
 }
 
@@ -1804,9 +2047,35 @@ static hipError_t raise_dynamic_lds(const void* const* fns, size_t nf, size_t by
   return hipSuccess;
 }
 
+hipError_t launch_small(int bf16, int omp, const Inst* d, const int* list, int count, int T,
+                        float beta1, float beta2, float lr_rel, float eps_rel, size_t lds,
+                        hipStream_t s) {
+  if (count <= 0) return nothing_to_launch(s);
+  const dim3 g(count), b(kSmallThreads);
+  if (bf16) {
+    if (omp)
+      CLOMP_LAUNCH((small_loop_kernel<uint16_t, true>), g, b, lds, s, d, list, T, beta1, beta2,
+                   lr_rel, eps_rel);
+    else
+      CLOMP_LAUNCH((small_loop_kernel<uint16_t, false>), g, b, lds, s, d, list, T, beta1, beta2,
+                   lr_rel, eps_rel);
+  } else {
+    if (omp)
+      CLOMP_LAUNCH((small_loop_kernel<float, true>), g, b, lds, s, d, list, T, beta1, beta2,
+                   lr_rel, eps_rel);
+    else
+      CLOMP_LAUNCH((small_loop_kernel<float, false>), g, b, lds, s, d, list, T, beta1, beta2,
+                   lr_rel, eps_rel);
+  }
+  return hipGetLastError();
+}
+
 hipError_t set_max_lds(size_t bytes) {
   // Raise the dynamic-LDS ceiling of the kernels that stage vectors.
   const void* fns[] = {
+      (const void*)small_loop_kernel<float, false>, (const void*)small_loop_kernel<float, true>,
+      (const void*)small_loop_kernel<uint16_t, false>,
+      (const void*)small_loop_kernel<uint16_t, true>,
       (const void*)scan_kernel<float, 4>, (const void*)scan_kernel<float, 8>,
       (const void*)scan_kernel<float, 16>, (const void*)scan_kernel<float, 32>,
       (const void*)scan_kernel<float, 64>, (const void*)scan_kernel<uint16_t, 4>,

@@ -21,12 +21,16 @@ from tests.gpu_helpers import (PARAMS, FP32_DELTA, FP32_U, BF16_DELTA, BF16_U, d
 pytestmark = pytest.mark.gpu
 
 
-FLOWS = {"resid": C.FLAG_RESIDUAL_FLOW, "corr": C.FLAG_CORR_FLOW}
+# the two iterated schedules with the fused small-signal loop off, and the
+# default configuration (small signals fused, the rest iterated)
+FLOWS = {"resid": C.FLAG_RESIDUAL_FLOW | C.FLAG_NO_FUSED_SMALL,
+         "corr": C.FLAG_CORR_FLOW | C.FLAG_NO_FUSED_SMALL,
+         "fused": 0}
 
 
 @pytest.fixture(scope="module", params=sorted(FLOWS))
 def solvers(request):
-    """CLOMP and OMP handles, under each of the two schedules."""
+    """CLOMP and OMP handles, under each configuration."""
     fl = FLOWS[request.param]
     s = {"clomp": C.Solver(0, method="clomp", flags=fl),
          "omp": C.Solver(0, method="omp", flags=fl)}
@@ -157,6 +161,51 @@ def test_coefficient_teams(method):
     assert ident >= 2
     team.close()
     single.close()
+
+
+@pytest.mark.parametrize("flow", ["resid", "corr"])
+def test_autotune_matches_default(flow):
+    """CLOMP_FLAG_AUTOTUNE times the candidate tile sizes on the first call of a
+    size class and reuses the choice; tiles only regroup atoms across
+    workgroups, so the results are bit-identical to the default tiles."""
+    sigs = [W.single_small(300 + i, n=3000, m=200, k=20) for i in range(3)]
+    fl = FLOWS[flow]
+    tuned = C.Solver(0, method="clomp", flags=fl | C.FLAG_AUTOTUNE)
+    plain = C.Solver(0, method="clomp", flags=fl)
+    a = tuned.solve_batch(_items(sigs))
+    b = plain.solve_batch(_items(sigs))
+    a2 = tuned.solve_batch(_items(sigs))
+    torch.cuda.synchronize()
+    kb = tuned.get_tuning()
+    if flow == "corr":
+        assert kb["pass_tile_kb"] in (128, 256, 512, 1024, 2048)
+    else:
+        assert kb["scan_tile_kb"] in (32, 64, 128, 256, 512)
+    print(f"{flow}: tuned {kb}")
+    for i in range(len(sigs)):
+        assert torch.equal(a.support[i], b.support[i]) and torch.equal(a2.support[i], b.support[i])
+        assert torch.equal(a.x[i], b.x[i]) and torch.equal(a2.x[i], b.x[i])
+    tuned.close()
+    plain.close()
+
+
+def test_prepared_batch_reruns(solvers):
+    """Descriptors packed once: repeated launches rewrite the same outputs with
+    the results of a one-off solve."""
+    sigs = [W.single_small(400 + i) for i in range(5)] + [W.single_small(410, n=2000, m=150, k=30)]
+    sol = solvers["clomp"]
+    stream = torch.cuda.Stream()
+    prep = sol.prepare(_items(sigs), stream=stream)
+    r1 = sol.run(prep)
+    torch.cuda.synchronize()
+    x1 = [t.clone() for t in r1.x]
+    r2 = sol.run(prep)
+    ref = sol.solve_batch(_items(sigs))
+    torch.cuda.synchronize()
+    assert r2 is r1
+    for i in range(len(sigs)):
+        assert torch.equal(r2.x[i], x1[i]) and torch.equal(r2.x[i], ref.x[i])
+        assert torch.equal(r2.support[i], ref.support[i])
 
 
 def test_edge_cases(solvers):
