@@ -11,7 +11,7 @@ column-major with leading dimension lda >= m.
 
 import ctypes
 import os
-from dataclasses import dataclass
+from dataclasses import dataclass, field
 
 import numpy as np
 
@@ -77,6 +77,7 @@ class PreparedBatch:
     items: list              # inputs, kept alive with the batch
     stream: object
     outputs: tuple
+    recorded: set = field(default_factory=set)   # streams the tensors are recorded on
 
 
 class ClompError(RuntimeError):
@@ -286,8 +287,10 @@ class Solver:
             self._h, prep.arr.ctypes.data_as(ctypes.POINTER(Instance)), prep.count, prep.dtype,
             ctypes.c_void_p(st.cuda_stream))
         _check(self._h, rc, "clomp_solve_batch")
-        if st != torch.cuda.current_stream(dev):
+        if st != torch.cuda.current_stream(dev) and st.cuda_stream not in prep.recorded:
             # tensors the caller may drop must outlive the queued work on `st`
+            # (one record per stream: the allocator checks every recorded
+            # stream when the tensor is freed)
             seen = set()
             for it in prep.items:
                 for key in ("At", "At_master", "y"):
@@ -297,6 +300,7 @@ class Solver:
                         t.record_stream(st)
             for t in prep.outputs:
                 t.record_stream(st)
+            prep.recorded.add(st.cuda_stream)
         self._keep = prep
         return prep.result
 

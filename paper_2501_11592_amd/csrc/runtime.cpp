@@ -82,6 +82,28 @@ struct Plan {
   size_t off_insts = 0, off_tiles = 0, off_rows = 0, off_qr = 0, off_cg = 0, off_cgrows = 0;
   size_t table_bytes = 0;
   std::string sig;                    // shape signature (graph cache key)
+  std::vector<int> order;             // sorted position -> input index
+};
+
+// Shape of one input instance: everything a plan depends on apart from the
+// data pointers.
+struct ShapeRec {
+  int n, m, k, has_master;
+  long long lda, ldam;
+  bool operator==(const ShapeRec& o) const {
+    return n == o.n && m == o.m && k == o.k && has_master == o.has_master && lda == o.lda &&
+           ldam == o.ldam;
+  }
+};
+
+// The plan of the last batch shape, before its workspace offsets are rebased:
+// a batch with the same shapes reuses it and only fills in the pointers.
+struct PlanCache {
+  bool valid = false;
+  int bf16 = -1;
+  std::vector<ShapeRec> shapes;
+  Plan P;
+  int scan_kb = 0, pass_kb = 0;
 };
 
 struct CachedGraph {
@@ -118,9 +140,17 @@ struct clomp_ctx {
   int team_min_rows = 256;            // larger supports use coefficient teams
   int last_scan_kb = kScanTargetKB, last_pass_kb = kPassTargetKB;   // of the last solve
   std::map<std::string, int> tuned;   // autotuned tile size per size class
+  PlanCache pcache;
 };
 
 namespace {
+
+// Restores the caller's current device on every return path.
+struct DeviceGuard {
+  int prev = 0;
+  DeviceGuard() { (void)hipGetDevice(&prev); }
+  ~DeviceGuard() { (void)hipSetDevice(prev); }
+};
 
 clomp_status_t fail(clomp_ctx* h, clomp_status_t s, const char* fmt, ...) {
   if (h) {
@@ -239,6 +269,7 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
   });
   P.nbig = 0;
   while (P.nbig < count && !fused[order[P.nbig]]) ++P.nbig;
+  P.order = order;
   const int qr_limit_floats = ((int)std::min<size_t>((size_t)h->lds_limit, 96 * 1024) - 1024) / 4;
   {
     // correlation-update schedule: few signals, H within budget, the pass
@@ -728,26 +759,13 @@ clomp_status_t launch_all(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st)
 // Workspace (grow-only; growth invalidates captured graphs), descriptors
 // rebased onto it, and the descriptor / tile tables uploaded on `st` through
 // pinned staging.
-clomp_status_t stage_plan(clomp_ctx* h, Plan& P, hipStream_t st) {
+clomp_status_t stage_plan(clomp_ctx* h, const Plan& P, hipStream_t st) {
   clomp_status_t s = CLOMP_OK;
   // workspace and tables (grow-only; growth invalidates captured graphs)
   bool g1 = false, g2 = false;
   if ((s = ensure(h, h->ws, P.ws_bytes, &g1)) != CLOMP_OK) return s;
   if ((s = ensure(h, h->tables, P.table_bytes, &g2)) != CLOMP_OK) return s;
   if (g1 || g2) drop_graphs(h);
-  // rebase workspace offsets
-  char* wsb = reinterpret_cast<char*>(h->ws.p);
-  for (Inst& d : P.insts) {
-    auto rb = [&](auto*& ptr) {
-      if (ptr) ptr = reinterpret_cast<std::remove_reference_t<decltype(ptr)>>(
-                   wsb + (reinterpret_cast<uintptr_t>(ptr) - 1));
-    };
-    rb(d.r); rb(d.G); rb(d.b); rb(d.s); rb(d.mo); rb(d.ve); rb(d.xf); rb(d.z);
-    rb(d.Linv); rb(d.cg); rb(d.c0); rb(d.dg); rb(d.H); rb(d.team); rb(d.npart);
-    rb(d.qpart); rb(d.key);
-    rb(d.bitmap);
-    rb(d.st);
-  }
   // stage tables in pinned memory and upload on the stream
   if (h->pinned_bytes < P.table_bytes) {
     if (h->pinned) {
@@ -767,7 +785,22 @@ clomp_status_t stage_plan(clomp_ctx* h, Plan& P, hipStream_t st) {
     HIP_TRY(hipEventSynchronize(h->staging_free), "hipEventSynchronize");
   }
   char* hb = reinterpret_cast<char*>(h->pinned);
-  memcpy(hb + P.off_insts, P.insts.data(), sizeof(Inst) * P.insts.size());
+  // descriptors with their workspace offsets rebased onto the workspace
+  char* wsb = reinterpret_cast<char*>(h->ws.p);
+  Inst* dst = reinterpret_cast<Inst*>(hb + P.off_insts);
+  for (size_t q = 0; q < P.insts.size(); ++q) {
+    Inst& d = dst[q];
+    d = P.insts[q];
+    auto rb = [&](auto*& ptr) {
+      if (ptr) ptr = reinterpret_cast<std::remove_reference_t<decltype(ptr)>>(
+                   wsb + (reinterpret_cast<uintptr_t>(ptr) - 1));
+    };
+    rb(d.r); rb(d.G); rb(d.b); rb(d.s); rb(d.mo); rb(d.ve); rb(d.xf); rb(d.z);
+    rb(d.Linv); rb(d.cg); rb(d.c0); rb(d.dg); rb(d.H); rb(d.team); rb(d.npart);
+    rb(d.qpart); rb(d.key);
+    rb(d.bitmap);
+    rb(d.st);
+  }
   if (!P.tiles.empty()) memcpy(hb + P.off_tiles, P.tiles.data(), sizeof(ScanTile) * P.tiles.size());
   if (!P.rows.empty()) memcpy(hb + P.off_rows, P.rows.data(), sizeof(RowTile) * P.rows.size());
   if (!P.qr_list.empty()) memcpy(hb + P.off_qr, P.qr_list.data(), sizeof(int) * P.qr_list.size());
@@ -975,6 +1008,7 @@ clomp_status_t clomp_set_params(clomp_handle_t h, const clomp_params_t* params) 
   const clomp_status_t s = check_params(h, params);
   if (s != CLOMP_OK) return s;
   h->params = *params;
+  h->pcache.valid = false;
   drop_graphs(h);
   return CLOMP_OK;
 }
@@ -991,14 +1025,36 @@ clomp_status_t clomp_solve_batch(clomp_handle_t h, const clomp_instance_t* inst,
   if (s != CLOMP_OK || count == 0) return s;
   const int bf16 = a_dtype == CLOMP_BF16;
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-  int prev = 0;
-  (void)hipGetDevice(&prev);
+  DeviceGuard dg;
   HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
 
-  Plan P;
+  std::vector<ShapeRec> shapes(count);
+  for (int i = 0; i < count; ++i)
+    shapes[i] = {inst[i].n, inst[i].m, inst[i].k, inst[i].A_master ? 1 : 0,
+                 (long long)inst[i].lda, (long long)inst[i].lda_master};
+  Plan fresh;
   int scan_kb = h->scan_tile_kb, pass_kb = h->pass_tile_kb;
-  build_plan(h, inst, count, bf16, P, scan_kb, pass_kb);
-  if ((h->params.flags & CLOMP_FLAG_AUTOTUNE) && P.nbig > 0) {
+  const bool cached = h->pcache.valid && h->pcache.bf16 == bf16 && h->pcache.shapes == shapes;
+  Plan& P = cached ? h->pcache.P : fresh;
+  if (cached) {
+    scan_kb = h->pcache.scan_kb;
+    pass_kb = h->pcache.pass_kb;
+    for (int q = 0; q < count; ++q) {
+      const clomp_instance_t& src = inst[P.order[q]];
+      Inst& d = P.insts[q];
+      d.A = src.A;
+      d.Am = src.A_master ? src.A_master : reinterpret_cast<const float*>(src.A);
+      d.y = src.y;
+      d.x = src.x;
+      d.support = src.support;
+      d.nsel = src.n_selected;
+      d.rnorm = src.resid_norm;
+      d.status = src.status;
+    }
+  } else {
+    build_plan(h, inst, count, bf16, P, scan_kb, pass_kb);
+  }
+  if (!cached && (h->params.flags & CLOMP_FLAG_AUTOTUNE) && P.nbig > 0) {
     double bulk = 0.0;
     for (int q = 0; q < P.nbig; ++q)
       bulk += (double)P.insts[q].m * P.insts[q].n * (bf16 ? 2.0 : 4.0);
@@ -1015,23 +1071,33 @@ clomp_status_t clomp_solve_batch(clomp_handle_t h, const clomp_instance_t* inst,
     if (P.hflow) pass_kb = kb; else scan_kb = kb;
     build_plan(h, inst, count, bf16, P, scan_kb, pass_kb);
   }
+  if (!cached) {
+    h->pcache.valid = false;   // until the new plan is in place
+    h->pcache.P = std::move(fresh);
+    h->pcache.bf16 = bf16;
+    h->pcache.shapes = std::move(shapes);
+    h->pcache.scan_kb = scan_kb;
+    h->pcache.pass_kb = pass_kb;
+    h->pcache.valid = true;
+  }
+  const Plan& PP = h->pcache.P;
   h->last_scan_kb = scan_kb;
   h->last_pass_kb = pass_kb;
-  if ((size_t)P.cg_mpad_max * sizeof(float) + 1024 > (size_t)h->lds_limit)
+  if ((size_t)PP.cg_mpad_max * sizeof(float) + 1024 > (size_t)h->lds_limit)
     return fail(h, CLOMP_NOT_SUPPORTED,
                 "m = %d needs %zu bytes of LDS for the refinement; the device allows %d",
-                P.cg_mpad_max, (size_t)P.cg_mpad_max * sizeof(float), h->lds_limit);
+                PP.cg_mpad_max, (size_t)PP.cg_mpad_max * sizeof(float), h->lds_limit);
 
-  if ((s = stage_plan(h, P, st)) != CLOMP_OK) return s;
+  if ((s = stage_plan(h, PP, st)) != CLOMP_OK) return s;
 
   const bool use_graph = (h->params.flags & CLOMP_FLAG_GRAPH) != 0;
   h->profiling = !use_graph && (h->params.flags & CLOMP_FLAG_PROFILE) != 0;
   if (use_graph) {
-    auto it = h->graphs.find(P.sig);
+    auto it = h->graphs.find(PP.sig);
     if (it == h->graphs.end()) {
       CachedGraph cg;
       HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
-      s = launch_all(h, P, bf16, st);
+      s = launch_all(h, PP, bf16, st);
       hipGraph_t g = nullptr;
       const hipError_t e = hipStreamEndCapture(st, &g);
       if (s != CLOMP_OK) {
@@ -1041,15 +1107,14 @@ clomp_status_t clomp_solve_batch(clomp_handle_t h, const clomp_instance_t* inst,
       if (e != hipSuccess) return hip_fail(h, e, "end capture");
       cg.graph = g;
       HIP_TRY(hipGraphInstantiate(&cg.exec, g, nullptr, nullptr, 0), "graph instantiate");
-      it = h->graphs.emplace(P.sig, cg).first;
+      it = h->graphs.emplace(PP.sig, cg).first;
     }
     HIP_TRY(hipGraphLaunch(it->second.exec, st), "graph launch");
   } else {
-    if ((s = launch_all(h, P, bf16, st)) != CLOMP_OK) return s;
+    if ((s = launch_all(h, PP, bf16, st)) != CLOMP_OK) return s;
   }
   HIP_TRY(hipEventRecord(h->work_done, st), "hipEventRecord");
   h->have_work = true;
-  (void)hipSetDevice(prev);
   return CLOMP_OK;
 }
 
@@ -1071,8 +1136,7 @@ clomp_status_t clomp_grad(clomp_handle_t h, int32_t n, int32_t m, int64_t lda, i
   const int ncolchunk = (n + colchunk - 1) / colchunk;
   const size_t nfin = (m + kBlock - 1) / kBlock;
   const size_t need = es * ((size_t)ncolchunk * m + m + nfin) + 256;
-  int prev = 0;
-  (void)hipGetDevice(&prev);
+  DeviceGuard dg;
   HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   if (h->gwork.bytes < need) {
@@ -1083,7 +1147,6 @@ clomp_status_t clomp_grad(clomp_handle_t h, int32_t n, int32_t m, int64_t lda, i
   HIP_TRY(launch_grad(dtype == CLOMP_F64, n, m, lda, A, x, mask, y, grad_out, grad_x, resid_out,
                       loss, h->gwork.p, ncolchunk, colchunk, st),
           "grad");
-  (void)hipSetDevice(prev);
   return CLOMP_OK;
 }
 
@@ -1097,6 +1160,7 @@ clomp_status_t clomp_set_tuning(clomp_handle_t h, const clomp_tuning_t* t) {
   if (t->pass_tile_kb) h->pass_tile_kb = h->last_pass_kb = t->pass_tile_kb;
   h->tuned.clear();
   if (t->team_min_rows) h->team_min_rows = t->team_min_rows;
+  h->pcache.valid = false;
   drop_graphs(h);
   return CLOMP_OK;
 }

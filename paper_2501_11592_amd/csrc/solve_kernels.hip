@@ -1052,8 +1052,9 @@ __global__ __launch_bounds__(kBlock) void copy_s_kernel(const Inst* __restrict__
 // barrier.  Arithmetic follows the per-iteration kernels; summation orders
 // differ.  The loop leaves s, b, the support and the state in the workspace
 // for the refinement and the FP64 norm.
-constexpr int kSmallThreads = 256;
+constexpr int kSmallThreads = 512;
 constexpr int kSmallWaves = kSmallThreads / 64;
+constexpr int kSmallDots = (kSmallMaxK + 2 + kSmallWaves - 1) / kSmallWaves;   // per wave
 
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1068,9 +1069,9 @@ __global__ __launch_bounds__(kSmallThreads) void small_loop_kernel(
   extern __shared__ __align__(16) float sm[];
   __shared__ unsigned long long wkey[kSmallWaves];
   __shared__ __align__(16) float sbuf[2][kSmallMaxK];   // coefficients (ping-pong) / OMP v
-  __shared__ float gcol[kSmallMaxK + 2];   // G[l, t] (l < t), ||a_j||^2, a_j^T y
+  __shared__ __align__(16) float gcol[kSmallMaxK + 4];  // G[l, t] (l < t), ||a_j||^2, a_j^T y
   __shared__ float bsh[kSmallMaxK];
-  __shared__ int sup[kSmallMaxK];
+  __shared__ __align__(16) int off[kSmallMaxK];         // LDS offset of selected atom l
   const Inst& I = insts[list[blockIdx.x]];
   if (I.st->done) return;   // y == 0: init has finished the signal
   const int n = I.n, m = I.m, ke = I.k_eff;
@@ -1080,9 +1081,12 @@ __global__ __launch_bounds__(kSmallThreads) void small_loop_kernel(
   const int m4 = (m + 3) & ~3;
   float* Gq = sm;                                   // [ke][ldq] G (CLOMP) or Ginv (OMP)
   float* Al = Gq + (size_t)ke * ldq;                // [n][ldl]
-  float* r = Al + (((size_t)n * ldl + 3) & ~(size_t)3);   // [m4]
-  float* yl = r + m4;                               // [m4]
+  float* r = Al + (((size_t)n * ldl + 3) & ~(size_t)3);   // [m4], zero beyond m
+  float* yl = r + m4;                               // [m4], zero beyond m
   unsigned* bm = reinterpret_cast<unsigned*>(yl + m4);    // [ceil(n/32)]
+  // lanes per atom in the scan: the most (up to 8) that keep every lane busy
+  int G = 1;
+  while (G < 8 && 2 * G * n <= kSmallThreads) G <<= 1;
   // ---- stage A, y, and clear the state
   {
     constexpr int VW = Vec<TA>::W;
@@ -1107,26 +1111,40 @@ __global__ __launch_bounds__(kSmallThreads) void small_loop_kernel(
   if (tid < kSmallMaxK) {
     sbuf[0][tid] = 0.f;
     sbuf[1][tid] = 0.f;
+    off[tid] = 0;
   }
+  if (tid < kSmallMaxK + 4) gcol[tid] = 0.f;
   __syncthreads();
   float sv = 0.f, mo = 0.f, ve = 0.f;   // wave 0, lane r: coefficient r and its moments
   float lr = 0.f, eps = 0.f, sigma = 0.f;
   int step = 0, cur = 0, t = 0;
   for (; t < ke; ++t) {
-    // ---- correlations of the unselected atoms and the argmax key
+    // ---- correlations of the unselected atoms and the argmax key: G lanes
+    // per atom, lane g taking the 4-element chunks g, g+G, ...
     unsigned long long best = 0ull;
-    for (int j = tid; j < n; j += kSmallThreads) {
-      const float* a = Al + (size_t)j * ldl;
-      float a0 = 0.f, a1 = 0.f;
-      int i = 0;
-      for (; i + 1 < m; i += 2) {
-        a0 = fmaf(a[i], r[i], a0);
-        a1 = fmaf(a[i + 1], r[i + 1], a1);
+    {
+      const int g = tid % G;
+      for (int j = tid / G; j < n; j += kSmallThreads / G) {
+        const float* a = Al + (size_t)j * ldl;
+        float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
+#pragma unroll 4
+        for (int i0 = 4 * g; i0 < m; i0 += 4 * G) {
+          const float4 r4 = *reinterpret_cast<const float4*>(r + i0);
+          const float a0 = a[i0];
+          const float a1 = (i0 + 1 < m) ? a[i0 + 1] : 0.f;
+          const float a2 = (i0 + 2 < m) ? a[i0 + 2] : 0.f;
+          const float a3 = (i0 + 3 < m) ? a[i0 + 3] : 0.f;
+          acc0 = fmaf(a0, r4.x, acc0);
+          acc1 = fmaf(a1, r4.y, acc1);
+          acc2 = fmaf(a2, r4.z, acc2);
+          acc3 = fmaf(a3, r4.w, acc3);
+        }
+        float c = (acc0 + acc1) + (acc2 + acc3);
+        for (int o = G >> 1; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+        const unsigned selb = (bm[j >> 5] >> (j & 31)) & 1u;
+        const unsigned long long key = selb ? 0ull : pack_key(c, j);
+        best = key > best ? key : best;
       }
-      if (i < m) a0 = fmaf(a[i], r[i], a0);
-      const unsigned selb = (bm[j >> 5] >> (j & 31)) & 1u;
-      const unsigned long long key = selb ? 0ull : pack_key(a0 + a1, j);
-      best = key > best ? key : best;
     }
     best = wave_max_u64(best);
     if (lane == 0) wkey[w] = best;
@@ -1148,22 +1166,36 @@ __global__ __launch_bounds__(kSmallThreads) void small_loop_kernel(
       eps = eps_rel * cj;
     }
     lr = lr_rel * cj;   // step size follows the selected correlation
-    // ---- selection record and the new Gram column
+    // ---- selection record and the new Gram column: wave w forms the partial
+    // sums of its dots l = w, w + 8, ... first, then reduces them
     if (tid == 0) {
       I.support[t] = j;
       *I.nsel = t + 1;
       if (!(cj <= 3.402823466e38f)) atomicOr(I.status, ST_NAN);
       bm[j >> 5] |= 1u << (j & 31);
-      sup[t] = j;
+      off[t] = j * ldl;
     }
     {
       const float* aj = Al + (size_t)j * ldl;
-      for (int l = w; l < t + 2; l += kSmallWaves) {
-        const float* v = (l < t) ? Al + (size_t)sup[l] * ldl : (l == t ? aj : yl);
+      float part[kSmallDots];
+#pragma unroll
+      for (int q = 0; q < kSmallDots; ++q) {
+        const int l = w + q * kSmallWaves;
         float acc = 0.f;
-        for (int i = lane; i < m; i += 64) acc = fmaf(aj[i], v[i], acc);
-        acc = wave_sum(acc);
-        if (lane == 0) gcol[l] = acc;
+        if (l < t + 2) {
+          const float* v = (l < t) ? Al + off[l] : (l == t ? aj : yl);
+          for (int i = lane; i < m; i += 64) acc = fmaf(aj[i], v[i], acc);
+        }
+        part[q] = acc;
+      }
+#pragma unroll
+      for (int q = 0; q < kSmallDots; ++q) part[q] = wave_sum(part[q]);
+      if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < kSmallDots; ++q) {
+          const int l = w + q * kSmallWaves;
+          if (l < t + 2) gcol[l] = part[q];
+        }
       }
     }
     __syncthreads();
@@ -1213,9 +1245,20 @@ __global__ __launch_bounds__(kSmallThreads) void small_loop_kernel(
         // bordered inverse: v = Ginv g, delta = gamma - g.v,
         // alpha = (b_t - g.x) / delta, x <- [x - alpha v; alpha]
         const float* grow = Gq + (size_t)(lane < ke ? lane : 0) * ldq;
-        float vr = 0.f;
-        if (lane < t)
-          for (int c = 0; c < t; ++c) vr = fmaf(grow[c], gcol[c], vr);
+        float a4[4] = {0.f, 0.f, 0.f, 0.f};
+        if (lane < t) {
+          // the 16-byte reads run to the next multiple of 4: Ginv has no
+          // entries in columns >= t yet, so g's tail does not contribute
+          for (int c = 0; c < t; c += 4) {
+            const float4 g4 = *reinterpret_cast<const float4*>(grow + c);
+            const float4 c4 = *reinterpret_cast<const float4*>(gcol + c);
+            a4[0] = fmaf(g4.x, c4.x, a4[0]);
+            a4[1] = fmaf(g4.y, c4.y, a4[1]);
+            a4[2] = fmaf(g4.z, c4.z, a4[2]);
+            a4[3] = fmaf(g4.w, c4.w, a4[3]);
+          }
+        }
+        const float vr = (a4[0] + a4[1]) + (a4[2] + a4[3]);
         const float gv = wave_sum(lane < t ? gcol[lane] * vr : 0.f);
         const float gx = wave_sum(lane < t ? gcol[lane] * sv : 0.f);
         const float gamma = gcol[t];
@@ -1246,18 +1289,19 @@ __global__ __launch_bounds__(kSmallThreads) void small_loop_kernel(
     if (!OMP) step += T;
     __syncthreads();
     if (!OMP) cur ^= (T & 1);   // every thread tracks the buffer holding s
-    // ---- residual r = y - A_S s
+    // ---- residual r = y - A_S s, eight selected columns per round
     {
       const float* sc = sbuf[OMP ? 1 : cur];
+      const int t1 = t + 1;
       for (int i = tid; i < m; i += kSmallThreads) {
-        float a0 = 0.f, a1 = 0.f;
+        float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         int l = 0;
-        for (; l + 1 <= t; l += 2) {
-          a0 = fmaf(Al[(size_t)sup[l] * ldl + i], sc[l], a0);
-          a1 = fmaf(Al[(size_t)sup[l + 1] * ldl + i], sc[l + 1], a1);
+        for (; l + 8 <= t1; l += 8) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) a[u] = fmaf(Al[off[l + u] + i], sc[l + u], a[u]);
         }
-        if (l <= t) a0 = fmaf(Al[(size_t)sup[l] * ldl + i], sc[l], a0);
-        r[i] = yl[i] - (a0 + a1);
+        for (int u = 0; l + u < t1; ++u) a[u] = fmaf(Al[off[l + u] + i], sc[l + u], a[u]);
+        r[i] = yl[i] - (((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7])));
       }
     }
     __syncthreads();

@@ -208,6 +208,23 @@ def test_prepared_batch_reruns(solvers):
         assert torch.equal(r2.support[i], ref.support[i])
 
 
+def test_plan_reuse_with_new_pointers(solvers):
+    """A batch with the shapes of the previous call reuses its plan with the
+    new data pointers: results equal those of a fresh handle."""
+    mk = lambda base: [W.single_small(base + i) for i in range(4)] + \
+        [W.single_small(base + 9, n=1500, m=120, k=24)]
+    sol = solvers["omp"]
+    sol.solve_batch(_items(mk(500)))
+    b = sol.solve_batch(_items(mk(600)))
+    fresh = C.Solver(0, method="omp", flags=sol.params.flags)
+    ref = fresh.solve_batch(_items(mk(600)))
+    torch.cuda.synchronize()
+    for i in range(5):
+        assert torch.equal(b.support[i], ref.support[i])
+        assert torch.equal(b.x[i], ref.x[i])
+    fresh.close()
+
+
 def test_edge_cases(solvers):
     sol = solvers["clomp"]
     base = W.single_small(7)
