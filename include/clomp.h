@@ -74,9 +74,11 @@ typedef enum {
                                         launch (ignored while capturing graphs);
                                         read with clomp_profile_read           */
 #define CLOMP_FLAG_RESIDUAL_FLOW 16u /* always use the residual schedule      */
-#define CLOMP_FLAG_CORR_FLOW 32u     /* always use the correlation-update
-                                        schedule (default: only for batches of
-                                        at most 8 signals)                     */
+#define CLOMP_FLAG_CORR_FLOW 32u     /* use the correlation-update schedule
+                                        (the default whenever H of the
+                                        iterated signals fits in 16 GB and the
+                                        staged vector in LDS; the flag only
+                                        documents the choice)                 */
 
 /*
  * Solver parameters.  The paper states the optimiser only as automatic
@@ -207,12 +209,16 @@ clomp_status_t clomp_grad(clomp_handle_t h, int32_t n, int32_t m, int64_t lda,
                           void* loss, void* hip_stream);
 
 /*
- * Schedules.  The residual schedule runs, per iteration, a scan c = A^T r with
- * the argmax, the Gram column, the coefficient update and r = y - A_S s.  The
- * correlation-update schedule (few large signals) uses c = A^T y - H s with
- * H[:, l] = A^T a_{S_l}: each iteration's pass over A computes the new column
- * of H and runs in the same launch as the coefficient update, and a scan of H
- * gives the next argmax.  Both compute the same correlations.
+ * Schedules.  Signals with k_eff <= 64 whose dictionary fits in LDS run the
+ * fused small-signal loop (one launch for the whole greedy loop of all of
+ * them).  The others are iterated, one launch sequence per iteration: the
+ * correlation-update schedule (default whenever it fits) uses
+ * c = A^T y - H s with H[:, l] = A^T a_{S_l}: each iteration's pass over A
+ * computes the new column of H and runs in the same launch as the
+ * coefficient update, and a scan of H gives the next argmax; the residual
+ * schedule runs, per iteration, a scan c = A^T r with the argmax, the Gram
+ * column, the coefficient update and r = y - A_S s.  All compute the same
+ * correlations.
  *
  * Phase timings gathered under CLOMP_FLAG_PROFILE, accumulated over every
  * solve since the last clomp_profile_reset.  Phases: 0 scan (residual

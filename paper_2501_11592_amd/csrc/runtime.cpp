@@ -272,8 +272,8 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
   P.order = order;
   const int qr_limit_floats = ((int)std::min<size_t>((size_t)h->lds_limit, 96 * 1024) - 1024) / 4;
   {
-    // correlation-update schedule: few signals, H within budget, the pass
-    // kernel's staged vector within LDS next to its 33 KB of static LDS
+    // correlation-update schedule: H within budget, the pass kernel's staged
+    // vector within LDS next to its 33 KB of static LDS
     size_t hbytes = 0;
     int mpad_max = 0;
     for (int s = 0; s < P.nbig; ++s) {
@@ -285,8 +285,9 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
                       (size_t)mpad_max * 4 + 34 * 1024 <= (size_t)h->lds_limit &&
                       hbytes <= (size_t)16 << 30;
     const uint32_t fl = prm.flags;
-    P.hflow = P.nbig > 0 && fits && !(fl & CLOMP_FLAG_RESIDUAL_FLOW) &&
-              ((fl & CLOMP_FLAG_CORR_FLOW) || P.nbig <= 8);
+    // measured faster than the residual schedule on every iterated workload
+    // (the pass and the coefficient update share one launch per iteration)
+    P.hflow = P.nbig > 0 && fits && !(fl & CLOMP_FLAG_RESIDUAL_FLOW);
   }
   snprintf(sigbuf, sizeof sigbuf, "h%d;f%d;", (int)P.hflow, count - P.nbig);
   P.sig += sigbuf;
