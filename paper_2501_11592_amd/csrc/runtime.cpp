@@ -57,6 +57,7 @@ struct Class {
   int kmax = 0;
   int nch = 0;                        // register-kernel vectors per lane (0: LDS kernels)
   std::vector<int> htile_prefix, ctile_prefix;
+  int cscan_sub = 1;                  // 64-atom sub-tiles per H-scan tile
   size_t htile_off = 0, ctile_off = 0;
 };
 
@@ -231,10 +232,12 @@ clomp_status_t check_batch_impl(clomp_ctx* h, const clomp_instance_t* inst, int3
   return CLOMP_OK;
 }
 
+// Lanes per atom: the most (up to 64) that still give every lane at least
+// 16 vectors of the column, so the per-atom reduction is amortised.
 int pick_lpa(int m, int vw) {
   const int nvec = (m + vw - 1) / vw;
   int lpa = 64;
-  while (lpa > 4 && lpa * 4 > nvec) lpa >>= 1;
+  while (lpa > 4 && lpa * 16 > nvec) lpa >>= 1;
   return lpa;
 }
 
@@ -396,6 +399,15 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     c.tile_off = P.tiles.size();
     c.row_off = P.rows.size();
     const int ng = kBlock / c.lpa;
+    {
+      // H-scan tiles of 64 * cscan_sub atoms: as large as keeps about four
+      // tiles per CU at the first iteration (many small tiles cost more to
+      // dispatch than their work)
+      long long t64 = 0;
+      for (int q = c.i0; q < c.i1; ++q) t64 += (P.insts[q].n + 63) / 64;
+      c.cscan_sub = 1;
+      while (c.cscan_sub < 16 && t64 / (2 * c.cscan_sub) >= 4LL * h->num_cu) c.cscan_sub *= 2;
+    }
     for (int q = c.i0; q < c.i1; ++q) {
       const Inst& d = P.insts[q];
       const size_t atom_bytes = (size_t)d.m_pad * esize;
@@ -419,7 +431,8 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
         for (int j0 = 0; j0 < d.n; j0 += hapt)
           P.htiles.push_back({q, j0, std::min(d.n, j0 + hapt), 0});
         c.htile_prefix.push_back((int)(P.htiles.size() - c.htile_off));
-        for (int j0 = 0; j0 < d.n; j0 += 64) P.ctiles.push_back({q, j0, std::min(d.n, j0 + 64), 0});
+        for (int j0 = 0; j0 < d.n; j0 += 64 * c.cscan_sub)
+          P.ctiles.push_back({q, j0, std::min(d.n, j0 + 64 * c.cscan_sub), 0});
         c.ctile_prefix.push_back((int)(P.ctiles.size() - c.ctile_off));
       }
       c.m_pad_max = std::max(c.m_pad_max, d.m_pad);

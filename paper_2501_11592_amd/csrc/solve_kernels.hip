@@ -1116,6 +1116,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_loop_kernel(
   if (tid < kSmallMaxK + 4) gcol[tid] = 0.f;
   __syncthreads();
   float sv = 0.f, mo = 0.f, ve = 0.f;   // wave 0, lane r: coefficient r and its moments
+  double b1p = 1.0, b2p = 1.0;          // beta^step, carried across iterations
   float lr = 0.f, eps = 0.f, sigma = 0.f;
   int step = 0, cur = 0, t = 0;
   for (; t < ke; ++t) {
@@ -1211,8 +1212,6 @@ __global__ __launch_bounds__(kSmallThreads) void small_loop_kernel(
         wave_sync();
         const float bb = (lane < t1) ? bsh[lane] : 0.f;
         const float* grow = Gq + (size_t)(lane < ke ? lane : 0) * ldq;
-        double b1p = pow((double)beta1, (double)step);
-        double b2p = pow((double)beta2, (double)step);
         int bufi = cur;
         for (int it = 0; it < T; ++it) {
           b1p *= beta1;
@@ -1781,56 +1780,58 @@ __global__ __launch_bounds__(kCscanThreads) void cscan_kernel(const Inst* __rest
   __shared__ float4 part[16][16];
   const ScanTile tile = tiles[blockIdx.x];
   const Inst& I = insts[tile.inst];
+  if (I.st->done) return;
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int q = lane & 15;
   const int L = 4 * w + (lane >> 4);
-  const int j = tile.j0 + 4 * q;          // tiles start at multiples of 64
-  // loads that do not depend on the sum are issued first (c0 is padded to a
-  // multiple of 256 entries, so the float4 read stays inside the buffer)
-  const int done = I.st->done;
-  float4 c0v = make_float4(0.f, 0.f, 0.f, 0.f);
-  unsigned bits = 0u;
-  if (w == 0 && lane < 16 && j < tile.j1) {
-    c0v = *reinterpret_cast<const float4*>(I.c0 + j);
-    bits = I.bitmap[j >> 5];
-  }
   const float* ssh = I.s;                  // t coefficients, read through L2
-  float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
-  if (!done && j < tile.j1) {
-    const float* Hj = I.H + j;
-    const long long ldh = I.ldh;
-    int l = L;
-    for (; l + 64 < t; l += 128) {
-      const float4 h0 = *reinterpret_cast<const float4*>(Hj + (long long)l * ldh);
-      const float4 h1 = *reinterpret_cast<const float4*>(Hj + (long long)(l + 64) * ldh);
-      const float s0 = ssh[l], s1 = ssh[l + 64];
-      a0.x = fmaf(h0.x, s0, a0.x); a0.y = fmaf(h0.y, s0, a0.y);
-      a0.z = fmaf(h0.z, s0, a0.z); a0.w = fmaf(h0.w, s0, a0.w);
-      a1.x = fmaf(h1.x, s1, a1.x); a1.y = fmaf(h1.y, s1, a1.y);
-      a1.z = fmaf(h1.z, s1, a1.z); a1.w = fmaf(h1.w, s1, a1.w);
+  const long long ldh = I.ldh;
+  unsigned long long key = 0ull;
+  // the tile spans one or more 64-atom sub-tiles (tiles start at multiples
+  // of 64); one atomicMax per tile
+  for (int jb = tile.j0; jb < tile.j1; jb += kCscanAtoms) {
+    const int j = jb + 4 * q;
+    // loads that do not depend on the sum are issued first (c0 is padded to
+    // a multiple of 256 entries, so the float4 read stays inside the buffer)
+    float4 c0v = make_float4(0.f, 0.f, 0.f, 0.f);
+    unsigned bits = 0u;
+    if (w == 0 && lane < 16 && j < tile.j1) {
+      c0v = *reinterpret_cast<const float4*>(I.c0 + j);
+      bits = I.bitmap[j >> 5];
     }
-    if (l < t) {
-      const float4 h0 = *reinterpret_cast<const float4*>(Hj + (long long)l * ldh);
-      const float s0 = ssh[l];
-      a0.x = fmaf(h0.x, s0, a0.x); a0.y = fmaf(h0.y, s0, a0.y);
-      a0.z = fmaf(h0.z, s0, a0.z); a0.w = fmaf(h0.w, s0, a0.w);
+    float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
+    if (j < tile.j1) {
+      const float* Hj = I.H + j;
+      int l = L;
+      for (; l + 64 < t; l += 128) {
+        const float4 h0 = *reinterpret_cast<const float4*>(Hj + (long long)l * ldh);
+        const float4 h1 = *reinterpret_cast<const float4*>(Hj + (long long)(l + 64) * ldh);
+        const float s0 = ssh[l], s1 = ssh[l + 64];
+        a0.x = fmaf(h0.x, s0, a0.x); a0.y = fmaf(h0.y, s0, a0.y);
+        a0.z = fmaf(h0.z, s0, a0.z); a0.w = fmaf(h0.w, s0, a0.w);
+        a1.x = fmaf(h1.x, s1, a1.x); a1.y = fmaf(h1.y, s1, a1.y);
+        a1.z = fmaf(h1.z, s1, a1.z); a1.w = fmaf(h1.w, s1, a1.w);
+      }
+      if (l < t) {
+        const float4 h0 = *reinterpret_cast<const float4*>(Hj + (long long)l * ldh);
+        const float s0 = ssh[l];
+        a0.x = fmaf(h0.x, s0, a0.x); a0.y = fmaf(h0.y, s0, a0.y);
+        a0.z = fmaf(h0.z, s0, a0.z); a0.w = fmaf(h0.w, s0, a0.w);
+      }
     }
-  }
-  float4 v = make_float4(a0.x + a1.x, a0.y + a1.y, a0.z + a1.z, a0.w + a1.w);
-  // the four slices of a wave (lanes q, q+16, q+32, q+48)
+    float4 v = make_float4(a0.x + a1.x, a0.y + a1.y, a0.z + a1.z, a0.w + a1.w);
+    // the four slices of a wave (lanes q, q+16, q+32, q+48)
 #pragma unroll
-  for (int o = 16; o < 64; o <<= 1) {
-    v.x += __shfl_xor(v.x, o, 64);
-    v.y += __shfl_xor(v.y, o, 64);
-    v.z += __shfl_xor(v.z, o, 64);
-    v.w += __shfl_xor(v.w, o, 64);
-  }
-  if (lane < 16) part[w][lane] = v;
-  __syncthreads();
-  if (w == 0 && !done) {
-    unsigned long long key = 0ull;
-    if (lane < 16) {
+    for (int o = 16; o < 64; o <<= 1) {
+      v.x += __shfl_xor(v.x, o, 64);
+      v.y += __shfl_xor(v.y, o, 64);
+      v.z += __shfl_xor(v.z, o, 64);
+      v.w += __shfl_xor(v.w, o, 64);
+    }
+    if (lane < 16) part[w][lane] = v;
+    __syncthreads();
+    if (w == 0 && lane < 16) {
       float4 sum = part[0][lane];
 #pragma unroll
       for (int ww = 1; ww < 16; ++ww) {
@@ -1850,6 +1851,9 @@ __global__ __launch_bounds__(kCscanThreads) void cscan_kernel(const Inst* __rest
         }
       }
     }
+    __syncthreads();   // part is rewritten by the next sub-tile
+  }
+  if (w == 0) {
     key = wave_max_u64(key);
     if (lane == 0 && key) atomicMax(&I.key[t & 1], key);
   }
