@@ -621,6 +621,8 @@ clomp_status_t launch_hflow(clomp_ctx* h, const Plan& P, int bf16, hipStream_t s
         }
         size_t lds = (size_t)c.m_pad_max * sizeof(float);
         lds = std::max(lds, (omp ? 6 : 1) * t1 * sizeof(float));
+        // split-row Adam (256 < t+1 <= 1024): s[R] and partials [1024/R][R]
+        if (!omp && t1 > 256 && t1 <= 1024) lds = std::max(lds, (size_t)2048 * sizeof(float));
         if (W > 1) lds = std::max(lds, (t1 + 4 + 32) * sizeof(float));
         PhaseScope ps(h, PH_PASS, st);
         HIP_TRY(launch_coef_pass(bf16, c.lpa, omp, d_insts + c.i0, nact, W, d_insts,

@@ -455,11 +455,14 @@ __device__ void adam_global_body(const Inst& I, int t, int T, float beta1, float
   }
   const float lr = I.st->lr, eps = I.st->eps;
   const int step0 = I.st->step;
+  double b1p = pow((double)beta1, (double)step0);
+  double b2p = pow((double)beta2, (double)step0);
   __syncthreads();
   for (int it = 0; it < T; ++it) {
-    const int step = step0 + it + 1;
-    const float bc1 = (float)(1.0 - pow((double)beta1, (double)step));
-    const float bc2 = (float)(1.0 - pow((double)beta2, (double)step));
+    b1p *= beta1;
+    b2p *= beta2;
+    const float bc1 = (float)(1.0 - b1p);
+    const float bc2 = (float)(1.0 - b2p);
 #pragma unroll
     for (int q = 0; q < kRPT; ++q) g[q] = 0.f;
     // rows of G are streamed from L2; four columns per pass keep four
@@ -514,6 +517,75 @@ __device__ void adam_global_body(const Inst& I, int t, int T, float beta1, float
     I.st->step = step0 + T;
     if (clear_key) *I.key = 0ull;
   }
+}
+
+// Fused-launch variant for 256 < t+1 <= 1024 on one 1024-thread workgroup:
+// P = 1024 / R threads per row (R = t+1 rounded up to a power of two), thread
+// (p, r) streaming the columns c = p, p+P, ... of row r from L2 (coalesced
+// along rows); the P partials of a row are added in LDS in a fixed order.
+// `lds` holds s[R] and the partials [P][R].
+__device__ void adam_split_body(const Inst& I, int t, int T, float beta1, float beta2,
+                                float* lds) {
+  constexpr int NT = 1024;   // the fused launch's workgroup size
+  const int t1 = t + 1;
+  int R = 256;
+  while (R < t1) R <<= 1;
+  const int P = NT / R;
+  const int tid = threadIdx.x;
+  const int p = tid / R, r = tid - p * R;
+  const bool own = p == 0 && r < t1;
+  const long long ldg = I.ldg;
+  const float* __restrict__ G = I.G;
+  float* ssh = lds;            // [R]
+  float* part = lds + R;       // [P][R]
+  float mo = 0.f, ve = 0.f, bb = 0.f;
+  if (tid < R) ssh[tid] = (tid < t1) ? I.s[tid] : 0.f;
+  if (own) {
+    mo = I.mo[r];
+    ve = I.ve[r];
+    bb = I.b[r];
+  }
+  const float lr = I.st->lr, eps = I.st->eps;
+  const int step0 = I.st->step;
+  double b1p = pow((double)beta1, (double)step0);
+  double b2p = pow((double)beta2, (double)step0);
+  __syncthreads();
+  for (int it = 0; it < T; ++it) {
+    b1p *= beta1;
+    b2p *= beta2;
+    const float ibc1 = __builtin_amdgcn_rcpf((float)(1.0 - b1p));
+    const float ibc2 = __builtin_amdgcn_rcpf((float)(1.0 - b2p));
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    if (r < t1) {
+      int c = p;
+      for (; c + 3 * P < t1; c += 4 * P) {
+        a0 = fmaf(G[(long long)c * ldg + r], ssh[c], a0);
+        a1 = fmaf(G[(long long)(c + P) * ldg + r], ssh[c + P], a1);
+        a2 = fmaf(G[(long long)(c + 2 * P) * ldg + r], ssh[c + 2 * P], a2);
+        a3 = fmaf(G[(long long)(c + 3 * P) * ldg + r], ssh[c + 3 * P], a3);
+      }
+      for (; c < t1; c += P) a0 = fmaf(G[(long long)c * ldg + r], ssh[c], a0);
+    }
+    part[p * R + r] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    if (own) {
+      float gs = 0.f;
+      for (int q = 0; q < P; ++q) gs += part[q * R + r];
+      const float gr = gs - bb;
+      mo = beta1 * mo + (1.f - beta1) * gr;
+      ve = beta2 * ve + (1.f - beta2) * (gr * gr);
+      const float mh = mo * ibc1;
+      const float vh = ve * ibc2;
+      ssh[r] = ssh[r] - lr * mh * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(vh) + eps);
+    }
+    __syncthreads();
+  }
+  if (own) {
+    I.s[r] = ssh[r];
+    I.mo[r] = mo;
+    I.ve[r] = ve;
+  }
+  if (tid == 0) I.st->step = step0 + T;
 }
 
 __global__ __launch_bounds__(kBlock) void adam_kernel(const Inst* __restrict__ insts, int t,
@@ -1334,7 +1406,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_loop_kernel(
 // coefficient update of iteration t (block 0 updates, the other blocks
 // stream A), hiding the serial Adam chain behind the HBM-bound pass.
 
-constexpr int kPassThreads = 1024;
+constexpr int kPassThreads = 1024;   // adam_split_body assumes this size
 
 // One tile of a pass over A with a staged vector v (zero padded):
 //   MODE 0: v = y, writes c0[j] = a_j^T y and the argmax key of |c0|
@@ -1751,6 +1823,8 @@ __global__ __launch_bounds__(kPassThreads) void coef_pass_kernel(
     __syncthreads();
     if (COEF == COEF_ADAM_REG)
       adam_reg_body(I, t, T, beta1, beta2, part, kPassThreads / 64, false);
+    else if (COEF == COEF_ADAM_GLOBAL && t + 1 <= kPassThreads)
+      adam_split_body(I, t, T, beta1, beta2, dsh);
     else if (COEF == COEF_ADAM_GLOBAL)
       adam_global_body<kPassThreads>(I, t, T, beta1, beta2, dsh, false);
     else

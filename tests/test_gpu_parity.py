@@ -225,6 +225,23 @@ def test_plan_reuse_with_new_pointers(solvers):
     fresh.close()
 
 
+def test_large_support_single_workgroup():
+    """k = 300 under the correlation-update schedule with coefficient teams
+    off: iterations with 256 < t+1 <= 300 run the split-row Adam of a single
+    1024-thread workgroup, reading G from memory."""
+    s = W.single_small(700, n=2048, m=1024, k=300)
+    sol = C.Solver(0, method="clomp", flags=C.FLAG_CORR_FLOW | C.FLAG_NO_FUSED_SMALL)
+    sol.set_tuning(team_min_rows=1 << 20)
+    out = sol.solve_batch(_items([s]))
+    torch.cuda.synchronize()
+    assert int(out.status[0]) == 0 and int(out.n_selected[0]) == 300
+    res = oracle_final_x("clomp", s.A, s.y, s.k)
+    kind = compare(out, 0, res, s.A, s.y, delta=FP32_DELTA, u=FP32_U, method="clomp",
+                   A_sel=s.A, k=s.k, tol_x=1e-5)
+    assert kind == "identical"    # the oracle calls this instance well separated
+    sol.close()
+
+
 def test_edge_cases(solvers):
     sol = solvers["clomp"]
     base = W.single_small(7)
