@@ -23,6 +23,8 @@ is derived from the loss, not from r.
 Modules
   omp        O1  plain OMP, least squares on the support by Householder QR
   clomp      O2  CLOMP: argmax selection + Adam steps on the masked coefficients
+  clomp_paper  F1  paper-mode CLOMP: normalised-threshold multi-selection, one
+                   Adam step per iteration, R iterations
   brute      O3  exhaustive support search for tiny instances
   grad       O4  loss/gradient of 1/2||A(mask*s) - y||^2;  O5 one Adam step
   lstsq      O6  least squares on a support;  FP64 residual norm
@@ -38,11 +40,13 @@ from .lstsq import lstsq_support, resid_norm_fp64
 from .grad import grad_fp64, adam_step_fp64
 from .omp import omp_fp64
 from .clomp import clomp_fp64, ClompParams
+from .clomp_paper import clomp_paper_fp64, PaperParams
 from .brute import bruteforce_support
 from .separation import well_separated
 
 __all__ = [
     "lstsq_support", "resid_norm_fp64", "grad_fp64", "adam_step_fp64",
-    "omp_fp64", "clomp_fp64", "ClompParams", "bruteforce_support",
+    "omp_fp64", "clomp_fp64", "ClompParams", "clomp_paper_fp64", "PaperParams",
+    "bruteforce_support",
     "well_separated",
 ]

@@ -7,7 +7,8 @@ are nearly tied, any rounding difference (float32 versus float64, bfloat16
 storage, a different summation order) may flip the choice, and every later
 iteration then differs.  Support identity between the GPU path and this oracle
 is therefore asserted only on instances where
-  1. every iteration's relative gap between the best and second-best score is
+  1. every iteration's relative gap between the best and second-best score
+     (paper mode: between the threshold and the nearest unselected score) is
      at least delta, and
   2. the oracle's support is unchanged when every entry of A and y is
      multiplied by (1 + u * e) with e a random sign, for two seeds.
@@ -18,12 +19,16 @@ per-iteration gap alone does not see.
 import numpy as np
 
 from .clomp import clomp_fp64, ClompParams
+from .clomp_paper import clomp_paper_fp64
 from .omp import omp_fp64
 
 
 def _run(method, A, y, k, params, A_refine):
     if method == "omp":
         return omp_fp64(A, y, k, resid_tol=params.resid_tol)
+    if method == "clomp_paper":
+        # gaps: distance of the nearest unselected score to the threshold
+        return clomp_paper_fp64(A, y, k, params, A_refine=A_refine)
     return clomp_fp64(A, y, k, params, A_refine=A_refine)
 
 

@@ -13,7 +13,8 @@ import os
 import numpy as np
 import pytest
 
-from oracle import (omp_fp64, clomp_fp64, ClompParams, lstsq_support,
+from oracle import (omp_fp64, clomp_fp64, ClompParams, clomp_paper_fp64, PaperParams,
+                    lstsq_support,
                     resid_norm_fp64, grad_fp64, adam_step_fp64,
                     bruteforce_support, well_separated)
 from oracle.omp import ST_ZERO_Y, ST_K_CAPPED, ST_NAN, ST_EARLY_STOP
@@ -358,6 +359,73 @@ def test_clomp_flags():
     assert r.status & ST_ZERO_Y and r.support == []
     r = clomp_fp64(A, y, 10)
     assert r.status & ST_K_CAPPED and len(r.support) == 6
+
+
+# ---------------------------------------------------------------- F1 paper mode
+def test_paper_mode_matches_autograd_and_torch_adam_rendering():
+    """Independent rendering of paper-mode CLOMP with framework pieces: the
+    normalised scores |c| / max|c| cut at T_h, the mask OR-ed, then one
+    autograd backward of 1/2 ||A(mask*s) - y||^2 and one torch.optim.Adam step
+    per iteration with lr = lr_rel * max|c|."""
+    torch = pytest.importorskip("torch")
+    for seed in range(3):
+        A, y, _, _ = gaussian_instance(40 + seed, 24, 64, 4)
+        y = y + 0.01 * np.random.default_rng(seed).standard_normal(24)
+        P = PaperParams(threshold=0.6, max_iters=25, lr_rel=0.1)
+        ref = clomp_paper_fp64(A, y, 24, P)
+        At, yt = torch.tensor(A), torch.tensor(y)
+        s = torch.zeros(64, dtype=torch.float64, requires_grad=True)
+        mask = torch.zeros(64, dtype=torch.bool)
+        opt = None
+        for it in range(25):
+            with torch.no_grad():
+                c = At.T @ (yt - At @ torch.where(mask, s, torch.zeros_like(s)))
+                cmax = float(c.abs().max())
+                if it == 0:
+                    opt = torch.optim.Adam([s], lr=0.1 * cmax, betas=(0.9, 0.999),
+                                           eps=1e-8 * cmax, foreach=False)
+                opt.param_groups[0]["lr"] = 0.1 * cmax
+                new = (~mask) & (c.abs() / cmax >= 0.6)
+                if int(mask.sum()) + int(new.sum()) <= 24:
+                    mask |= new
+            opt.zero_grad()
+            loss = 0.5 * ((At @ torch.where(mask, s, torch.zeros_like(s)) - yt) ** 2).sum()
+            loss.backward()
+            opt.step()
+        S = torch.nonzero(mask).flatten().tolist()
+        assert S == ref.support
+        np.testing.assert_allclose(s.detach().numpy()[S], ref.extra["s_adam"],
+                                   rtol=1e-11, atol=1e-13)
+
+
+def test_paper_mode_orthonormal_first_batch_closed_form():
+    """A orthonormal (m = n) and y = A s: c = A^T y = s at the first
+    iteration, so the first batch is { j : |s_j| >= T_h max|s| }."""
+    rng = np.random.default_rng(5)
+    Q, _ = np.linalg.qr(rng.standard_normal((40, 40)))
+    strue = rng.standard_normal(40) * (rng.random(40) < 0.3)
+    res = clomp_paper_fp64(Q, Q @ strue, 40, PaperParams(threshold=0.5, max_iters=1))
+    expect = np.flatnonzero(np.abs(strue) >= 0.5 * np.abs(strue).max()).tolist()
+    assert res.extra["batches"] == [expect] and res.support == expect
+
+
+def test_paper_mode_power_of_two_scaling_and_invariants():
+    A, y, _, _ = gaussian_instance(44, 32, 128, 6)
+    y = y + 0.01 * np.random.default_rng(1).standard_normal(32)
+    P = PaperParams(max_iters=60)
+    a = clomp_paper_fp64(A, y, 10, P)
+    for p in (-5, 9):
+        b = clomp_paper_fp64(A, y * 2.0 ** p, 10, P)
+        assert b.support == a.support
+        np.testing.assert_array_equal(b.extra["s_adam"], a.extra["s_adam"] * 2.0 ** p)
+    # the support is the union of the accepted batches, within k_eff, and a
+    # refused batch sets the K-capped bit
+    union = sorted(j for bt in a.extra["batches"] for j in bt)
+    assert union == a.support and len(a.support) <= 10
+    full = clomp_paper_fp64(A, y, 32, P)
+    assert len(full.support) >= len(a.support)
+    if len(a.support) < len(full.support):
+        assert a.status & ST_K_CAPPED
 
 
 def test_workload_generators_are_deterministic():
