@@ -25,6 +25,7 @@ Modules
   clomp      O2  CLOMP: argmax selection + Adam steps on the masked coefficients
   clomp_paper  F1  paper-mode CLOMP: normalised-threshold multi-selection, one
                    Adam step per iteration, R iterations
+  iht        F4  normalised iterative hard thresholding (comparison method)
   brute      O3  exhaustive support search for tiny instances
   grad       O4  loss/gradient of 1/2||A(mask*s) - y||^2;  O5 one Adam step
   lstsq      O6  least squares on a support;  FP64 residual norm
@@ -41,12 +42,13 @@ from .grad import grad_fp64, adam_step_fp64
 from .omp import omp_fp64
 from .clomp import clomp_fp64, ClompParams
 from .clomp_paper import clomp_paper_fp64, PaperParams
+from .iht import iht_fp64
 from .brute import bruteforce_support
 from .separation import well_separated
 
 __all__ = [
     "lstsq_support", "resid_norm_fp64", "grad_fp64", "adam_step_fp64",
-    "omp_fp64", "clomp_fp64", "ClompParams", "clomp_paper_fp64", "PaperParams",
+    "omp_fp64", "clomp_fp64", "ClompParams", "clomp_paper_fp64", "PaperParams", "iht_fp64",
     "bruteforce_support",
     "well_separated",
 ]

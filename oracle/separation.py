@@ -21,11 +21,16 @@ import numpy as np
 from .clomp import clomp_fp64, ClompParams
 from .clomp_paper import clomp_paper_fp64
 from .omp import omp_fp64
+from .iht import iht_fp64
 
 
 def _run(method, A, y, k, params, A_refine):
     if method == "omp":
         return omp_fp64(A, y, k, resid_tol=params.resid_tol)
+    if method == "iht":
+        # gaps: relative gap at the top-K boundary of every iteration
+        return iht_fp64(A, y, k, max_iters=getattr(params, "max_iters", 200),
+                        A_refine=A_refine)
     if method == "clomp_paper":
         # gaps: distance of the nearest unselected score to the threshold
         return clomp_paper_fp64(A, y, k, params, A_refine=A_refine)

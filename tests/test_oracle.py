@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 from oracle import (omp_fp64, clomp_fp64, ClompParams, clomp_paper_fp64, PaperParams,
-                    lstsq_support,
+                    iht_fp64, lstsq_support,
                     resid_norm_fp64, grad_fp64, adam_step_fp64,
                     bruteforce_support, well_separated)
 from oracle.omp import ST_ZERO_Y, ST_K_CAPPED, ST_NAN, ST_EARLY_STOP
@@ -426,6 +426,86 @@ def test_paper_mode_power_of_two_scaling_and_invariants():
     assert len(full.support) >= len(a.support)
     if len(a.support) < len(full.support):
         assert a.status & ST_K_CAPPED
+
+
+# ---------------------------------------------------------------- F4 IHT
+def test_iht_top_k_ties_and_nan():
+    from oracle.iht import top_k
+    z = np.array([1.0, -3.0, 3.0, 0.5, np.nan, -1.0, 3.0])
+    sel, _ = top_k(z, 3)        # NaN first, then |3| at indices 1, 2 (lowest of three)
+    assert sel.tolist() == [1, 2, 4]
+    sel, gap = top_k(np.array([4.0, -2.0, 1.0]), 2)
+    assert sel.tolist() == [0, 1] and gap == pytest.approx(0.5)
+
+
+def test_iht_orthonormal_closed_form():
+    """A orthonormal: the normalised step is exactly 1 and one iteration
+    lands on H_K(A^T y) = H_K(s), a fixed point of every later iteration."""
+    rng = np.random.default_rng(8)
+    Q, _ = np.linalg.qr(rng.standard_normal((50, 50)))
+    strue = rng.standard_normal(50)
+    y = Q @ strue
+    K = 7
+    expect = np.sort(np.argsort(-np.abs(strue), kind="stable")[:K])
+    for R in (1, 6):
+        res = iht_fp64(Q, y, K, max_iters=R)
+        assert res.support == expect.tolist()
+        np.testing.assert_allclose(res.extra["s_iht"], strue[expect], rtol=1e-12, atol=1e-14)
+        np.testing.assert_allclose(res.extra["steps"], 1.0, rtol=1e-12)
+
+
+def test_iht_exact_recovery_noiseless():
+    """Noiseless Gaussian k-sparse instances (n=256, m=64, k=8): the k-sparse
+    solution is unique and normalised IHT reaches it."""
+    ok = 0
+    for seed in range(20):
+        sig = W.single_small(900 + seed)
+        res = iht_fp64(sig.A, sig.y, 8)
+        if res.support == sig.support.tolist():
+            ok += 1
+            np.testing.assert_allclose(res.x, sig.s, rtol=0, atol=1e-7)
+    assert ok >= 19
+
+
+def test_iht_matches_autograd_and_torch_topk_rendering():
+    """Independent rendering: the gradient of 1/2||As - y||^2 by autograd and
+    the hard threshold by a stable descending torch sort."""
+    torch = pytest.importorskip("torch")
+    for seed in range(3):
+        A, y, _, _ = gaussian_instance(60 + seed, 30, 90, 5)
+        y = y + 0.01 * np.random.default_rng(seed).standard_normal(30)
+        ref = iht_fp64(A, y, 6, max_iters=15)
+        At, yt = torch.tensor(A), torch.tensor(y)
+        s = torch.zeros(90, dtype=torch.float64)
+        G = None
+        for it in range(15):
+            sv = s.clone().requires_grad_(True)
+            loss = 0.5 * ((At @ sv - yt) ** 2).sum()
+            loss.backward()
+            g = -sv.grad
+            if G is None:
+                G = torch.sort(torch.sort(-g.abs(), stable=True).indices[:6]).values
+            gG = g[G]
+            t = float((gG ** 2).sum() / ((At[:, G] @ gG) ** 2).sum())
+            z = s + t * g
+            G = torch.sort(torch.sort(-z.abs(), stable=True).indices[:6]).values
+            s = torch.zeros(90, dtype=torch.float64)
+            s[G] = z[G]
+        assert G.tolist() == ref.support
+        np.testing.assert_allclose(s[G].numpy(), ref.extra["s_iht"], rtol=1e-10, atol=1e-13)
+
+
+def test_iht_power_of_two_scaling_and_permutation():
+    A, y, _, _ = gaussian_instance(64, 32, 128, 6)
+    y = y + 0.01 * np.random.default_rng(2).standard_normal(32)
+    a = iht_fp64(A, y, 6, max_iters=40)
+    b = iht_fp64(A, y * 2.0 ** 7, 6, max_iters=40)
+    assert b.support == a.support
+    np.testing.assert_array_equal(b.extra["s_iht"], a.extra["s_iht"] * 2.0 ** 7)
+    perm = np.random.default_rng(3).permutation(128)
+    c = iht_fp64(A[:, perm], y, 6, max_iters=40)
+    assert sorted(int(perm[j]) for j in c.support) == a.support
+    np.testing.assert_allclose(c.x, a.x[perm], rtol=0, atol=1e-10)
 
 
 def test_workload_generators_are_deterministic():
