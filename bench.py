@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--sr", type=float, default=0.3, help="image workload sampling rate")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-iht", action="store_true", help="skip the IHT comparison leg")
     ap.add_argument("--flow", default="auto", choices=["auto", "resid", "corr"],
                     help="schedule: library default, residual, or correlation update")
     ap.add_argument("--profile-steps", type=int, default=2)
@@ -198,7 +199,8 @@ def roofline(p, items=None, method="clomp"):
         name = "coef_pass_kernel (Adam/OMP block + pass h = A^T a_j over A)"
         nl, ms, byt = p["launches"]["pass"], p["ms"]["pass"], p["pass_bytes"]
     else:
-        name = ("cscan/ypass kernels (c = c0 - H s, argmax)" if p["launches"]["pass"] > 0
+        name = ("iht_grad_kernel (g = A^T r over A)" if method == "iht" else
+                "cscan/ypass kernels (c = c0 - H s, argmax)" if p["launches"]["pass"] > 0
                 else "scan_reg_kernel (c = A^T r, |c|, argmax)")
         nl, ms, byt = max(1, p["launches"]["scan"]), p["ms"]["scan"], p["scan_bytes"]
     k_ms = ms / nl
@@ -229,15 +231,18 @@ def main():
     stream = torch.cuda.Stream(torch.device("cuda", 0))
     flow_flag = {"auto": 0, "resid": C.FLAG_RESIDUAL_FLOW, "corr": C.FLAG_CORR_FLOW}[args.flow]
     flags = (0 if args.no_graph else C.FLAG_GRAPH) | flow_flag
-    solvers = {m: C.Solver(0, method=m, flags=flags) for m in ("clomp", "omp")}
-    items = {"clomp": wl["clomp_items"], "omp": wl["omp_items"]}
+    methods = ("clomp", "omp") if args.no_iht else ("clomp", "omp", "iht")
+    solvers = {m: C.Solver(0, method=m, flags=flags) for m in methods}
+    # IHT (200 iterations, the experiments' comparison method) runs on the
+    # same storage as CLOMP
+    items = {"clomp": wl["clomp_items"], "omp": wl["omp_items"], "iht": wl["clomp_items"]}
     count = len(items["clomp"])
 
     # descriptors and outputs packed once (inputs stay resident); every step
     # launches the whole batch through the C ABI
-    preps = {m: solvers[m].prepare(items[m], stream=stream) for m in ("clomp", "omp")}
+    preps = {m: solvers[m].prepare(items[m], stream=stream) for m in methods}
     timings, outs = {}, {}
-    for method in ("clomp", "omp"):
+    for method in methods:
         log(f"{method} warmup {args.warmup}")
         for _ in range(args.warmup):
             solvers[method].run(preps[method], stream=stream)
@@ -258,7 +263,7 @@ def main():
 
     # live per-phase timing with HIP events on the launch stream (no graph)
     prof = {}
-    for method in ("clomp", "omp"):
+    for method in methods:
         ps = C.Solver(0, method=method, flags=C.FLAG_PROFILE | flow_flag)
         pp = ps.prepare(items[method], stream=stream)
         ps.run(pp, stream=stream)
@@ -296,6 +301,9 @@ def main():
                 "ms_per_step": 1e3 * timings["omp"],
                 "dtype": "f32" if wl["name"] == "flat" else wl["dtype"]},
         "clomp_vs_omp": timings["omp"] / timings["clomp"],
+        "iht": ({"value": count / timings["iht"], "unit": "signals/s",
+                 "ms_per_step": 1e3 * timings["iht"], "iterations": 200,
+                 "dtype": wl["dtype"]} if "iht" in timings else None),
         "accuracy": acc,
         "accuracy_gate_1e-3": (all(a["rel_err"] <= 1e-3 for a in acc.values()) if acc else None),
         "status_flags_nonzero": {m: int((st[m] != 0).sum()) for m in st},
@@ -303,6 +311,7 @@ def main():
                               for m in prof},
         "roofline": roofline(prof["clomp"], items["clomp"], "clomp"),
         "roofline_omp": roofline(prof["omp"], items["omp"], "omp"),
+        "roofline_iht": roofline(prof["iht"], items["iht"], "iht") if "iht" in prof else None,
         "cpu_baseline": cpu,
     }
     line["roofline"]["traffic"] = measured_traffic(wl["name"], line["roofline"]["kernel"])

@@ -49,7 +49,9 @@ typedef enum { CLOMP_F32 = 0, CLOMP_BF16 = 1, CLOMP_F64 = 2 } clomp_dtype_t;
 
 typedef enum {
   CLOMP_METHOD_CLOMP = 0,  /* Adam steps on the masked coefficients */
-  CLOMP_METHOD_OMP = 1     /* plain OMP: least squares on the support */
+  CLOMP_METHOD_OMP = 1,    /* plain OMP: least squares on the support */
+  CLOMP_METHOD_IHT = 2     /* normalised iterative hard thresholding to K =
+                              k_eff atoms (the experiments' comparison method) */
 } clomp_method_t;
 
 /* Per-instance status bits (written to clomp_instance_t.status). */
@@ -62,7 +64,9 @@ typedef enum {
 /* Solver flags (clomp_params_t.flags). */
 #define CLOMP_FLAG_GRAPH 1u          /* capture the launch sequence of a batch
                                         shape into a HIP graph and replay it on
-                                        later calls with the same shape        */
+                                        later calls with the same shape (on a
+                                        created stream; calls on the default
+                                        stream launch eagerly)                 */
 #define CLOMP_FLAG_NO_FUSED_SMALL 2u /* never use the fused small-signal
                                         loop (one workgroup runs a signal's
                                         whole greedy loop with its dictionary
@@ -85,8 +89,9 @@ typedef enum {
  * differentiation and back-propagation on learnable s (Methods, "Coefficients
  * learning on OMP"); everything below is this library's fixed reading, the
  * same values the reference oracle uses:
- *   method       CLOMP (default) or plain OMP
- *   inner_steps  T, Adam steps per selected atom (default 32)
+ *   method       CLOMP (default), plain OMP, or IHT
+ *   inner_steps  CLOMP: T, Adam steps per selected atom (default 32);
+ *                IHT: the number of iterations R (the experiments use 200)
  *   lr_rel       learning rate of iteration t: lr_t = lr_rel * |c_j|, the
  *                correlation of the atom selected at t (default 0.05)
  *   beta1/beta2  Adam moment decays (0.9 / 0.999); eps = eps_rel * sigma with

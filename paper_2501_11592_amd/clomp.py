@@ -21,7 +21,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libclomp.so")
 
 F32, BF16, F64 = 0, 1, 2
-METHOD_CLOMP, METHOD_OMP = 0, 1
+METHOD_CLOMP, METHOD_OMP, METHOD_IHT = 0, 1, 2
+METHODS = {"clomp": METHOD_CLOMP, "omp": METHOD_OMP, "iht": METHOD_IHT}
 ST_NAN, ST_K_CAPPED, ST_ZERO_Y, ST_REFINE_INACCURATE, ST_WATCHDOG = 1, 2, 4, 8, 32
 FLAG_GRAPH, FLAG_NO_FUSED_SMALL, FLAG_AUTOTUNE, FLAG_PROFILE = 1, 2, 4, 8
 FLAG_RESIDUAL_FLOW, FLAG_CORR_FLOW = 16, 32
@@ -169,7 +170,7 @@ class BatchResult:
 class Solver:
     """A library handle bound to one device, holding the solver parameters."""
 
-    def __init__(self, device=0, method="clomp", inner_steps=32, lr_rel=0.05,
+    def __init__(self, device=0, method="clomp", inner_steps=None, lr_rel=0.05,
                  beta1=0.9, beta2=0.999, eps_rel=1e-8, refine_iters=0,
                  refine_tol=0.0, flags=0):
         lib = load_library()
@@ -177,7 +178,11 @@ class Solver:
             raise ClompError("no GPU available: the CLOMP library runs only on the device")
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         p = default_params()
-        p.method = METHOD_OMP if method == "omp" else METHOD_CLOMP
+        if method not in METHODS:
+            raise ClompError(f"unknown method {method!r}")
+        p.method = METHODS[method]
+        if inner_steps is None:   # CLOMP: Adam steps per atom; IHT: iterations
+            inner_steps = 200 if method == "iht" else 32
         p.inner_steps, p.lr_rel, p.beta1, p.beta2 = inner_steps, lr_rel, beta1, beta2
         p.eps_rel, p.refine_iters, p.refine_tol, p.flags = eps_rel, refine_iters, refine_tol, flags
         self.params = p
@@ -200,7 +205,7 @@ class Solver:
     def set_params(self, **kw):
         for key, v in kw.items():
             if key == "method":
-                v = METHOD_OMP if v == "omp" else METHOD_CLOMP
+                v = METHODS[v]
             setattr(self.params, key, v)
         _check(self._h, load_library().clomp_set_params(self._h, ctypes.byref(self.params)),
                "clomp_set_params")

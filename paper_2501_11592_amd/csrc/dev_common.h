@@ -76,6 +76,8 @@ struct Inst {
   long long ldh;
   unsigned long long* team;   // [2*k_eff + 2*kTeamMax] tagged words exchanged by a team
                               // (correlation-update schedule; zeroed at solve start)
+  float* gbuf;         // IHT: [ldh] g = A^T r of the current iteration
+  float* sfull;        // IHT: [n] dense coefficients (zero off the support)
   double* npart;       // [n_rowtiles] FP64 residual-norm partial sums
   float* qpart;        // [n_rowtiles] CGLS ||q||^2 partial sums
   unsigned long long* key;

@@ -36,6 +36,17 @@ hipError_t set_max_lds(size_t bytes);
 // Events the next single-kernel launch records around itself (profiling).
 void set_launch_events(hipEvent_t start, hipEvent_t stop);
 
+// Normalised IHT (one iteration = optional residual, gradient scan, step
+// denominator, thresholded update).  rows mode 0: r = y - A_G s_G; mode 1:
+// partial ||A_G g_G||^2.  select mode 0: support = top-K |g|; mode 1: the
+// normalised step and s = H_K(s + t g).
+hipError_t launch_iht_grad(int bf16, int lpa, const Inst* d, const ScanTile* tiles, int ntiles,
+                           int r_lds, int first, hipStream_t s);
+hipError_t launch_iht_rows(int bf16, int mode, const Inst* d, const RowTile* tiles, int ntiles,
+                           int kmax, hipStream_t s);
+// nmax: the largest n among the signals (picks threads and chunk size).
+hipError_t launch_iht_select(const Inst* dc, int nact, int mode, int nmax, hipStream_t s);
+
 // Fused greedy loop of the signals list[0..count): one 256-thread workgroup
 // per signal with its dictionary in LDS (k_eff <= kSmallMaxK, dynamic LDS of
 // small_lds_bytes for the largest signal).

@@ -58,6 +58,7 @@ struct Class {
   int nch = 0;                        // register-kernel vectors per lane (0: LDS kernels)
   std::vector<int> htile_prefix, ctile_prefix;
   int cscan_sub = 1;                  // 64-atom sub-tiles per H-scan tile
+  int nmax = 0;                       // largest n of the class
   size_t htile_off = 0, ctile_off = 0;
 };
 
@@ -177,8 +178,11 @@ clomp_status_t hip_fail(clomp_ctx* h, hipError_t e, const char* what) {
 
 clomp_status_t check_params(clomp_ctx* h, const clomp_params_t* p) {
   if (!p) return fail(h, CLOMP_INVALID_ARGUMENT, "params is NULL");
-  if (p->method != CLOMP_METHOD_CLOMP && p->method != CLOMP_METHOD_OMP)
+  if (p->method != CLOMP_METHOD_CLOMP && p->method != CLOMP_METHOD_OMP &&
+      p->method != CLOMP_METHOD_IHT)
     return fail(h, CLOMP_INVALID_ARGUMENT, "unknown method %d", p->method);
+  if (p->method == CLOMP_METHOD_IHT && p->inner_steps < 1)
+    return fail(h, CLOMP_INVALID_ARGUMENT, "IHT needs inner_steps (iterations) >= 1");
   if (p->inner_steps < 0 || p->inner_steps > 100000)
     return fail(h, CLOMP_INVALID_ARGUMENT, "inner_steps %d out of range", p->inner_steps);
   if (!(p->beta1 >= 0.f && p->beta1 < 1.f) || !(p->beta2 >= 0.f && p->beta2 < 1.f))
@@ -246,6 +250,7 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
                 int scan_kb, int pass_kb) {
   const clomp_params_t& prm = h->params;
   const bool omp = prm.method == CLOMP_METHOD_OMP;
+  const bool iht = prm.method == CLOMP_METHOD_IHT;
   const int vw = bf16 ? 8 : 4;
   const size_t esize = bf16 ? 2 : 4;
   char sigbuf[96];
@@ -254,7 +259,7 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
   std::vector<int> order(count);
   std::vector<int> lpa(count), keff(count);
   std::vector<char> fused(count, 0);
-  const bool allow_fused = !(prm.flags & CLOMP_FLAG_NO_FUSED_SMALL);
+  const bool allow_fused = !(prm.flags & CLOMP_FLAG_NO_FUSED_SMALL) && !iht;
   for (int i = 0; i < count; ++i) {
     order[i] = i;
     lpa[i] = pick_lpa(inst[i].m, vw);
@@ -290,7 +295,7 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     const uint32_t fl = prm.flags;
     // measured faster than the residual schedule on every iterated workload
     // (the pass and the coefficient update share one launch per iteration)
-    P.hflow = P.nbig > 0 && fits && !(fl & CLOMP_FLAG_RESIDUAL_FLOW);
+    P.hflow = P.nbig > 0 && fits && !(fl & CLOMP_FLAG_RESIDUAL_FLOW) && !iht;
   }
   snprintf(sigbuf, sizeof sigbuf, "h%d;f%d;", (int)P.hflow, count - P.nbig);
   P.sig += sigbuf;
@@ -332,7 +337,7 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
       return o;
     };
     const size_t o_r = take(sizeof(float) * 2 * d.m_pad);
-    const size_t o_G = take(sizeof(float) * (size_t)d.k_eff * d.ldg);
+    const size_t o_G = iht ? 0 : take(sizeof(float) * (size_t)d.k_eff * d.ldg);
     const size_t o_b = take(sizeof(float) * d.k_eff);
     const size_t o_s = take(sizeof(float) * d.k_eff);
     const size_t o_mo = take(sizeof(float) * d.k_eff);
@@ -341,8 +346,14 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     const size_t o_z = take(sizeof(float) * d.k_eff);
     const size_t o_L = omp ? take(sizeof(float) * (size_t)d.k_eff * d.ldg) : 0;
     const size_t o_cg = use_qr ? 0 : take(sizeof(float) * (3 * (size_t)d.m_pad + 3 * d.k_eff));
-    size_t o_c0 = 0, o_H = 0, o_dg = 0, o_team = 0;
+    size_t o_c0 = 0, o_H = 0, o_dg = 0, o_team = 0, o_gb = 0, o_sf = 0;
     const bool hf = P.hflow && s < P.nbig;
+    if (iht) {
+      d.ldh = round_up_int(d.n, 256);
+      o_c0 = take(sizeof(float) * d.ldh);
+      o_gb = take(sizeof(float) * d.ldh);
+      o_sf = take(sizeof(float) * d.ldh);
+    }
     if (hf) {
       d.ldh = round_up_int(d.n, 256);
       o_c0 = take(sizeof(float) * d.ldh);
@@ -357,7 +368,7 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     const size_t o_st = take(sizeof(InstState));
     // store offsets in the pointer fields for now (+1 so 0 means "absent")
     d.r = (float*)(o_r + 1);
-    d.G = (float*)(o_G + 1);
+    d.G = iht ? nullptr : (float*)(o_G + 1);
     d.b = (float*)(o_b + 1);
     d.s = (float*)(o_s + 1);
     d.mo = (float*)(o_mo + 1);
@@ -366,7 +377,9 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     d.z = (float*)(o_z + 1);
     d.Linv = omp ? (float*)(o_L + 1) : nullptr;
     d.cg = use_qr ? nullptr : (float*)(o_cg + 1);
-    d.c0 = hf ? (float*)(o_c0 + 1) : nullptr;
+    d.c0 = (hf || iht) ? (float*)(o_c0 + 1) : nullptr;
+    d.gbuf = iht ? (float*)(o_gb + 1) : nullptr;
+    d.sfull = iht ? (float*)(o_sf + 1) : nullptr;
     d.dg = hf ? (float*)(o_dg + 1) : nullptr;
     d.team = hf ? (unsigned long long*)(o_team + 1) : nullptr;
     d.H = hf ? (float*)(o_H + 1) : nullptr;
@@ -437,6 +450,7 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
       }
       c.m_pad_max = std::max(c.m_pad_max, d.m_pad);
       c.kmax = std::max(c.kmax, d.k_eff);
+      c.nmax = std::max(c.nmax, d.n);
     }
     // register kernels when every lane's share of the longest column fits in
     // 64 registers
@@ -647,6 +661,53 @@ clomp_status_t launch_hflow(clomp_ctx* h, const Plan& P, int bf16, hipStream_t s
   return CLOMP_OK;
 }
 
+// Iterations of normalised IHT (inner_steps of them) for every class.
+clomp_status_t launch_iht(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st) {
+  char* tb = reinterpret_cast<char*>(h->tables.p);
+  const Inst* d_insts = reinterpret_cast<const Inst*>(tb + P.off_insts);
+  const ScanTile* d_tiles = reinterpret_cast<const ScanTile*>(tb + P.off_tiles);
+  const RowTile* d_rows = reinterpret_cast<const RowTile*>(tb + P.off_rows);
+  const int lds_cap = (h->lds_limit - 1024) / 4;
+  const double esz = bf16 ? 2.0 : 4.0;
+  for (int it = 0; it < h->params.inner_steps; ++it) {
+    for (const Class& c : P.classes) {
+      const int nall = c.i1 - c.i0;
+      const int ntiles = c.tile_prefix[nall];
+      const int nrows = c.row_prefix[nall];
+      const int r_lds = (c.m_pad_max <= lds_cap) ? c.m_pad_max : 0;
+      if (it > 0) {
+        PhaseScope ps(h, PH_RESID, st);
+        HIP_TRY(launch_iht_rows(bf16, 0, d_insts, d_rows + c.row_off, nrows, c.kmax, st),
+                "iht resid");
+      }
+      {
+        PhaseScope ps(h, PH_SCAN, st);
+        HIP_TRY(launch_iht_grad(bf16, c.lpa, d_insts, d_tiles + c.tile_off, ntiles, r_lds,
+                                it == 0, st),
+                "iht grad");
+        if (h->profiling)
+          for (int q = c.i0; q < c.i1; ++q)
+            h->scan_bytes += (double)P.insts[q].m * P.insts[q].n * esz + 4.0 * P.insts[q].m +
+                             4.0 * P.insts[q].n;
+      }
+      if (it == 0) {
+        PhaseScope ps(h, PH_COEF, st);
+        HIP_TRY(launch_iht_select(d_insts + c.i0, nall, 0, c.nmax, st), "iht select");
+      }
+      {
+        PhaseScope ps(h, PH_GRAM, st);
+        HIP_TRY(launch_iht_rows(bf16, 1, d_insts, d_rows + c.row_off, nrows, c.kmax, st),
+                "iht step");
+      }
+      {
+        PhaseScope ps(h, PH_COEF, st);
+        HIP_TRY(launch_iht_select(d_insts + c.i0, nall, 1, c.nmax, st), "iht select");
+      }
+    }
+  }
+  return CLOMP_OK;
+}
+
 // The launch sequence of one batch (captured as a graph when requested).
 clomp_status_t launch_all(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st) {
   const clomp_params_t& prm = h->params;
@@ -678,11 +739,15 @@ clomp_status_t launch_all(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st)
         h->fused_bytes += (double)P.insts[q].m * P.insts[q].n * esz + 4.0 * P.insts[q].m;
     }
   }
-  if (P.hflow) {
+  const bool iht = prm.method == CLOMP_METHOD_IHT;
+  if (iht) {
+    clomp_status_t hs = launch_iht(h, P, bf16, st);
+    if (hs != CLOMP_OK) return hs;
+  } else if (P.hflow) {
     clomp_status_t hs = launch_hflow(h, P, bf16, st);
     if (hs != CLOMP_OK) return hs;
   }
-  for (int t = 0; t < (P.hflow ? 0 : P.kmax); ++t) {
+  for (int t = 0; t < ((P.hflow || iht) ? 0 : P.kmax); ++t) {
     for (const Class& c : P.classes) {
       if (c.kmax <= t) continue;
       // active prefix of the class: instances with k_eff > t
@@ -812,7 +877,8 @@ clomp_status_t stage_plan(clomp_ctx* h, const Plan& P, hipStream_t st) {
                    wsb + (reinterpret_cast<uintptr_t>(ptr) - 1));
     };
     rb(d.r); rb(d.G); rb(d.b); rb(d.s); rb(d.mo); rb(d.ve); rb(d.xf); rb(d.z);
-    rb(d.Linv); rb(d.cg); rb(d.c0); rb(d.dg); rb(d.H); rb(d.team); rb(d.npart);
+    rb(d.Linv); rb(d.cg); rb(d.c0); rb(d.dg); rb(d.H); rb(d.team); rb(d.gbuf); rb(d.sfull);
+    rb(d.npart);
     rb(d.qpart); rb(d.key);
     rb(d.bitmap);
     rb(d.st);
@@ -1106,7 +1172,8 @@ clomp_status_t clomp_solve_batch(clomp_handle_t h, const clomp_instance_t* inst,
 
   if ((s = stage_plan(h, PP, st)) != CLOMP_OK) return s;
 
-  const bool use_graph = (h->params.flags & CLOMP_FLAG_GRAPH) != 0;
+  // the legacy default stream cannot be captured: launch eagerly there
+  const bool use_graph = (h->params.flags & CLOMP_FLAG_GRAPH) != 0 && st != nullptr;
   h->profiling = !use_graph && (h->params.flags & CLOMP_FLAG_PROFILE) != 0;
   if (use_graph) {
     auto it = h->graphs.find(PP.sig);

@@ -65,6 +65,8 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const Inst* __restrict__ i
   }
   if (I.team)   // tag 0 is never awaited
     for (int i = threadIdx.x; i < 2 * I.k_eff + 2 * kTeamMax; i += kBlock) I.team[i] = 0ull;
+  if (I.sfull)
+    for (int i = threadIdx.x; i < I.n; i += kBlock) I.sfull[i] = 0.f;
   __syncthreads();
   if (threadIdx.x == 0) {
     InstState st = {};
@@ -815,7 +817,9 @@ __global__ __launch_bounds__(kOmpThreads) void omp_ginv_kernel(const Inst* __res
 enum RowMode : int {
   ROW_RESID = 0,   // r = y - A_bulk[:, S] s
   ROW_CG_R0 = 1,   // cg.r0 = y - A_master[:, S] xf
-  ROW_CG_Q = 2     // cg.q = A_master[:, S] p   (+ partial ||q||^2)
+  ROW_CG_Q = 2,    // cg.q = A_master[:, S] p   (+ partial ||q||^2)
+  ROW_IHT_R = 3,   // IHT: r = y - A_bulk[:, S] s over the instance's own support
+  ROW_IHT_U = 4    // IHT: partial ||A_bulk[:, S] g_S||^2 (the normalised step)
 };
 
 template <typename TA, int MODE>
@@ -833,7 +837,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const Inst* __restrict__ i
   int* sup = reinterpret_cast<int*>(rsh + t1);
   float* part = rsh + 2 * t1;
   const float* src;
-  if (MODE == ROW_RESID) src = I.s;
+  if (MODE == ROW_RESID || MODE == ROW_IHT_R) src = I.s;
   else if (MODE == ROW_CG_R0) src = I.xf;
   else src = nullptr;
   if (MODE == ROW_CG_Q) {
@@ -861,6 +865,8 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const Inst* __restrict__ i
       if (rt.tile == 0) pnew[l] = p;
     }
     if (rt.tile == 0 && threadIdx.x == 0) I.st->gamma[it & 1] = gamma;
+  } else if (MODE == ROW_IHT_U) {
+    for (int l = threadIdx.x; l < t1; l += kBlock) coef[l] = I.gbuf[I.support[l]];
   } else {
     for (int l = threadIdx.x; l < t1; l += kBlock) coef[l] = src[l];
   }
@@ -868,7 +874,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const Inst* __restrict__ i
   __syncthreads();
   const TA* A;
   long long lda;
-  if (MODE == ROW_RESID) {
+  if (MODE == ROW_RESID || MODE == ROW_IHT_R || MODE == ROW_IHT_U) {
     A = reinterpret_cast<const TA*>(I.A);
     lda = I.lda;
   } else {
@@ -903,16 +909,18 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const Inst* __restrict__ i
     if (i < rt.i1) {
       const float sum = (part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]);
       const float* yw = I.r + I.m_pad;
-      if (MODE == ROW_RESID) {
+      if (MODE == ROW_RESID || MODE == ROW_IHT_R) {
         I.r[i] = yw[i] - sum;
       } else if (MODE == ROW_CG_R0) {
         I.cg[i] = yw[i] - sum;  // r0
+      } else if (MODE == ROW_IHT_U) {
+        v = sum * sum;
       } else {
         I.cg[2 * I.m_pad + i] = sum;  // q
         v = sum * sum;
       }
     }
-    if (MODE == ROW_CG_Q) {
+    if (MODE == ROW_CG_Q || MODE == ROW_IHT_U) {
       v = wave_sum(v);
       if (lane == 0) I.qpart[rt.tile] = v;
     }
@@ -1111,6 +1119,249 @@ __global__ __launch_bounds__(kBlock) void copy_s_kernel(const Inst* __restrict__
   const int t1 = *I.nsel;
   for (int l = threadIdx.x; l < t1; l += kBlock) I.xf[l] = I.s[l];
   if (threadIdx.x == 0) I.st->cg_done = 0;
+}
+
+// ============================================================ iterative hard thresholding
+// Normalised IHT (the experiments' comparison method), per iteration:
+//   r = y - A_G s_G        rows_kernel<ROW_IHT_R>      (skipped at it = 0: r = y)
+//   g = A^T r              iht_grad_kernel (stores g; at it = 0 also A^T y)
+//   G0 = top-K |g|         iht_select_kernel mode 0    (it = 0 only)
+//   ||A_G g_G||^2          rows_kernel<ROW_IHT_U>      (partials per row tile)
+//   z = s + t g, t = ||g_G||^2 / ||A_G g_G||^2, s = z on the top-K |z|
+//                          iht_select_kernel mode 1
+// The top-K is exact: the K-th largest of the unique 64-bit keys (magnitude
+// bits, inverted index: ties to the lowest index, NaN highest) is found by an
+// 8-pass radix select, then the support is compacted in index order.
+template <typename TA, int LPA>
+__global__ __launch_bounds__(kBlock) void iht_grad_kernel(const Inst* __restrict__ insts,
+                                                          const ScanTile* __restrict__ tiles,
+                                                          int r_in_lds, int first) {
+  extern __shared__ __align__(16) float smem[];
+  const ScanTile tile = tiles[blockIdx.x];
+  const Inst& I = insts[tile.inst];
+  if (I.st->done) return;
+  constexpr int VW = Vec<TA>::W;
+  const int m = I.m;
+  const int nvec = (m + VW - 1) / VW;
+  const float* rp = I.r;  // zero padded to a multiple of 8
+  if (r_in_lds) {
+    for (int i = threadIdx.x; i < nvec * VW; i += kBlock) smem[i] = I.r[i];
+    __syncthreads();
+    rp = smem;
+  }
+  const TA* A = reinterpret_cast<const TA*>(I.A);
+  const long long lda = I.lda;
+  const int gl = threadIdx.x % LPA;
+  const int grp = threadIdx.x / LPA;
+  constexpr int NG = kBlock / LPA;
+  const int tail = m - (nvec - 1) * VW;
+  // 16-byte loads in flight per lane: 8 for FP32, 4 for BF16 (whose loads
+  // expand to twice the registers)
+  constexpr int UNR = sizeof(TA) == 2 ? 4 : 8;
+  for (int j = tile.j0 + grp; j < tile.j1; j += NG) {
+    const TA* col = A + (long long)j * lda;
+    float acc = 0.f;
+#pragma unroll UNR
+    for (int c = gl; c < nvec; c += LPA) {
+      float v[VW];
+      Vec<TA>::load(col + (long long)c * VW, v);
+      if (c == nvec - 1) {
+#pragma unroll
+        for (int e = 0; e < VW; ++e) v[e] = (e < tail) ? v[e] : 0.f;
+      }
+      const float* rr = rp + c * VW;
+#pragma unroll
+      for (int e = 0; e < VW; ++e) acc = fmaf(v[e], rr[e], acc);
+    }
+    acc = group_sum<LPA>(acc);
+    if (gl == 0) {
+      I.gbuf[j] = acc;
+      if (first) I.c0[j] = acc;   // A^T y, for the refinement
+    }
+  }
+}
+
+// Exclusive scan of v over an NT-thread workgroup: wave scans, then one
+// pass over the per-wave totals held in `wsum` (NT/64 entries).  Returns
+// the prefix of this thread; `total` receives the workgroup sum.
+template <int NT>
+__device__ inline unsigned block_excl_scan(unsigned v, unsigned* wsum, unsigned& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  unsigned x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  __syncthreads();   // earlier readers of wsum are done
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  unsigned before = 0u, tot = 0u;
+#pragma unroll
+  for (int q = 0; q < NT / 64; ++q) {
+    const unsigned t = wsum[q];
+    before += (q < w) ? t : 0u;
+    tot += t;
+  }
+  total = tot;
+  return before + x - v;
+}
+
+// Magnitude bits of z as an order key: the sign is cleared, so non-negative
+// floats order like their bits and NaN ranks above +Inf.
+__device__ inline unsigned mag_bits(float z) { return __float_as_uint(z) & 0x7fffffffu; }
+
+// Top-K by magnitude of one signal per workgroup (ties to the lowest index).
+// Thread q owns the contiguous index chunk [q*CH, q*CH + CH) with its values
+// in registers (CH > 0; NT*CH >= n), or walks [q*C, q*C + C) in memory (CH =
+// 0).  The K-th largest magnitude Tv is built bit by bit from the top: Tv is
+// the largest key with #{|z| >= Tv} >= K (31 counting passes, one barrier
+// each).  Every larger magnitude is taken, and the first K - #{|z| > Tv}
+// equal ones in index order.  mode 0: z = g (support of the first
+// iteration); mode 1: the normalised step t and z = s + t g, then s = z on
+// the support.
+template <int NT, int CH>
+__global__ __launch_bounds__(NT) void iht_select_kernel(const Inst* __restrict__ insts_c,
+                                                       int mode) {
+  __shared__ unsigned ured[2][NT / 64];
+  __shared__ unsigned wsum[NT / 64];
+  __shared__ float red[NT / 64];
+  __shared__ float step_sh;
+  const Inst& I = insts_c[blockIdx.x];
+  if (I.st->done) return;
+  const int n = I.n, K = I.k_eff;
+  const int tid = threadIdx.x;
+  // normalised step t = ||g_G||^2 / ||A_G g_G||^2 (mode 1)
+  if (mode == 1) {
+    float num = 0.f;
+    for (int l = tid; l < K; l += NT) {
+      const float g = I.gbuf[I.support[l]];
+      num = fmaf(g, g, num);
+    }
+    num = wave_sum(num);
+    if ((tid & 63) == 0) red[tid >> 6] = num;
+    __syncthreads();
+    if (tid == 0) {
+      float a = 0.f, d = 0.f;
+      for (int q = 0; q < NT / 64; ++q) a += red[q];
+      for (int q = 0; q < I.n_rowtiles; ++q) d += I.qpart[q];
+      step_sh = (d > 0.f) ? a / d : 0.f;
+    }
+    __syncthreads();
+  }
+  const float tstep = (mode == 1) ? step_sh : 1.f;
+  auto zval = [&](int j) { return (mode == 1) ? fmaf(tstep, I.gbuf[j], I.sfull[j]) : I.gbuf[j]; };
+  constexpr int R = CH > 0 ? CH : 1;
+  const int C = CH > 0 ? CH : (n + NT - 1) / NT;
+  const int j0 = tid * C, j1 = min(n, j0 + C);
+  float zr[R];
+  if constexpr (CH > 0) {
+    // gbuf and sfull hold ldh >= roundup(n, 256) floats, so a whole chunk
+    // starting below n is in bounds; entries at or past n are zeroed
+    if (j0 < n) {
+      if constexpr (CH % 4 == 0) {
+#pragma unroll
+        for (int q = 0; q < CH; q += 4) {
+          float4 g = *reinterpret_cast<const float4*>(I.gbuf + j0 + q);
+          if (mode == 1) {
+            const float4 sv = *reinterpret_cast<const float4*>(I.sfull + j0 + q);
+            g.x = fmaf(tstep, g.x, sv.x);
+            g.y = fmaf(tstep, g.y, sv.y);
+            g.z = fmaf(tstep, g.z, sv.z);
+            g.w = fmaf(tstep, g.w, sv.w);
+          }
+          zr[q] = g.x;
+          zr[q + 1] = g.y;
+          zr[q + 2] = g.z;
+          zr[q + 3] = g.w;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < CH; ++q) zr[q] = zval(j0 + q);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+      if (j0 + q >= n) zr[q] = 0.f;
+  }
+  // workgroup count of magnitudes >= cand; absent entries hold 0 and every
+  // candidate is >= 1
+  int par = 0;
+  auto count_ge = [&](unsigned cand) {
+    unsigned c = 0u;
+    if constexpr (CH > 0) {
+#pragma unroll
+      for (int q = 0; q < CH; ++q) c += (mag_bits(zr[q]) >= cand) ? 1u : 0u;
+    } else {
+      for (int j = j0; j < j1; ++j) c += (mag_bits(zval(j)) >= cand) ? 1u : 0u;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((tid & 63) == 0) ured[par][tid >> 6] = c;
+    __syncthreads();
+    unsigned tot = 0u;
+#pragma unroll
+    for (int q = 0; q < NT / 64; ++q) tot += ured[par][q];
+    par ^= 1;   // the next pass writes the other buffer
+    return tot;
+  };
+  unsigned Tv = 0u;
+  for (int bit = 30; bit >= 0; --bit) {
+    const unsigned cand = Tv | (1u << bit);
+    if (count_ge(cand) >= (unsigned)K) Tv = cand;
+  }
+  const unsigned ngt_all = (Tv == 0x7fffffffu) ? 0u : count_ge(Tv + 1u);
+  const unsigned take = (unsigned)K - ngt_all;
+  unsigned ngt = 0u, neq = 0u;
+  if constexpr (CH > 0) {
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const bool ok = j0 + q < j1;
+      const unsigned v = mag_bits(zr[q]);
+      ngt += (ok && v > Tv) ? 1u : 0u;
+      neq += (ok && v == Tv) ? 1u : 0u;
+    }
+  } else {
+    for (int j = j0; j < j1; ++j) {
+      const unsigned v = mag_bits(zval(j));
+      ngt += (v > Tv) ? 1u : 0u;
+      neq += (v == Tv) ? 1u : 0u;
+    }
+  }
+  unsigned tot;
+  const unsigned eq_before = block_excl_scan<NT>(neq, wsum, tot);
+  const unsigned eq_take = (eq_before >= take) ? 0u : min(neq, take - eq_before);
+  unsigned pos = block_excl_scan<NT>(ngt + eq_take, wsum, tot);
+  unsigned eq_seen = eq_before;
+  auto place = [&](int j, float z) {
+    const unsigned v = mag_bits(z);
+    bool sel = v > Tv;
+    if (v == Tv) {
+      sel = eq_seen < take;
+      ++eq_seen;
+    }
+    sel = sel && pos < (unsigned)K;   // exactly K selected
+    if (sel) {
+      I.support[pos] = j;
+      if (mode == 1) {
+        I.s[pos] = z;
+        I.b[pos] = I.c0[j];
+      }
+      ++pos;
+    }
+    if (mode == 1) I.sfull[j] = sel ? z : 0.f;
+  };
+  if constexpr (CH > 0) {
+#pragma unroll
+    for (int q = 0; q < CH; ++q)
+      if (j0 + q < j1) place(j0 + q, zr[q]);
+  } else {
+    for (int j = j0; j < j1; ++j) place(j, zval(j));
+  }
+  if (tid == 0) {
+    *I.nsel = K;
+    if (mode == 1 && !(step_sh <= 3.402823466e38f)) atomicOr(I.status, ST_NAN);
+  }
 }
 
 // ============================================================ fused small-signal loop
@@ -2192,12 +2443,80 @@ hipError_t launch_small(int bf16, int omp, const Inst* d, const int* list, int c
   return hipGetLastError();
 }
 
+template <typename TA>
+static hipError_t iht_grad_lpa(int lpa, const Inst* d, const ScanTile* tiles, int ntiles,
+                               int r_lds, int first, hipStream_t s) {
+  const dim3 g(ntiles), b(kBlock);
+  const size_t lds = (size_t)r_lds * sizeof(float);
+  switch (lpa) {
+    case 4: CLOMP_LAUNCH((iht_grad_kernel<TA, 4>), g, b, lds, s, d, tiles, r_lds, first); break;
+    case 8: CLOMP_LAUNCH((iht_grad_kernel<TA, 8>), g, b, lds, s, d, tiles, r_lds, first); break;
+    case 16: CLOMP_LAUNCH((iht_grad_kernel<TA, 16>), g, b, lds, s, d, tiles, r_lds, first); break;
+    case 32: CLOMP_LAUNCH((iht_grad_kernel<TA, 32>), g, b, lds, s, d, tiles, r_lds, first); break;
+    default: CLOMP_LAUNCH((iht_grad_kernel<TA, 64>), g, b, lds, s, d, tiles, r_lds, first); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_iht_grad(int bf16, int lpa, const Inst* d, const ScanTile* tiles, int ntiles,
+                           int r_lds, int first, hipStream_t s) {
+  if (ntiles <= 0) return nothing_to_launch(s);
+  return bf16 ? iht_grad_lpa<uint16_t>(lpa, d, tiles, ntiles, r_lds, first, s)
+              : iht_grad_lpa<float>(lpa, d, tiles, ntiles, r_lds, first, s);
+}
+
+hipError_t launch_iht_rows(int bf16, int mode, const Inst* d, const RowTile* tiles, int ntiles,
+                           int kmax, hipStream_t s) {
+  if (ntiles <= 0) return nothing_to_launch(s);
+  const size_t lds = ((size_t)2 * (kmax + 1) + 4 * 64) * sizeof(float);
+  if (bf16) {
+    if (mode == 0)
+      CLOMP_LAUNCH((rows_kernel<uint16_t, ROW_IHT_R>), dim3(ntiles), dim3(kBlock), lds, s, d,
+                   tiles, kmax, 0, 0.f);
+    else
+      CLOMP_LAUNCH((rows_kernel<uint16_t, ROW_IHT_U>), dim3(ntiles), dim3(kBlock), lds, s, d,
+                   tiles, kmax, 0, 0.f);
+  } else {
+    if (mode == 0)
+      CLOMP_LAUNCH((rows_kernel<float, ROW_IHT_R>), dim3(ntiles), dim3(kBlock), lds, s, d, tiles,
+                   kmax, 0, 0.f);
+    else
+      CLOMP_LAUNCH((rows_kernel<float, ROW_IHT_U>), dim3(ntiles), dim3(kBlock), lds, s, d, tiles,
+                   kmax, 0, 0.f);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_iht_select(const Inst* dc, int nact, int mode, int nmax, hipStream_t s) {
+  if (nact <= 0) return nothing_to_launch(s);
+  const dim3 g(nact);
+  if (nmax <= 256) {
+    CLOMP_LAUNCH((iht_select_kernel<256, 1>), g, dim3(256), 0, s, dc, mode);
+  } else if (nmax <= 1024) {
+    CLOMP_LAUNCH((iht_select_kernel<256, 4>), g, dim3(256), 0, s, dc, mode);
+  } else if (nmax <= 4096) {
+    CLOMP_LAUNCH((iht_select_kernel<256, 16>), g, dim3(256), 0, s, dc, mode);
+  } else if (nmax <= 16384) {
+    CLOMP_LAUNCH((iht_select_kernel<1024, 16>), g, dim3(1024), 0, s, dc, mode);
+  } else if (nmax <= 65536) {
+    CLOMP_LAUNCH((iht_select_kernel<1024, 64>), g, dim3(1024), 0, s, dc, mode);
+  } else {
+    CLOMP_LAUNCH((iht_select_kernel<1024, 0>), g, dim3(1024), 0, s, dc, mode);
+  }
+  return hipGetLastError();
+}
+
 hipError_t set_max_lds(size_t bytes) {
   // Raise the dynamic-LDS ceiling of the kernels that stage vectors.
   const void* fns[] = {
       (const void*)small_loop_kernel<float, false>, (const void*)small_loop_kernel<float, true>,
       (const void*)small_loop_kernel<uint16_t, false>,
       (const void*)small_loop_kernel<uint16_t, true>,
+      (const void*)iht_grad_kernel<float, 4>, (const void*)iht_grad_kernel<float, 8>,
+      (const void*)iht_grad_kernel<float, 16>, (const void*)iht_grad_kernel<float, 32>,
+      (const void*)iht_grad_kernel<float, 64>, (const void*)iht_grad_kernel<uint16_t, 4>,
+      (const void*)iht_grad_kernel<uint16_t, 8>, (const void*)iht_grad_kernel<uint16_t, 16>,
+      (const void*)iht_grad_kernel<uint16_t, 32>, (const void*)iht_grad_kernel<uint16_t, 64>,
       (const void*)scan_kernel<float, 4>, (const void*)scan_kernel<float, 8>,
       (const void*)scan_kernel<float, 16>, (const void*)scan_kernel<float, 32>,
       (const void*)scan_kernel<float, 64>, (const void*)scan_kernel<uint16_t, 4>,

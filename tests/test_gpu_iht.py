@@ -1,0 +1,138 @@
+"""GPU parity of normalised IHT (the comparison method) against the FP64 oracle.
+
+Support identity is asserted on well-separated instances: every iteration's
+relative gap at the top-K boundary is at least delta and the oracle's support
+is unchanged under relative perturbations of A and y (oracle.separation);
+final coefficients (least squares on the support) within 1e-5 relative
+(FP32 bulk) or 1e-3 (BF16 bulk with FP32 master).
+"""
+
+from types import SimpleNamespace
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import iht_fp64, well_separated
+from paper_2501_11592_amd import clomp as C
+from paper_2501_11592_amd import workloads as W
+from tests.gpu_helpers import FP32_DELTA, FP32_U, BF16_DELTA, BF16_U, dev, rel_err, fp64_resid
+
+pytestmark = pytest.mark.gpu
+
+
+def _items(sigs, dtype=torch.float32):
+    items = []
+    for s in sigs:
+        At = dev(s.At)
+        it = dict(At=At if dtype == torch.float32 else At.to(torch.bfloat16), m=s.m,
+                  y=dev(s.y), k=s.k)
+        if dtype != torch.float32:
+            it["At_master"] = At
+        items.append(it)
+    return items
+
+
+def _check(out, i, A_sel, A_ref, y, k, R, delta, u, tol_x):
+    """Returns True when the instance is well separated (and then asserted)."""
+    supp = out.support[i][: int(out.n_selected[i])].cpu().numpy().tolist()
+    x = out.x[i].cpu().numpy().astype(np.float64)
+    assert abs(float(out.resid_norm[i]) - fp64_resid(A_ref, y, supp, x)) <= 1e-9 * (
+        1 + np.linalg.norm(y))
+    ref = iht_fp64(A_sel, y, k, max_iters=R, A_refine=None if A_sel is A_ref else A_ref)
+    ok, _ = well_separated(A_sel, y, k, method="iht", params=SimpleNamespace(max_iters=R),
+                           delta=delta, u=u, A_refine=None if A_sel is A_ref else A_ref,
+                           base=ref)
+    if not ok:
+        return False
+    assert supp == ref.support, (i, supp, ref.support)
+    assert rel_err(x, ref.x) <= tol_x, (i, rel_err(x, ref.x))
+    return True
+
+
+@pytest.mark.parametrize("R", [1, 3, 200])
+def test_iht_small_batch(R):
+    """n=256, m=64, k=8: twenty signals in one batch, R iterations."""
+    sigs = [W.single_small(900 + i) for i in range(20)]
+    sol = C.Solver(0, method="iht", inner_steps=R, flags=C.FLAG_GRAPH)
+    out = sol.solve_batch(_items(sigs))
+    out = sol.solve_batch(_items(sigs))   # graph replay
+    torch.cuda.synchronize()
+    ident = sum(_check(out, i, s.A, s.A, s.y, s.k, R, FP32_DELTA, FP32_U, 1e-5)
+                for i, s in enumerate(sigs))
+    assert (out.status.cpu().numpy() == 0).all()
+    assert (out.n_selected.cpu().numpy() == 8).all()
+    print(f"R={R}: identical {ident}/20")
+    assert ident >= 15
+    sol.close()
+
+
+def test_iht_ragged_sizes_nan_padding():
+    """Sizes that are not multiples of the vector width or tile, across lane
+    classes, with lda padding filled with NaN."""
+    sigs = []
+    for i, (n, m, k) in enumerate([(1000, 77, 9), (3001, 130, 12), (517, 26, 6), (700, 299, 31)]):
+        s = W.single_small(950 + i, n=n, m=m, k=k)
+        At = s.At.copy()
+        At[:, m:] = np.nan
+        s.At = At
+        sigs.append(s)
+    sol = C.Solver(0, method="iht", inner_steps=100)
+    out = sol.solve_batch(_items(sigs))
+    torch.cuda.synchronize()
+    ident = sum(_check(out, i, s.A, s.A, s.y, s.k, 100, FP32_DELTA, FP32_U, 1e-5)
+                for i, s in enumerate(sigs))
+    assert not (out.status.cpu().numpy() & C.ST_NAN).any()
+    assert ident >= 2
+    sol.close()
+
+
+def test_iht_bf16_with_master():
+    specs = [sp for sp in W.uneven_specs(400) if sp.n <= 1400][:12]
+    sigs = [W.uneven_instance_host(i, sp) for i, sp in enumerate(specs)]
+    sol = C.Solver(0, method="iht", inner_steps=60)
+    out = sol.solve_batch(_items(sigs, torch.bfloat16))
+    torch.cuda.synchronize()
+    ident = 0
+    for i, s in enumerate(sigs):
+        Abf = torch.from_numpy(s.At[:, :s.m]).to(torch.bfloat16).to(torch.float64).numpy().T
+        ident += _check(out, i, Abf, s.A, s.y, s.k, 60, BF16_DELTA, BF16_U, 1e-3)
+    print(f"bf16: identical {ident}/12")
+    assert ident >= 1
+    sol.close()
+
+
+def test_iht_large1d():
+    """The headline signal (n=16384, m=4096, k=256, float32, noisy), 200
+    iterations, against the oracle."""
+    sig = W.single_large(0)
+    sol = C.Solver(0, method="iht")
+    At = torch.from_numpy(sig.At).cuda()
+    y = torch.from_numpy(sig.y).cuda()
+    out = sol.solve_batch([dict(At=At, m=sig.m, y=y, k=sig.k)])
+    torch.cuda.synchronize()
+    A = sig.A
+    assert int(out.status[0]) == 0
+    assert _check(out, 0, A, A, sig.y.astype(np.float64), sig.k, 200, FP32_DELTA, FP32_U, 1e-5)
+    sol.close()
+
+
+def test_iht_edge_cases_and_determinism():
+    zero = W.single_small(7)
+    zero.y = np.zeros_like(zero.y)
+    cap = W.single_small(8, n=40, m=12, k=30)
+    base = W.single_small(9)
+    sigs = [base, zero, cap]
+    sol = C.Solver(0, method="iht", inner_steps=50)
+    a = sol.solve_batch(_items(sigs))
+    torch.cuda.synchronize()
+    xa = [t.clone() for t in a.x]
+    st = a.status.cpu().numpy()
+    assert st[0] == 0
+    assert st[1] & C.ST_ZERO_Y and int(a.n_selected[1]) == 0 and not a.x[1].any()
+    assert st[2] & C.ST_K_CAPPED and int(a.n_selected[2]) == 12
+    b = sol.solve_batch(_items(sigs))
+    torch.cuda.synchronize()
+    for u, v in zip(xa, b.x):
+        assert torch.equal(u, v)
+    sol.close()
