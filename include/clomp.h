@@ -50,8 +50,12 @@ typedef enum { CLOMP_F32 = 0, CLOMP_BF16 = 1, CLOMP_F64 = 2 } clomp_dtype_t;
 typedef enum {
   CLOMP_METHOD_CLOMP = 0,  /* Adam steps on the masked coefficients */
   CLOMP_METHOD_OMP = 1,    /* plain OMP: least squares on the support */
-  CLOMP_METHOD_IHT = 2     /* normalised iterative hard thresholding to K =
+  CLOMP_METHOD_IHT = 2,    /* normalised iterative hard thresholding to K =
                               k_eff atoms (the experiments' comparison method) */
+  CLOMP_METHOD_PAPER = 3   /* CLOMP as the experiments run it: every iteration
+                              selects all unselected atoms with |c_j| >=
+                              select_threshold * max|c| and takes one Adam
+                              step; inner_steps iterations */
 } clomp_method_t;
 
 /* Per-instance status bits (written to clomp_instance_t.status). */
@@ -89,17 +93,27 @@ typedef enum {
  * differentiation and back-propagation on learnable s (Methods, "Coefficients
  * learning on OMP"); everything below is this library's fixed reading, the
  * same values the reference oracle uses:
- *   method       CLOMP (default), plain OMP, or IHT
+ *   method       CLOMP (default), plain OMP, IHT, or paper-mode CLOMP
  *   inner_steps  CLOMP: T, Adam steps per selected atom (default 32);
- *                IHT: the number of iterations R (the experiments use 200)
+ *                IHT and paper mode: the number of iterations R (the
+ *                experiments use 200)
  *   lr_rel       learning rate of iteration t: lr_t = lr_rel * |c_j|, the
- *                correlation of the atom selected at t (default 0.05)
+ *                correlation of the atom selected at t (paper mode: lr_rel *
+ *                max_j |c_j| of the iteration) (default 0.05)
  *   beta1/beta2  Adam moment decays (0.9 / 0.999); eps = eps_rel * sigma with
  *                sigma = max_j |a_j^T y| (eps_rel default 1e-8)
  *   resid_tol    must be 0 (early stopping on ||r|| is not served)
  *   refine_iters maximum CGLS iterations of the final refinement for supports
  *                too large for the in-LDS QR (0: library default)
  *   refine_tol   relative CGLS stopping tolerance on ||A_S^T r|| (0: 1e-6)
+ *   select_threshold
+ *                paper mode: the normalised cut-off threshold T_h in (0, 1]
+ *                (default 0.7, the experiments' value; Results, synthetic
+ *                data); a batch that would take the support beyond k_eff is
+ *                refused whole and sets CLOMP_ST_K_CAPPED.  The support is
+ *                returned in increasing index order.  A non-finite
+ *                correlation (CLOMP_ST_NAN) or max|c| = 0 ends the loop; the
+ *                support reached so far is refined.
  */
 typedef struct {
   int32_t method;
@@ -112,6 +126,7 @@ typedef struct {
   int32_t refine_iters;
   float refine_tol;
   uint32_t flags;
+  float select_threshold;
 } clomp_params_t;
 
 /*

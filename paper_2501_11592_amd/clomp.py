@@ -21,8 +21,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libclomp.so")
 
 F32, BF16, F64 = 0, 1, 2
-METHOD_CLOMP, METHOD_OMP, METHOD_IHT = 0, 1, 2
-METHODS = {"clomp": METHOD_CLOMP, "omp": METHOD_OMP, "iht": METHOD_IHT}
+METHOD_CLOMP, METHOD_OMP, METHOD_IHT, METHOD_PAPER = 0, 1, 2, 3
+METHODS = {"clomp": METHOD_CLOMP, "omp": METHOD_OMP, "iht": METHOD_IHT,
+           "clomp_paper": METHOD_PAPER}
 ST_NAN, ST_K_CAPPED, ST_ZERO_Y, ST_REFINE_INACCURATE, ST_WATCHDOG = 1, 2, 4, 8, 32
 FLAG_GRAPH, FLAG_NO_FUSED_SMALL, FLAG_AUTOTUNE, FLAG_PROFILE = 1, 2, 4, 8
 FLAG_RESIDUAL_FLOW, FLAG_CORR_FLOW = 16, 32
@@ -37,7 +38,8 @@ class Params(ctypes.Structure):
                 ("lr_rel", ctypes.c_float), ("beta1", ctypes.c_float),
                 ("beta2", ctypes.c_float), ("eps_rel", ctypes.c_float),
                 ("resid_tol", ctypes.c_float), ("refine_iters", ctypes.c_int32),
-                ("refine_tol", ctypes.c_float), ("flags", ctypes.c_uint32)]
+                ("refine_tol", ctypes.c_float), ("flags", ctypes.c_uint32),
+                ("select_threshold", ctypes.c_float)]
 
 
 class Instance(ctypes.Structure):
@@ -172,7 +174,7 @@ class Solver:
 
     def __init__(self, device=0, method="clomp", inner_steps=None, lr_rel=0.05,
                  beta1=0.9, beta2=0.999, eps_rel=1e-8, refine_iters=0,
-                 refine_tol=0.0, flags=0):
+                 refine_tol=0.0, flags=0, select_threshold=0.7):
         lib = load_library()
         if not torch.cuda.is_available():
             raise ClompError("no GPU available: the CLOMP library runs only on the device")
@@ -181,10 +183,11 @@ class Solver:
         if method not in METHODS:
             raise ClompError(f"unknown method {method!r}")
         p.method = METHODS[method]
-        if inner_steps is None:   # CLOMP: Adam steps per atom; IHT: iterations
-            inner_steps = 200 if method == "iht" else 32
+        if inner_steps is None:   # CLOMP: Adam steps per atom; IHT, paper mode: iterations
+            inner_steps = 200 if method in ("iht", "clomp_paper") else 32
         p.inner_steps, p.lr_rel, p.beta1, p.beta2 = inner_steps, lr_rel, beta1, beta2
         p.eps_rel, p.refine_iters, p.refine_tol, p.flags = eps_rel, refine_iters, refine_tol, flags
+        p.select_threshold = select_threshold
         self.params = p
         h = ctypes.c_void_p()
         _check(None, lib.clomp_create(ctypes.byref(h), self.device.index or 0, ctypes.byref(p)),

@@ -25,6 +25,10 @@ namespace clomp {
 constexpr int kBlock = 256;     // threads per workgroup for every solver kernel
 constexpr int kTeamRows = 16;   // coefficient rows per team member
 constexpr int kTeamMax = 128;   // team members per signal (2048 rows)
+// IHT gradient scan: at most this many floats of r are staged in LDS per
+// workgroup; longer columns are split into slices of m whose partial dots
+// are summed afterwards in slice order.
+constexpr int kIhtSliceFloats = 6144;
 constexpr int kSmallMaxK = 64;  // fused small-signal loop: k_eff bound (one wave)
 
 // Fused small-signal loop: row stride of the LDS Gram / inverse-Gram matrix
@@ -45,7 +49,8 @@ struct InstState {
   int cg_done;     // 1: refinement converged
   float gamma[2];  // CGLS ||A_S^T r||^2, ping-pong by iteration parity
   float gamma0;
-  int pad[7];
+  int stop;        // 1: the paper-mode loop ended early (max |c| = 0 or non-finite)
+  int pad[6];
 };
 
 struct Inst {
@@ -74,10 +79,15 @@ struct Inst {
   float* dg;           // [ldh] ||a_j||^2 (correlation-update schedule)
   float* H;            // [ldh * k_eff] columns A^T a_{S_l} (correlation-update schedule)
   long long ldh;
+  int nslice;          // IHT: slices of m in the gradient scan (>= 1)
+  int pad_ns;
   unsigned long long* team;   // [2*k_eff + 2*kTeamMax] tagged words exchanged by a team
                               // (correlation-update schedule; zeroed at solve start)
-  float* gbuf;         // IHT: [ldh] g = A^T r of the current iteration
-  float* sfull;        // IHT: [n] dense coefficients (zero off the support)
+  float* gbuf;         // IHT: [nslice * ldh] per-slice partial dots; g = A^T r of the
+                       // current iteration in the first ldh entries
+  float* sfull;        // IHT, paper mode: [ldh] dense coefficients (zero off the support)
+  float* mden;         // paper mode: [ldh] dense Adam first moments
+  float* vden;         // paper mode: [ldh] dense Adam second moments
   double* npart;       // [n_rowtiles] FP64 residual-norm partial sums
   float* qpart;        // [n_rowtiles] CGLS ||q||^2 partial sums
   unsigned long long* key;

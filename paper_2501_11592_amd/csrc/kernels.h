@@ -39,13 +39,24 @@ void set_launch_events(hipEvent_t start, hipEvent_t stop);
 // Normalised IHT (one iteration = optional residual, gradient scan, step
 // denominator, thresholded update).  rows mode 0: r = y - A_G s_G; mode 1:
 // partial ||A_G g_G||^2.  select mode 0: support = top-K |g|; mode 1: the
-// normalised step and s = H_K(s + t g).
+// normalised step and s = H_K(s + t g); mode 2: mode 1 and b = (A^T y)_S.
+// grad: grid (ntiles, nslice), r_lds floats of r staged per workgroup (0:
+// read from memory); combine sums the slices of signals with nslice > 1.
 hipError_t launch_iht_grad(int bf16, int lpa, const Inst* d, const ScanTile* tiles, int ntiles,
-                           int r_lds, int first, hipStream_t s);
+                           int nslice, int r_lds, int first, hipStream_t s);
+hipError_t launch_iht_combine(const Inst* d, const ScanTile* tiles, int ntiles, int first,
+                              hipStream_t s);
 hipError_t launch_iht_rows(int bf16, int mode, const Inst* d, const RowTile* tiles, int ntiles,
                            int kmax, hipStream_t s);
 // nmax: the largest n among the signals (picks threads and chunk size).
 hipError_t launch_iht_select(const Inst* dc, int nact, int mode, int nmax, hipStream_t s);
+
+// Paper-mode CLOMP selection and gradient step of iteration `it` (one
+// workgroup per signal; `last`: also gather b for the refinement; bc1/bc2:
+// the Adam bias corrections 1 - beta^(it+1)).
+hipError_t launch_paper_select(const Inst* dc, int nact, int it, int last, float thr,
+                               float lr_rel, float beta1, float beta2, float bc1, float bc2,
+                               float eps_rel, int nmax, hipStream_t s);
 
 // Fused greedy loop of the signals list[0..count): one 256-thread workgroup
 // per signal with its dictionary in LDS (k_eff <= kSmallMaxK, dynamic LDS of

@@ -59,6 +59,8 @@ struct Class {
   std::vector<int> htile_prefix, ctile_prefix;
   int cscan_sub = 1;                  // 64-atom sub-tiles per H-scan tile
   int nmax = 0;                       // largest n of the class
+  int nslice = 1;                     // IHT: most m-slices of any signal of the class
+  int slice_floats = 0;               // IHT: largest slice of r (floats, LDS)
   size_t htile_off = 0, ctile_off = 0;
 };
 
@@ -179,10 +181,12 @@ clomp_status_t hip_fail(clomp_ctx* h, hipError_t e, const char* what) {
 clomp_status_t check_params(clomp_ctx* h, const clomp_params_t* p) {
   if (!p) return fail(h, CLOMP_INVALID_ARGUMENT, "params is NULL");
   if (p->method != CLOMP_METHOD_CLOMP && p->method != CLOMP_METHOD_OMP &&
-      p->method != CLOMP_METHOD_IHT)
+      p->method != CLOMP_METHOD_IHT && p->method != CLOMP_METHOD_PAPER)
     return fail(h, CLOMP_INVALID_ARGUMENT, "unknown method %d", p->method);
-  if (p->method == CLOMP_METHOD_IHT && p->inner_steps < 1)
-    return fail(h, CLOMP_INVALID_ARGUMENT, "IHT needs inner_steps (iterations) >= 1");
+  if ((p->method == CLOMP_METHOD_IHT || p->method == CLOMP_METHOD_PAPER) && p->inner_steps < 1)
+    return fail(h, CLOMP_INVALID_ARGUMENT, "IHT and paper mode need inner_steps (iterations) >= 1");
+  if (p->method == CLOMP_METHOD_PAPER && !(p->select_threshold > 0.f && p->select_threshold <= 1.f))
+    return fail(h, CLOMP_INVALID_ARGUMENT, "select_threshold must lie in (0, 1]");
   if (p->inner_steps < 0 || p->inner_steps > 100000)
     return fail(h, CLOMP_INVALID_ARGUMENT, "inner_steps %d out of range", p->inner_steps);
   if (!(p->beta1 >= 0.f && p->beta1 < 1.f) || !(p->beta2 >= 0.f && p->beta2 < 1.f))
@@ -250,7 +254,10 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
                 int scan_kb, int pass_kb) {
   const clomp_params_t& prm = h->params;
   const bool omp = prm.method == CLOMP_METHOD_OMP;
-  const bool iht = prm.method == CLOMP_METHOD_IHT;
+  // IHT and paper-mode CLOMP iterate over dense coefficients: no Gram matrix,
+  // no fused loop, no correlation-update schedule
+  const bool paper = prm.method == CLOMP_METHOD_PAPER;
+  const bool iht = prm.method == CLOMP_METHOD_IHT || paper;
   const int vw = bf16 ? 8 : 4;
   const size_t esize = bf16 ? 2 : 4;
   char sigbuf[96];
@@ -346,13 +353,19 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     const size_t o_z = take(sizeof(float) * d.k_eff);
     const size_t o_L = omp ? take(sizeof(float) * (size_t)d.k_eff * d.ldg) : 0;
     const size_t o_cg = use_qr ? 0 : take(sizeof(float) * (3 * (size_t)d.m_pad + 3 * d.k_eff));
-    size_t o_c0 = 0, o_H = 0, o_dg = 0, o_team = 0, o_gb = 0, o_sf = 0;
+    size_t o_c0 = 0, o_H = 0, o_dg = 0, o_team = 0, o_gb = 0, o_sf = 0, o_md = 0, o_vd = 0;
     const bool hf = P.hflow && s < P.nbig;
+    d.nslice = 1;
     if (iht) {
       d.ldh = round_up_int(d.n, 256);
+      d.nslice = std::max(1, (d.m_pad + kIhtSliceFloats - 1) / kIhtSliceFloats);
       o_c0 = take(sizeof(float) * d.ldh);
-      o_gb = take(sizeof(float) * d.ldh);
+      o_gb = take(sizeof(float) * d.ldh * d.nslice);
       o_sf = take(sizeof(float) * d.ldh);
+      if (paper) {
+        o_md = take(sizeof(float) * d.ldh);
+        o_vd = take(sizeof(float) * d.ldh);
+      }
     }
     if (hf) {
       d.ldh = round_up_int(d.n, 256);
@@ -380,6 +393,8 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     d.c0 = (hf || iht) ? (float*)(o_c0 + 1) : nullptr;
     d.gbuf = iht ? (float*)(o_gb + 1) : nullptr;
     d.sfull = iht ? (float*)(o_sf + 1) : nullptr;
+    d.mden = paper ? (float*)(o_md + 1) : nullptr;
+    d.vden = paper ? (float*)(o_vd + 1) : nullptr;
     d.dg = hf ? (float*)(o_dg + 1) : nullptr;
     d.team = hf ? (unsigned long long*)(o_team + 1) : nullptr;
     d.H = hf ? (float*)(o_H + 1) : nullptr;
@@ -423,7 +438,9 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     }
     for (int q = c.i0; q < c.i1; ++q) {
       const Inst& d = P.insts[q];
-      const size_t atom_bytes = (size_t)d.m_pad * esize;
+      // an IHT gradient workgroup streams one slice of m of each atom of its
+      // tile, so the tile holds nslice times the atoms
+      const size_t atom_bytes = (size_t)d.m_pad * esize / d.nslice;
       int apg = (int)std::max<size_t>(1, (size_t)scan_kb * 1024 / (atom_bytes * ng));
       const int apt = ng * apg;
       for (int j0 = 0; j0 < d.n; j0 += apt) P.tiles.push_back({q, j0, std::min(d.n, j0 + apt), 0});
@@ -451,6 +468,12 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
       c.m_pad_max = std::max(c.m_pad_max, d.m_pad);
       c.kmax = std::max(c.kmax, d.k_eff);
       c.nmax = std::max(c.nmax, d.n);
+      {
+        const int nvec = (d.m + vw - 1) / vw;
+        const int sv = (nvec + d.nslice - 1) / d.nslice;
+        c.nslice = std::max(c.nslice, d.nslice);
+        c.slice_floats = std::max(c.slice_floats, sv * vw);
+      }
     }
     // register kernels when every lane's share of the longest column fits in
     // 64 registers
@@ -674,7 +697,7 @@ clomp_status_t launch_iht(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st)
       const int nall = c.i1 - c.i0;
       const int ntiles = c.tile_prefix[nall];
       const int nrows = c.row_prefix[nall];
-      const int r_lds = (c.m_pad_max <= lds_cap) ? c.m_pad_max : 0;
+      const int r_lds = (c.slice_floats <= lds_cap) ? c.slice_floats : 0;
       if (it > 0) {
         PhaseScope ps(h, PH_RESID, st);
         HIP_TRY(launch_iht_rows(bf16, 0, d_insts, d_rows + c.row_off, nrows, c.kmax, st),
@@ -682,13 +705,18 @@ clomp_status_t launch_iht(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st)
       }
       {
         PhaseScope ps(h, PH_SCAN, st);
-        HIP_TRY(launch_iht_grad(bf16, c.lpa, d_insts, d_tiles + c.tile_off, ntiles, r_lds,
-                                it == 0, st),
+        HIP_TRY(launch_iht_grad(bf16, c.lpa, d_insts, d_tiles + c.tile_off, ntiles, c.nslice,
+                                r_lds, it == 0, st),
                 "iht grad");
         if (h->profiling)
           for (int q = c.i0; q < c.i1; ++q)
             h->scan_bytes += (double)P.insts[q].m * P.insts[q].n * esz + 4.0 * P.insts[q].m +
-                             4.0 * P.insts[q].n;
+                             4.0 * P.insts[q].n * P.insts[q].nslice;
+      }
+      if (c.nslice > 1) {
+        PhaseScope ps(h, PH_COEF, st);
+        HIP_TRY(launch_iht_combine(d_insts, d_tiles + c.tile_off, ntiles, it == 0, st),
+                "iht combine");
       }
       if (it == 0) {
         PhaseScope ps(h, PH_COEF, st);
@@ -701,8 +729,56 @@ clomp_status_t launch_iht(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st)
       }
       {
         PhaseScope ps(h, PH_COEF, st);
-        HIP_TRY(launch_iht_select(d_insts + c.i0, nall, 1, c.nmax, st), "iht select");
+        HIP_TRY(launch_iht_select(d_insts + c.i0, nall, it + 1 == h->params.inner_steps ? 2 : 1,
+                                  c.nmax, st), "iht select");
       }
+    }
+  }
+  return CLOMP_OK;
+}
+
+// R = inner_steps iterations of paper-mode CLOMP for every class.
+clomp_status_t launch_paper(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st) {
+  const clomp_params_t& prm = h->params;
+  char* tb = reinterpret_cast<char*>(h->tables.p);
+  const Inst* d_insts = reinterpret_cast<const Inst*>(tb + P.off_insts);
+  const ScanTile* d_tiles = reinterpret_cast<const ScanTile*>(tb + P.off_tiles);
+  const RowTile* d_rows = reinterpret_cast<const RowTile*>(tb + P.off_rows);
+  const int lds_cap = (h->lds_limit - 1024) / 4;
+  const double esz = bf16 ? 2.0 : 4.0;
+  double b1p = 1.0, b2p = 1.0;
+  for (int it = 0; it < prm.inner_steps; ++it) {
+    b1p *= prm.beta1;
+    b2p *= prm.beta2;
+    const float bc1 = (float)(1.0 - b1p), bc2 = (float)(1.0 - b2p);
+    for (const Class& c : P.classes) {
+      const int nall = c.i1 - c.i0;
+      const int ntiles = c.tile_prefix[nall];
+      const int nrows = c.row_prefix[nall];
+      const int r_lds = (c.slice_floats <= lds_cap) ? c.slice_floats : 0;
+      if (it > 0) {
+        PhaseScope ps(h, PH_RESID, st);
+        HIP_TRY(launch_iht_rows(bf16, 0, d_insts, d_rows + c.row_off, nrows, c.kmax, st),
+                "paper resid");
+      }
+      {
+        PhaseScope ps(h, PH_SCAN, st);
+        HIP_TRY(launch_iht_grad(bf16, c.lpa, d_insts, d_tiles + c.tile_off, ntiles, c.nslice,
+                                r_lds, it == 0, st),
+                "paper scan");
+        if (h->profiling)
+          for (int q = c.i0; q < c.i1; ++q)
+            h->scan_bytes += (double)P.insts[q].m * P.insts[q].n * esz + 4.0 * P.insts[q].m +
+                             4.0 * P.insts[q].n * P.insts[q].nslice;
+      }
+      PhaseScope ps(h, PH_COEF, st);
+      if (c.nslice > 1)
+        HIP_TRY(launch_iht_combine(d_insts, d_tiles + c.tile_off, ntiles, it == 0, st),
+                "paper combine");
+      HIP_TRY(launch_paper_select(d_insts + c.i0, nall, it, it + 1 == prm.inner_steps,
+                                  prm.select_threshold, prm.lr_rel, prm.beta1, prm.beta2, bc1,
+                                  bc2, prm.eps_rel, c.nmax, st),
+              "paper select");
     }
   }
   return CLOMP_OK;
@@ -739,9 +815,12 @@ clomp_status_t launch_all(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st)
         h->fused_bytes += (double)P.insts[q].m * P.insts[q].n * esz + 4.0 * P.insts[q].m;
     }
   }
-  const bool iht = prm.method == CLOMP_METHOD_IHT;
-  if (iht) {
+  const bool iht = prm.method == CLOMP_METHOD_IHT || prm.method == CLOMP_METHOD_PAPER;
+  if (prm.method == CLOMP_METHOD_IHT) {
     clomp_status_t hs = launch_iht(h, P, bf16, st);
+    if (hs != CLOMP_OK) return hs;
+  } else if (prm.method == CLOMP_METHOD_PAPER) {
+    clomp_status_t hs = launch_paper(h, P, bf16, st);
     if (hs != CLOMP_OK) return hs;
   } else if (P.hflow) {
     clomp_status_t hs = launch_hflow(h, P, bf16, st);
@@ -878,6 +957,7 @@ clomp_status_t stage_plan(clomp_ctx* h, const Plan& P, hipStream_t st) {
     };
     rb(d.r); rb(d.G); rb(d.b); rb(d.s); rb(d.mo); rb(d.ve); rb(d.xf); rb(d.z);
     rb(d.Linv); rb(d.cg); rb(d.c0); rb(d.dg); rb(d.H); rb(d.team); rb(d.gbuf); rb(d.sfull);
+    rb(d.mden); rb(d.vden);
     rb(d.npart);
     rb(d.qpart); rb(d.key);
     rb(d.bitmap);
@@ -1021,6 +1101,7 @@ void clomp_default_params(clomp_params_t* p) {
   p->refine_iters = 0;
   p->refine_tol = 0.f;
   p->flags = 0u;
+  p->select_threshold = 0.7f;
 }
 
 const char* clomp_status_string(clomp_status_t s) {

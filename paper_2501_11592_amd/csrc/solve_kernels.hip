@@ -67,6 +67,11 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const Inst* __restrict__ i
     for (int i = threadIdx.x; i < 2 * I.k_eff + 2 * kTeamMax; i += kBlock) I.team[i] = 0ull;
   if (I.sfull)
     for (int i = threadIdx.x; i < I.n; i += kBlock) I.sfull[i] = 0.f;
+  if (I.mden)
+    for (int i = threadIdx.x; i < I.n; i += kBlock) {
+      I.mden[i] = 0.f;
+      I.vden[i] = 0.f;
+    }
   __syncthreads();
   if (threadIdx.x == 0) {
     InstState st = {};
@@ -85,6 +90,31 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const Inst* __restrict__ i
 // Tile = atoms [j0, j1) of one instance.  LPA lanes cooperate on one atom,
 // each lane streaming 16-byte vectors of the column; r is staged in LDS when
 // it fits.  The workgroup's best key goes to the instance key by atomicMax.
+// Partial dot of column `col` with r over the vectors [cbeg, cend) that lane
+// gl of LPA lanes visits; rv holds r from vector cbeg on (zero padded past m).
+// Called once with an LDS copy and once with r in memory, so that each
+// instance is compiled for its own memory (a pointer that may name either
+// compiles to flat loads, whose waits also cover the outstanding HBM loads).
+template <typename TA, int LPA, int UNR>
+__device__ inline float span_dot(const TA* __restrict__ col, const float* __restrict__ rv,
+                                 int cbeg, int cend, int nvec, int tail, int gl) {
+  constexpr int VW = Vec<TA>::W;
+  float acc = 0.f;
+#pragma unroll UNR
+  for (int c = cbeg + gl; c < cend; c += LPA) {
+    float v[VW];
+    Vec<TA>::load(col + (long long)c * VW, v);
+    if (c == nvec - 1) {
+#pragma unroll
+      for (int e = 0; e < VW; ++e) v[e] = (e < tail) ? v[e] : 0.f;
+    }
+    const float* rr = rv + (c - cbeg) * VW;
+#pragma unroll
+    for (int e = 0; e < VW; ++e) acc = fmaf(v[e], rr[e], acc);
+  }
+  return acc;
+}
+
 template <typename TA, int LPA>
 __global__ __launch_bounds__(kBlock) void scan_kernel(const Inst* __restrict__ insts,
                                                       const ScanTile* __restrict__ tiles,
@@ -100,11 +130,9 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const Inst* __restrict__ i
   constexpr int VW = Vec<TA>::W;
   const int m = I.m;
   const int nvec = (m + VW - 1) / VW;
-  const float* rp = I.r;  // zero padded to a multiple of 8
   if (r_in_lds) {
     for (int i = threadIdx.x; i < nvec * VW; i += kBlock) smem[i] = I.r[i];
     __syncthreads();
-    rp = smem;
   }
   const TA* A = reinterpret_cast<const TA*>(I.A);
   const long long lda = I.lda;
@@ -116,19 +144,8 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const Inst* __restrict__ i
   unsigned long long best = 0ull;
   for (int j = tile.j0 + grp; j < tile.j1; j += NG) {
     const TA* col = A + (long long)j * lda;
-    float acc = 0.f;
-#pragma unroll 8
-    for (int c = gl; c < nvec; c += LPA) {
-      float v[VW];
-      Vec<TA>::load(col + (long long)c * VW, v);
-      if (c == nvec - 1) {
-#pragma unroll
-        for (int e = 0; e < VW; ++e) v[e] = (e < tail) ? v[e] : 0.f;
-      }
-      const float* rr = rp + c * VW;
-#pragma unroll
-      for (int e = 0; e < VW; ++e) acc = fmaf(v[e], rr[e], acc);
-    }
+    float acc = r_in_lds ? span_dot<TA, LPA, 8>(col, smem, 0, nvec, nvec, tail, gl)
+                         : span_dot<TA, LPA, 8>(col, I.r, 0, nvec, nvec, tail, gl);
     acc = group_sum<LPA>(acc);
     const unsigned sel = (bitmap[j >> 5] >> (j & 31)) & 1u;
     const unsigned long long key = sel ? 0ull : pack_key(acc, j);
@@ -831,6 +848,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const Inst* __restrict__ i
   const RowTile rt = tiles[blockIdx.x];
   const Inst& I = insts[rt.inst];
   if (I.st->done) return;
+  if ((MODE == ROW_IHT_R || MODE == ROW_IHT_U) && I.st->stop) return;
   // in the loop every active instance has t+1 atoms; after it, its own count
   const int t1 = (MODE == ROW_RESID) ? t + 1 : *I.nsel;
   float* coef = rsh;
@@ -936,6 +954,7 @@ __global__ __launch_bounds__(kBlock) void cg_dots_kernel(const Inst* __restrict_
                                                          const int* __restrict__ list,
                                                          int t, int nblk, int D, int it) {
   extern __shared__ __align__(16) float vsh[];
+  __shared__ float qred[kWaves];
   const int ii = blockIdx.x / nblk;
   const int blk = blockIdx.x - ii * nblk;
   const Inst& I = insts[list[ii]];
@@ -952,7 +971,8 @@ __global__ __launch_bounds__(kBlock) void cg_dots_kernel(const Inst* __restrict_
     for (int i = threadIdx.x; i < mp; i += kBlock) vsh[i] = (i < m) ? rbuf0[i] : 0.f;
   } else {
     float qq = 0.f;
-    for (int tt = 0; tt < I.n_rowtiles; ++tt) qq += I.qpart[tt];
+    for (int tt = threadIdx.x; tt < I.n_rowtiles; tt += kBlock) qq += I.qpart[tt];
+    qq = block_sum(qq, qred);
     const float gamma = I.st->gamma[it & 1];
     const float alpha = (qq > 0.f) ? gamma / qq : 0.f;
     const float* rold = (it & 1) ? rbuf1 : rbuf0;
@@ -1096,17 +1116,23 @@ __global__ __launch_bounds__(kBlock) void norm_rows_kernel(const Inst* __restric
   }
 }
 
-// One workgroup per instance: FP64 norm from the partials (fixed order),
-// scatter x_S into x, refinement status.
+// One workgroup per instance: FP64 norm from the partials (fixed order:
+// strided per-thread sums, then waves), scatter x_S into x, refinement status.
 __global__ __launch_bounds__(kBlock) void finalize_kernel(const Inst* __restrict__ insts,
                                                           int check_cg) {
+  __shared__ double dred[kWaves];
   const Inst& I = insts[blockIdx.x];
   const int t1 = *I.nsel;
   for (int l = threadIdx.x; l < t1; l += kBlock) I.x[I.support[l]] = I.xf[l];
+  double ps = 0.0;
+  for (int tt = threadIdx.x; tt < I.n_rowtiles; tt += kBlock) ps += I.npart[tt];
+  ps = wave_sum_d(ps);
+  if ((threadIdx.x & 63) == 0) dred[threadIdx.x >> 6] = ps;
+  __syncthreads();
   if (threadIdx.x == 0) {
     double s = 0.0;
-    for (int tt = 0; tt < I.n_rowtiles; ++tt) s += I.npart[tt];
-    *I.rnorm = (t1 > 0) ? sqrt(s) : 0.0;
+    for (int w = 0; w < kWaves; ++w) s += dred[w];
+    *I.rnorm = sqrt(s);   // ||y|| for an empty support (0 when y == 0)
     if (check_cg && I.cg_slot >= 0 && !I.st->done && !I.st->cg_done)
       atomicOr(I.status, ST_REFINE_INACCURATE);
   }
@@ -1129,9 +1155,18 @@ __global__ __launch_bounds__(kBlock) void copy_s_kernel(const Inst* __restrict__
 //   ||A_G g_G||^2          rows_kernel<ROW_IHT_U>      (partials per row tile)
 //   z = s + t g, t = ||g_G||^2 / ||A_G g_G||^2, s = z on the top-K |z|
 //                          iht_select_kernel mode 1
-// The top-K is exact: the K-th largest of the unique 64-bit keys (magnitude
-// bits, inverted index: ties to the lowest index, NaN highest) is found by an
-// 8-pass radix select, then the support is compacted in index order.
+// The top-K is exact (ties to the lowest index, NaN highest); the support is
+// compacted in index order.
+//
+// The gradient scan splits a long column into I.nslice slices of m (blockIdx.y
+// is the slice) so that the staged part of r stays small and many
+// workgroups share a CU; slice partials go to gbuf[slice * ldh + j] and
+// iht_combine_kernel sums them in slice order.
+// 16-byte loads in flight per lane in the gradient scan: 8 for FP32, 4 for
+// BF16 (whose loads expand to twice the registers)
+template <typename TA>
+constexpr int kIhtUnroll = sizeof(TA) == 2 ? 4 : 8;
+
 template <typename TA, int LPA>
 __global__ __launch_bounds__(kBlock) void iht_grad_kernel(const Inst* __restrict__ insts,
                                                           const ScanTile* __restrict__ tiles,
@@ -1139,15 +1174,19 @@ __global__ __launch_bounds__(kBlock) void iht_grad_kernel(const Inst* __restrict
   extern __shared__ __align__(16) float smem[];
   const ScanTile tile = tiles[blockIdx.x];
   const Inst& I = insts[tile.inst];
-  if (I.st->done) return;
+  if (I.st->done || I.st->stop) return;
+  const int nsl = I.nslice;
+  const int sl = blockIdx.y;
+  if (sl >= nsl) return;
   constexpr int VW = Vec<TA>::W;
   const int m = I.m;
   const int nvec = (m + VW - 1) / VW;
-  const float* rp = I.r;  // zero padded to a multiple of 8
+  const int sv = (nvec + nsl - 1) / nsl;
+  const int cv0 = sl * sv, cv1 = min(nvec, cv0 + sv);
   if (r_in_lds) {
-    for (int i = threadIdx.x; i < nvec * VW; i += kBlock) smem[i] = I.r[i];
+    const int cnt = max(0, cv1 - cv0) * VW;
+    for (int i = threadIdx.x; i < cnt; i += kBlock) smem[i] = I.r[cv0 * VW + i];
     __syncthreads();
-    rp = smem;
   }
   const TA* A = reinterpret_cast<const TA*>(I.A);
   const long long lda = I.lda;
@@ -1155,29 +1194,33 @@ __global__ __launch_bounds__(kBlock) void iht_grad_kernel(const Inst* __restrict
   const int grp = threadIdx.x / LPA;
   constexpr int NG = kBlock / LPA;
   const int tail = m - (nvec - 1) * VW;
-  // 16-byte loads in flight per lane: 8 for FP32, 4 for BF16 (whose loads
-  // expand to twice the registers)
-  constexpr int UNR = sizeof(TA) == 2 ? 4 : 8;
   for (int j = tile.j0 + grp; j < tile.j1; j += NG) {
     const TA* col = A + (long long)j * lda;
-    float acc = 0.f;
-#pragma unroll UNR
-    for (int c = gl; c < nvec; c += LPA) {
-      float v[VW];
-      Vec<TA>::load(col + (long long)c * VW, v);
-      if (c == nvec - 1) {
-#pragma unroll
-        for (int e = 0; e < VW; ++e) v[e] = (e < tail) ? v[e] : 0.f;
-      }
-      const float* rr = rp + c * VW;
-#pragma unroll
-      for (int e = 0; e < VW; ++e) acc = fmaf(v[e], rr[e], acc);
-    }
+    float acc = r_in_lds
+                    ? span_dot<TA, LPA, kIhtUnroll<TA>>(col, smem, cv0, cv1, nvec, tail, gl)
+                    : span_dot<TA, LPA, kIhtUnroll<TA>>(col, I.r + (long long)cv0 * VW, cv0,
+                                                        cv1, nvec, tail, gl);
     acc = group_sum<LPA>(acc);
     if (gl == 0) {
-      I.gbuf[j] = acc;
-      if (first) I.c0[j] = acc;   // A^T y, for the refinement
+      I.gbuf[(long long)sl * I.ldh + j] = acc;
+      if (first && nsl == 1) I.c0[j] = acc;   // A^T y, for the refinement
     }
+  }
+}
+
+// g_j = sum of the slice partials of atom j, in slice order (signals with
+// nslice > 1; at the first iteration also c0 = A^T y).
+__global__ __launch_bounds__(kBlock) void iht_combine_kernel(const Inst* __restrict__ insts,
+                                                             const ScanTile* __restrict__ tiles,
+                                                             int first) {
+  const ScanTile tile = tiles[blockIdx.x];
+  const Inst& I = insts[tile.inst];
+  if (I.st->done || I.st->stop || I.nslice == 1) return;
+  for (int j = tile.j0 + threadIdx.x; j < tile.j1; j += kBlock) {
+    float g = I.gbuf[j];
+    for (int q = 1; q < I.nslice; ++q) g += I.gbuf[(long long)q * I.ldh + j];
+    I.gbuf[j] = g;
+    if (first) I.c0[j] = g;
   }
 }
 
@@ -1214,43 +1257,54 @@ __device__ inline unsigned mag_bits(float z) { return __float_as_uint(z) & 0x7ff
 // Top-K by magnitude of one signal per workgroup (ties to the lowest index).
 // Thread q owns the contiguous index chunk [q*CH, q*CH + CH) with its values
 // in registers (CH > 0; NT*CH >= n), or walks [q*C, q*C + C) in memory (CH =
-// 0).  The K-th largest magnitude Tv is built bit by bit from the top: Tv is
-// the largest key with #{|z| >= Tv} >= K (31 counting passes, one barrier
-// each).  Every larger magnitude is taken, and the first K - #{|z| > Tv}
+// 0).  The K-th largest magnitude Tv is built from the top bit down: Tv is
+// the largest key with #{|z| >= Tv} >= K (16 counting passes of one or two
+// bits, counts by wave ballots, one barrier each).  Every larger magnitude is taken, and the first K - #{|z| > Tv}
 // equal ones in index order.  mode 0: z = g (support of the first
 // iteration); mode 1: the normalised step t and z = s + t g, then s = z on
-// the support.
+// the support; mode 2: as mode 1, then b = (A^T y)_S for the refinement
+// (the last iteration).
 template <int NT, int CH>
 __global__ __launch_bounds__(NT) void iht_select_kernel(const Inst* __restrict__ insts_c,
                                                        int mode) {
-  __shared__ unsigned ured[2][NT / 64];
+  __shared__ unsigned ured[2][3][NT / 64];
   __shared__ unsigned wsum[NT / 64];
-  __shared__ float red[NT / 64];
+  __shared__ float red[NT / 64], red2[NT / 64];
   __shared__ float step_sh;
   const Inst& I = insts_c[blockIdx.x];
   if (I.st->done) return;
   const int n = I.n, K = I.k_eff;
   const int tid = threadIdx.x;
   // normalised step t = ||g_G||^2 / ||A_G g_G||^2 (mode 1)
-  if (mode == 1) {
-    float num = 0.f;
+  if (mode >= 1) {
+    // numerator and denominator reduced over the whole workgroup (the row
+    // partials are many for long columns; a serial walk costs a memory
+    // latency per entry)
+    float num = 0.f, den = 0.f;
     for (int l = tid; l < K; l += NT) {
       const float g = I.gbuf[I.support[l]];
       num = fmaf(g, g, num);
     }
+    for (int q = tid; q < I.n_rowtiles; q += NT) den += I.qpart[q];
     num = wave_sum(num);
-    if ((tid & 63) == 0) red[tid >> 6] = num;
+    den = wave_sum(den);
+    if ((tid & 63) == 0) {
+      red[tid >> 6] = num;
+      red2[tid >> 6] = den;
+    }
     __syncthreads();
     if (tid == 0) {
       float a = 0.f, d = 0.f;
-      for (int q = 0; q < NT / 64; ++q) a += red[q];
-      for (int q = 0; q < I.n_rowtiles; ++q) d += I.qpart[q];
+      for (int q = 0; q < NT / 64; ++q) {
+        a += red[q];
+        d += red2[q];
+      }
       step_sh = (d > 0.f) ? a / d : 0.f;
     }
     __syncthreads();
   }
-  const float tstep = (mode == 1) ? step_sh : 1.f;
-  auto zval = [&](int j) { return (mode == 1) ? fmaf(tstep, I.gbuf[j], I.sfull[j]) : I.gbuf[j]; };
+  const float tstep = (mode >= 1) ? step_sh : 1.f;
+  auto zval = [&](int j) { return (mode >= 1) ? fmaf(tstep, I.gbuf[j], I.sfull[j]) : I.gbuf[j]; };
   constexpr int R = CH > 0 ? CH : 1;
   const int C = CH > 0 ? CH : (n + NT - 1) / NT;
   const int j0 = tid * C, j1 = min(n, j0 + C);
@@ -1263,7 +1317,7 @@ __global__ __launch_bounds__(NT) void iht_select_kernel(const Inst* __restrict__
 #pragma unroll
         for (int q = 0; q < CH; q += 4) {
           float4 g = *reinterpret_cast<const float4*>(I.gbuf + j0 + q);
-          if (mode == 1) {
+          if (mode >= 1) {
             const float4 sv = *reinterpret_cast<const float4*>(I.sfull + j0 + q);
             g.x = fmaf(tstep, g.x, sv.x);
             g.y = fmaf(tstep, g.y, sv.y);
@@ -1284,33 +1338,59 @@ __global__ __launch_bounds__(NT) void iht_select_kernel(const Inst* __restrict__
     for (int q = 0; q < R; ++q)
       if (j0 + q >= n) zr[q] = 0.f;
   }
-  // workgroup count of magnitudes >= cand; absent entries hold 0 and every
-  // candidate is >= 1
-  int par = 0;
-  auto count_ge = [&](unsigned cand) {
-    unsigned c = 0u;
+  // wave count of magnitudes >= cand (uniform over the wave); absent entries
+  // hold 0 and every candidate is >= 1
+  auto wcount = [&](unsigned cand) -> unsigned {
     if constexpr (CH > 0) {
+      unsigned c = 0u;
 #pragma unroll
-      for (int q = 0; q < CH; ++q) c += (mag_bits(zr[q]) >= cand) ? 1u : 0u;
+      for (int q = 0; q < CH; ++q) c += (unsigned)__popcll(__ballot(mag_bits(zr[q]) >= cand));
+      return c;
     } else {
+      unsigned c = 0u;
       for (int j = j0; j < j1; ++j) c += (mag_bits(zval(j)) >= cand) ? 1u : 0u;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+      return c;
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-    if ((tid & 63) == 0) ured[par][tid >> 6] = c;
-    __syncthreads();
-    unsigned tot = 0u;
-#pragma unroll
-    for (int q = 0; q < NT / 64; ++q) tot += ured[par][q];
-    par ^= 1;   // the next pass writes the other buffer
-    return tot;
   };
+  // one pass resolves the bits [b, b + nb) of the threshold (nb = 1 or 2):
+  // the workgroup counts for the 2^nb - 1 candidates Tv | d << b, which
+  // decrease with d, and keeps the largest d whose count reaches K
   unsigned Tv = 0u;
-  for (int bit = 30; bit >= 0; --bit) {
-    const unsigned cand = Tv | (1u << bit);
-    if (count_ge(cand) >= (unsigned)K) Tv = cand;
+  int par = 0;
+  auto resolve = [&](int b, int nb) {
+    const int nc = (1 << nb) - 1;
+    unsigned cnt[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) cnt[d] = (d < nc) ? wcount(Tv | ((unsigned)(d + 1) << b)) : 0u;
+    if ((tid & 63) == 0) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) ured[par][d][tid >> 6] = cnt[d];
+    }
+    __syncthreads();
+    unsigned dsel = 0u;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      unsigned tot = 0u;
+#pragma unroll
+      for (int q = 0; q < NT / 64; ++q) tot += ured[par][d][q];
+      if (d < nc && tot >= (unsigned)K) dsel = d + 1;
+    }
+    par ^= 1;   // the next pass writes the other buffer
+    Tv |= dsel << b;
+  };
+  resolve(30, 1);
+  for (int b = 28; b >= 0; b -= 2) resolve(b, 2);
+  // number of magnitudes above Tv
+  unsigned ngt_all = 0u;
+  if (Tv != 0x7fffffffu) {
+    const unsigned c = wcount(Tv + 1u);
+    if ((tid & 63) == 0) ured[par][0][tid >> 6] = c;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NT / 64; ++q) ngt_all += ured[par][0][q];
   }
-  const unsigned ngt_all = (Tv == 0x7fffffffu) ? 0u : count_ge(Tv + 1u);
   const unsigned take = (unsigned)K - ngt_all;
   unsigned ngt = 0u, neq = 0u;
   if constexpr (CH > 0) {
@@ -1343,13 +1423,10 @@ __global__ __launch_bounds__(NT) void iht_select_kernel(const Inst* __restrict__
     sel = sel && pos < (unsigned)K;   // exactly K selected
     if (sel) {
       I.support[pos] = j;
-      if (mode == 1) {
-        I.s[pos] = z;
-        I.b[pos] = I.c0[j];
-      }
+      if (mode >= 1) I.s[pos] = z;
       ++pos;
     }
-    if (mode == 1) I.sfull[j] = sel ? z : 0.f;
+    if (mode >= 1) I.sfull[j] = sel ? z : 0.f;
   };
   if constexpr (CH > 0) {
 #pragma unroll
@@ -1358,9 +1435,140 @@ __global__ __launch_bounds__(NT) void iht_select_kernel(const Inst* __restrict__
   } else {
     for (int j = j0; j < j1; ++j) place(j, zval(j));
   }
+  if (mode == 2) {
+    // b = (A^T y)_S for the refinement, gathered once after the last update
+    __syncthreads();   // the support written above is visible to the workgroup
+    for (int l = tid; l < K; l += NT) I.b[l] = I.c0[I.support[l]];
+  }
   if (tid == 0) {
     *I.nsel = K;
-    if (mode == 1 && !(step_sh <= 3.402823466e38f)) atomicOr(I.status, ST_NAN);
+    if (mode >= 1 && !(step_sh <= 3.402823466e38f)) atomicOr(I.status, ST_NAN);
+  }
+}
+
+// ============================================================ paper-mode CLOMP
+// The variant the experiments time (normalised cut-off threshold T_h, R
+// iterations of one gradient step each).  Per iteration:
+//   r = y - A_S s_S        rows_kernel<ROW_IHT_R>   (skipped at it = 0: r = y)
+//   c = A^T r              iht_grad_kernel (+ combine for sliced columns)
+//   paper_select_kernel    cmax = max_j |c_j|; the unselected atoms with
+//                          |c_j| / cmax >= T_h join the mask unless the support
+//                          would exceed k_eff (the batch is then refused whole);
+//                          one Adam step on the masked coefficients with
+//                          g = -c, lr = lr_rel * cmax, eps = eps_rel * sigma
+//                          (sigma = cmax of the first iteration); the support
+//                          is rebuilt in index order with its coefficients.
+// A non-finite correlation or cmax = 0 ends the loop for the signal (stop),
+// and b = (A^T y)_S is gathered then or after the last iteration, for the
+// least-squares refinement.
+template <int NT>
+__global__ __launch_bounds__(NT) void paper_select_kernel(const Inst* __restrict__ insts_c,
+                                                         int it, int last, float thr,
+                                                         float lr_rel, float beta1, float beta2,
+                                                         float bc1, float bc2, float eps_rel) {
+  __shared__ float fred[NT / 64];
+  __shared__ unsigned ured[NT / 64];
+  __shared__ unsigned wsum[NT / 64];
+  const Inst& I = insts_c[blockIdx.x];
+  if (I.st->done || I.st->stop) return;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int n = I.n, K = I.k_eff;
+  const int C = (n + NT - 1) / NT;
+  const int j0 = tid * C, j1 = min(n, j0 + C);
+  const float* c = I.gbuf;
+  const unsigned* bits = I.bitmap;
+  const int nsel_old = *I.nsel;
+  auto gather_b = [&](int t1) {
+    for (int l = tid; l < t1; l += NT) I.b[l] = I.c0[I.support[l]];
+  };
+  // (1) cmax over every atom, and whether any correlation is non-finite
+  float mx = 0.f;
+  unsigned bad = 0u;
+  for (int j = j0; j < j1; ++j) {
+    const float a = fabsf(c[j]);
+    bad |= (a <= 3.402823466e38f) ? 0u : 1u;
+    mx = fmaxf(mx, a);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    bad |= __shfl_xor(bad, o, 64);
+  }
+  if (lane == 0) {
+    fred[w] = mx;
+    ured[w] = bad;
+  }
+  __syncthreads();
+  float cmax = 0.f;
+  bad = 0u;
+#pragma unroll
+  for (int q = 0; q < NT / 64; ++q) {
+    cmax = fmaxf(cmax, fred[q]);
+    bad |= ured[q];
+  }
+  if (bad || cmax == 0.f) {
+    // the loop ends here; the refinement uses the support of the previous
+    // iteration
+    if (tid == 0) {
+      I.st->stop = 1;
+      if (bad) atomicOr(I.status, ST_NAN);
+    }
+    gather_b(nsel_old);
+    return;
+  }
+  float eps;
+  if (it == 0) {
+    eps = eps_rel * cmax;
+    if (tid == 0) {
+      I.st->sigma = cmax;
+      I.st->eps = eps;
+    }
+  } else {
+    eps = I.st->eps;
+  }
+  auto in_mask = [&](int j) { return ((bits[j >> 5] >> (j & 31)) & 1u) != 0u; };
+  auto passes = [&](int j) { return fabsf(c[j]) / cmax >= thr; };
+  // (2) the batch of new atoms
+  unsigned nnew = 0u;
+  for (int j = j0; j < j1; ++j) nnew += (!in_mask(j) && passes(j)) ? 1u : 0u;
+  unsigned tot_new;
+  (void)block_excl_scan<NT>(nnew, wsum, tot_new);
+  const bool accept = tot_new > 0u && (unsigned)nsel_old + tot_new <= (unsigned)K;
+  if (tid == 0 && tot_new > 0u && !accept) atomicOr(I.status, ST_K_CAPPED);
+  // (3) one Adam step on the masked coordinates (old mask plus the accepted
+  // batch); new bits are set here
+  const float lr = lr_rel * cmax;
+  unsigned cnt = 0u;
+  for (int j = j0; j < j1; ++j) {
+    const bool old = in_mask(j);
+    const bool add = !old && accept && passes(j);
+    if (!(old || add)) continue;
+    if (add) atomicOr(I.bitmap + (j >> 5), 1u << (j & 31));
+    const float g = -c[j];
+    const float mo = fmaf(beta1, I.mden[j], (1.f - beta1) * g);
+    const float ve = fmaf(beta2, I.vden[j], (1.f - beta2) * (g * g));
+    I.mden[j] = mo;
+    I.vden[j] = ve;
+    I.sfull[j] = I.sfull[j] - lr * (mo / bc1) / (sqrtf(ve / bc2) + eps);
+    ++cnt;
+  }
+  // (4) the support in index order, with its coefficients
+  unsigned tot;
+  unsigned pos = block_excl_scan<NT>(cnt, wsum, tot);
+  for (int j = j0; j < j1; ++j) {
+    // a set bit of this chunk is either old or set above by this thread, so
+    // the test agrees with (3) whichever copy of the word the load sees
+    const bool sel = in_mask(j) || (accept && passes(j));
+    if (sel) {
+      I.support[pos] = j;
+      I.s[pos] = I.sfull[j];
+      ++pos;
+    }
+  }
+  if (tid == 0) *I.nsel = (int)tot;
+  if (last) {
+    __syncthreads();   // the support written above is visible to the workgroup
+    gather_b((int)tot);
   }
 }
 
@@ -2445,8 +2653,8 @@ hipError_t launch_small(int bf16, int omp, const Inst* d, const int* list, int c
 
 template <typename TA>
 static hipError_t iht_grad_lpa(int lpa, const Inst* d, const ScanTile* tiles, int ntiles,
-                               int r_lds, int first, hipStream_t s) {
-  const dim3 g(ntiles), b(kBlock);
+                               int nslice, int r_lds, int first, hipStream_t s) {
+  const dim3 g(ntiles, nslice), b(kBlock);
   const size_t lds = (size_t)r_lds * sizeof(float);
   switch (lpa) {
     case 4: CLOMP_LAUNCH((iht_grad_kernel<TA, 4>), g, b, lds, s, d, tiles, r_lds, first); break;
@@ -2459,10 +2667,30 @@ static hipError_t iht_grad_lpa(int lpa, const Inst* d, const ScanTile* tiles, in
 }
 
 hipError_t launch_iht_grad(int bf16, int lpa, const Inst* d, const ScanTile* tiles, int ntiles,
-                           int r_lds, int first, hipStream_t s) {
+                           int nslice, int r_lds, int first, hipStream_t s) {
   if (ntiles <= 0) return nothing_to_launch(s);
-  return bf16 ? iht_grad_lpa<uint16_t>(lpa, d, tiles, ntiles, r_lds, first, s)
-              : iht_grad_lpa<float>(lpa, d, tiles, ntiles, r_lds, first, s);
+  return bf16 ? iht_grad_lpa<uint16_t>(lpa, d, tiles, ntiles, nslice, r_lds, first, s)
+              : iht_grad_lpa<float>(lpa, d, tiles, ntiles, nslice, r_lds, first, s);
+}
+
+hipError_t launch_paper_select(const Inst* dc, int nact, int it, int last, float thr,
+                               float lr_rel, float beta1, float beta2, float bc1, float bc2,
+                               float eps_rel, int nmax, hipStream_t s) {
+  if (nact <= 0) return nothing_to_launch(s);
+  if (nmax <= 4096)
+    CLOMP_LAUNCH((paper_select_kernel<256>), dim3(nact), dim3(256), 0, s, dc, it, last, thr,
+                 lr_rel, beta1, beta2, bc1, bc2, eps_rel);
+  else
+    CLOMP_LAUNCH((paper_select_kernel<1024>), dim3(nact), dim3(1024), 0, s, dc, it, last, thr,
+                 lr_rel, beta1, beta2, bc1, bc2, eps_rel);
+  return hipGetLastError();
+}
+
+hipError_t launch_iht_combine(const Inst* d, const ScanTile* tiles, int ntiles, int first,
+                              hipStream_t s) {
+  if (ntiles <= 0) return nothing_to_launch(s);
+  CLOMP_LAUNCH(iht_combine_kernel, dim3(ntiles), dim3(kBlock), 0, s, d, tiles, first);
+  return hipGetLastError();
 }
 
 hipError_t launch_iht_rows(int bf16, int mode, const Inst* d, const RowTile* tiles, int ntiles,
