@@ -1473,18 +1473,17 @@ __global__ __launch_bounds__(NT) void paper_select_kernel(const Inst* __restrict
   if (I.st->done || I.st->stop) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int n = I.n, K = I.k_eff;
-  const int C = (n + NT - 1) / NT;
-  const int j0 = tid * C, j1 = min(n, j0 + C);
   const float* c = I.gbuf;
   const unsigned* bits = I.bitmap;
   const int nsel_old = *I.nsel;
   auto gather_b = [&](int t1) {
     for (int l = tid; l < t1; l += NT) I.b[l] = I.c0[I.support[l]];
   };
+  auto in_mask = [&](int j) { return ((bits[j >> 5] >> (j & 31)) & 1u) != 0u; };
   // (1) cmax over every atom, and whether any correlation is non-finite
   float mx = 0.f;
   unsigned bad = 0u;
-  for (int j = j0; j < j1; ++j) {
+  for (int j = tid; j < n; j += NT) {
     const float a = fabsf(c[j]);
     bad |= (a <= 3.402823466e38f) ? 0u : 1u;
     mx = fmaxf(mx, a);
@@ -1526,49 +1525,58 @@ __global__ __launch_bounds__(NT) void paper_select_kernel(const Inst* __restrict
   } else {
     eps = I.st->eps;
   }
-  auto in_mask = [&](int j) { return ((bits[j >> 5] >> (j & 31)) & 1u) != 0u; };
   auto passes = [&](int j) { return fabsf(c[j]) / cmax >= thr; };
-  // (2) the batch of new atoms
+  // (2) the batch of new atoms (loads only)
   unsigned nnew = 0u;
-  for (int j = j0; j < j1; ++j) nnew += (!in_mask(j) && passes(j)) ? 1u : 0u;
+  for (int j = tid; j < n; j += NT) nnew += (!in_mask(j) && passes(j)) ? 1u : 0u;
   unsigned tot_new;
   (void)block_excl_scan<NT>(nnew, wsum, tot_new);
   const bool accept = tot_new > 0u && (unsigned)nsel_old + tot_new <= (unsigned)K;
   if (tid == 0 && tot_new > 0u && !accept) atomicOr(I.status, ST_K_CAPPED);
-  // (3) one Adam step on the masked coordinates (old mask plus the accepted
-  // batch); new bits are set here
+  // (3) rounds of NT contiguous chunks of C <= 64 atoms: a load-only pass
+  // marks the masked atoms of the chunk (old mask plus the accepted batch),
+  // a workgroup scan places them in index order, and only those take the
+  // Adam step (g = -c) and are written to the support
   const float lr = lr_rel * cmax;
-  unsigned cnt = 0u;
-  for (int j = j0; j < j1; ++j) {
-    const bool old = in_mask(j);
-    const bool add = !old && accept && passes(j);
-    if (!(old || add)) continue;
-    if (add) atomicOr(I.bitmap + (j >> 5), 1u << (j & 31));
-    const float g = -c[j];
-    const float mo = fmaf(beta1, I.mden[j], (1.f - beta1) * g);
-    const float ve = fmaf(beta2, I.vden[j], (1.f - beta2) * (g * g));
-    I.mden[j] = mo;
-    I.vden[j] = ve;
-    I.sfull[j] = I.sfull[j] - lr * (mo / bc1) / (sqrtf(ve / bc2) + eps);
-    ++cnt;
-  }
-  // (4) the support in index order, with its coefficients
-  unsigned tot;
-  unsigned pos = block_excl_scan<NT>(cnt, wsum, tot);
-  for (int j = j0; j < j1; ++j) {
-    // a set bit of this chunk is either old or set above by this thread, so
-    // the test agrees with (3) whichever copy of the word the load sees
-    const bool sel = in_mask(j) || (accept && passes(j));
-    if (sel) {
+  const int C = min(64, (n + NT - 1) / NT);
+  unsigned base = 0u;
+  for (int r0 = 0; r0 < n; r0 += NT * C) {
+    const int j0 = r0 + tid * C;
+    unsigned long long sel = 0ull, add = 0ull;
+    for (int q = 0; q < C; ++q) {
+      const int j = j0 + q;
+      if (j >= n) break;
+      if (in_mask(j)) {
+        sel |= 1ull << q;
+      } else if (accept && passes(j)) {
+        sel |= 1ull << q;
+        add |= 1ull << q;
+      }
+    }
+    unsigned tot;
+    unsigned pos = base + block_excl_scan<NT>((unsigned)__popcll(sel), wsum, tot);
+    while (sel) {
+      const int q = __ffsll((long long)sel) - 1;
+      sel &= sel - 1ull;
+      const int j = j0 + q;
+      if ((add >> q) & 1ull) atomicOr(I.bitmap + (j >> 5), 1u << (j & 31));
+      const float g = -c[j];
+      const float mo = fmaf(beta1, I.mden[j], (1.f - beta1) * g);
+      const float ve = fmaf(beta2, I.vden[j], (1.f - beta2) * (g * g));
+      const float sj = I.sfull[j] - lr * (mo / bc1) / (sqrtf(ve / bc2) + eps);
+      I.mden[j] = mo;
+      I.vden[j] = ve;
+      I.sfull[j] = sj;
       I.support[pos] = j;
-      I.s[pos] = I.sfull[j];
+      I.s[pos] = sj;
       ++pos;
     }
+    base += tot;
   }
-  if (tid == 0) *I.nsel = (int)tot;
+  if (tid == 0) *I.nsel = (int)base;
   if (last) {
     __syncthreads();   // the support written above is visible to the workgroup
-    gather_b((int)tot);
+    gather_b((int)base);
   }
 }
 
