@@ -26,6 +26,7 @@ Modules
   clomp_paper  F1  paper-mode CLOMP: normalised-threshold multi-selection, one
                    Adam step per iteration, R iterations
   iht        F4  normalised iterative hard thresholding (comparison method)
+  prior      F2  total-variation prior of Eq. (5) on x = D s (explicit DCT-II D)
   brute      O3  exhaustive support search for tiny instances
   grad       O4  loss/gradient of 1/2||A(mask*s) - y||^2;  O5 one Adam step
   lstsq      O6  least squares on a support;  FP64 residual norm
@@ -43,12 +44,14 @@ from .omp import omp_fp64
 from .clomp import clomp_fp64, ClompParams
 from .clomp_paper import clomp_paper_fp64, PaperParams
 from .iht import iht_fp64
+from .prior import dct_synthesis, forward_difference, tv_1d, tv_grad_coeffs, lstsq_support_tv
 from .brute import bruteforce_support
 from .separation import well_separated
 
 __all__ = [
     "lstsq_support", "resid_norm_fp64", "grad_fp64", "adam_step_fp64",
     "omp_fp64", "clomp_fp64", "ClompParams", "clomp_paper_fp64", "PaperParams", "iht_fp64",
+    "dct_synthesis", "forward_difference", "tv_1d", "tv_grad_coeffs", "lstsq_support_tv",
     "bruteforce_support",
     "well_separated",
 ]

@@ -40,6 +40,9 @@ Readings fixed here (the paper is silent on all of them):
     lr whatever the gradient's magnitude.)
   * loss scale 1/2 ||A(mask*s) - y||^2 (see grad.py).
 
+prior_tv = w > 0 adds the total-variation prior of Eq. (4)-(5) on the signal
+D (mask*s) to the loss, in step (iv) and in the refinement (prior.py).
+
 inner='exact' replaces step (iv) by the least-squares s-forward, which turns the
 loop into plain OMP (used as a reduction test).
 
@@ -54,6 +57,7 @@ import numpy as np
 
 from .grad import adam_step_fp64
 from .lstsq import lstsq_support
+from .prior import dct_synthesis, lstsq_support_tv, tv_grad_coeffs
 from .omp import (SolveResult, argmax_unselected, ST_NAN, ST_K_CAPPED,
                   ST_ZERO_Y, ST_EARLY_STOP)
 
@@ -66,6 +70,7 @@ class ClompParams:
     beta2: float = 0.999
     eps_rel: float = 1e-8      # eps = eps_rel * sigma
     resid_tol: float = 0.0     # stop when ||r|| <= resid_tol * ||y|| (0: off)
+    prior_tv: float = 0.0      # w of the total-variation prior (0: no prior)
 
 
 def clomp_fp64(A, y, k, params=ClompParams(), inner="adam", A_refine=None):
@@ -92,6 +97,8 @@ def clomp_fp64(A, y, k, params=ClompParams(), inner="adam", A_refine=None):
     step = 0
     S, gaps, hist = [], [], []
     lr = eps = sigma = 0.0
+    w_tv = params.prior_tv
+    D = dct_synthesis(n) if w_tv > 0.0 else None
 
     for t in range(k_eff):
         # (i) residual of the current estimate y' = A (mask * s)
@@ -127,6 +134,8 @@ def clomp_fp64(A, y, k, params=ClompParams(), inner="adam", A_refine=None):
                 u = AS @ s[S] - y
                 g = np.zeros(n)
                 g[S] = AS.T @ u
+                if D is not None:
+                    g[S] += w_tv * tv_grad_coeffs(np.where(mask, s, 0.0), D)[S]
                 s, mom, vel = adam_step_fp64(s, g, mom, vel, step, lr,
                                              params.beta1, params.beta2, eps)
 
@@ -134,7 +143,7 @@ def clomp_fp64(A, y, k, params=ClompParams(), inner="adam", A_refine=None):
         r = y - A @ np.where(mask, s, 0.0)
         hist.append(float(np.linalg.norm(r)))
     s_adam = s[S].copy()
-    xS = lstsq_support(Ar, y, S)
+    xS = lstsq_support(Ar, y, S) if D is None else lstsq_support_tv(Ar, y, S, w_tv, D)
     x[S] = xS
     rn = float(np.linalg.norm(y - Ar[:, S] @ xS))
     return SolveResult(S, x, rn, gaps, hist, status,

@@ -16,7 +16,8 @@ import pytest
 from oracle import (omp_fp64, clomp_fp64, ClompParams, clomp_paper_fp64, PaperParams,
                     iht_fp64, lstsq_support,
                     resid_norm_fp64, grad_fp64, adam_step_fp64,
-                    bruteforce_support, well_separated)
+                    bruteforce_support, well_separated,
+                    dct_synthesis, forward_difference, tv_1d, tv_grad_coeffs, lstsq_support_tv)
 from oracle.omp import ST_ZERO_Y, ST_K_CAPPED, ST_NAN, ST_EARLY_STOP
 from paper_2501_11592_amd import workloads as W
 
@@ -521,3 +522,130 @@ def test_workload_generators_are_deterministic():
     for sp in specs:
         assert 512 <= sp.n <= 8192 and 0.09 * sp.n <= sp.m <= 0.51 * sp.n
         assert math.ceil(sp.n / 64) <= sp.k <= sp.n // 16
+
+
+# ---------------------------------------------------------------- F2 TV prior
+# Eq. (5): TV(x) = (1/n) sum (x_j - x_{j+1})^2 on x = D s, D the DCT basis.
+
+def test_dct_synthesis_is_scipy_orthonormal_idct():
+    """Library special case: column k of D is the inverse orthonormal DCT-II of
+    the k-th unit vector; D is orthogonal."""
+    sfft = pytest.importorskip("scipy.fft")
+    for n in (1, 2, 7, 64, 255):
+        D = dct_synthesis(n)
+        ref = sfft.idct(np.eye(n), type=2, norm="ortho", axis=0)
+        np.testing.assert_allclose(D, ref, rtol=0, atol=1e-13)
+        np.testing.assert_allclose(D.T @ D, np.eye(n), rtol=0, atol=1e-12)
+
+
+def test_tv_of_dct_coefficients_closed_form():
+    """The DCT-II basis diagonalises the path-graph difference operator:
+    TV(D s) = (1/n) sum_k 4 sin^2(pi k / (2n)) s_k^2, and the gradient is
+    (2/n) * 4 sin^2(pi k / (2n)) s_k (an identity of the mathematics, not of
+    the oracle's explicit differences)."""
+    rng = np.random.default_rng(3)
+    for n in (2, 9, 128, 333):
+        s = rng.standard_normal(n)
+        lam = 4.0 * np.sin(np.pi * np.arange(n) / (2.0 * n)) ** 2
+        D = dct_synthesis(n)
+        assert abs(tv_1d(D @ s) - np.sum(lam * s * s) / n) <= 1e-12 * (1 + np.sum(s * s))
+        np.testing.assert_allclose(tv_grad_coeffs(s, D), (2.0 / n) * lam * s, rtol=0,
+                                   atol=1e-12 * np.abs(s).max())
+    # hand example: n = 3, x = (1, 0, 2): TV = (1 + 4) / 3
+    assert abs(tv_1d(np.array([1.0, 0.0, 2.0])) - 5.0 / 3.0) < 1e-15
+    np.testing.assert_array_equal(forward_difference(3),
+                                  np.array([[1.0, -1.0, 0.0], [0.0, 1.0, -1.0]]))
+
+
+def test_tv_prior_gradient_central_differences():
+    """The prior loss is quadratic in s: central differences are exact up to
+    rounding for the full loss 1/2||y - A(mask*s)||^2 + w TV(D(mask*s))."""
+    A, y, _, _ = gaussian_instance(31, 12, 40, 3)
+    rng = np.random.default_rng(5)
+    mask = np.zeros(40, dtype=bool)
+    mask[[2, 7, 19, 33]] = True
+    s = rng.standard_normal(40)
+    w = 0.37
+    D = dct_synthesis(40)
+
+    def loss(v):
+        vm = np.where(mask, v, 0.0)
+        return 0.5 * np.sum((A @ vm - y) ** 2) + w * tv_1d(D @ vm)
+
+    sm = np.where(mask, s, 0.0)
+    g = np.where(mask, A.T @ (A @ sm - y) + w * tv_grad_coeffs(sm, D), 0.0)
+    h = 1e-3
+    for j in range(40):
+        e = np.zeros(40)
+        e[j] = h
+        fd = (loss(s + e) - loss(s - e)) / (2 * h)
+        assert abs(fd - g[j]) <= 1e-9 * (1 + abs(g[j])), (j, fd, g[j])
+
+
+def test_clomp_prior_zero_weight_is_clomp():
+    A, y, _, _ = gaussian_instance(32, 24, 80, 5)
+    a = clomp_fp64(A, y, 6)
+    b = clomp_fp64(A, y, 6, ClompParams(prior_tv=0.0))
+    assert a.support == b.support
+    np.testing.assert_array_equal(a.extra["s_adam"], b.extra["s_adam"])
+    np.testing.assert_array_equal(a.x, b.x)
+
+
+def test_clomp_prior_refinement_solves_regularised_normal_equations():
+    """The refinement with the prior is the minimiser of the prior loss on the
+    support: (A_S^T A_S + w (2/n) (Delta D_S)^T (Delta D_S)) x = A_S^T y."""
+    A, y, _, _ = gaussian_instance(33, 20, 64, 4)
+    y = y + 0.05 * np.random.default_rng(1).standard_normal(20)
+    w = 2.5
+    res = clomp_fp64(A, y, 6, ClompParams(prior_tv=w))
+    S = res.support
+    D = dct_synthesis(64)
+    B = forward_difference(64) @ D[:, S]
+    lhs = A[:, S].T @ A[:, S] + w * (2.0 / 64) * B.T @ B
+    np.testing.assert_allclose(lhs @ res.x[S], A[:, S].T @ y, rtol=0, atol=1e-11)
+    # the prior pulls the fit away from the plain least squares
+    assert np.linalg.norm(res.x[S] - lstsq_support(A, y, S)) > 1e-6
+    np.testing.assert_allclose(lstsq_support_tv(A, y, S, w, D), res.x[S], rtol=0, atol=1e-13)
+
+
+def test_clomp_prior_matches_autograd_and_torch_adam_rendering():
+    """Independent rendering with framework pieces: the loss adds w * TV of the
+    signal D (mask * s) written with torch differences; autograd and
+    torch.optim.Adam as in the plain rendering."""
+    torch = pytest.importorskip("torch")
+    sfft = pytest.importorskip("scipy.fft")
+    for seed in range(2):
+        A, y, _, _ = gaussian_instance(40 + seed, 16, 48, 4)
+        y = y + 0.01 * np.random.default_rng(seed).standard_normal(16)
+        w = 0.8
+        P = ClompParams(inner_steps=12, lr_rel=0.05, prior_tv=w)
+        ref = clomp_fp64(A, y, 5, P)
+        At, yt = torch.tensor(A), torch.tensor(y)
+        Dt = torch.tensor(sfft.idct(np.eye(48), type=2, norm="ortho", axis=0))
+        s = torch.zeros(48, dtype=torch.float64, requires_grad=True)
+        mask = torch.zeros(48, dtype=torch.float64)
+        opt = None
+        S = []
+        for t in range(5):
+            with torch.no_grad():
+                c = At.T @ (yt - At @ (mask * s))
+                score = c.abs().clone()
+                score[mask.bool()] = -float("inf")
+                j = int(torch.argmax(score))
+                if t == 0:
+                    sig = float(c.abs().max())
+                    opt = torch.optim.Adam([s], lr=0.05 * sig, betas=(0.9, 0.999),
+                                           eps=1e-8 * sig, foreach=False)
+                opt.param_groups[0]["lr"] = 0.05 * abs(float(c[j]))
+                mask[j] = 1.0
+                S.append(j)
+            for _ in range(12):
+                opt.zero_grad()
+                xs = Dt @ (mask * s)
+                loss = 0.5 * ((At @ (mask * s) - yt) ** 2).sum() + \
+                    w * ((xs[:-1] - xs[1:]) ** 2).sum() / 48
+                loss.backward()
+                opt.step()
+        assert S == ref.support
+        np.testing.assert_allclose(s.detach().numpy()[S], ref.extra["s_adam"],
+                                   rtol=1e-10, atol=1e-12)
