@@ -114,6 +114,17 @@ typedef enum {
  *                returned in increasing index order.  A non-finite
  *                correlation (CLOMP_ST_NAN) or max|c| = 0 ends the loop; the
  *                support reached so far is refined.
+ *   prior_tv     CLOMP only: weight w >= 0 of the total-variation prior of
+ *                Eq. (4)-(5) on the signal x = D (mask*s), D the orthonormal
+ *                DCT-II synthesis basis (atom j of A = M D carries frequency
+ *                j).  The loss becomes 1/2 ||y - A(mask*s)||^2 + w TV(x) with
+ *                TV(x) = (1/n) sum_j (x_j - x_{j+1})^2, which equals (1/n)
+ *                sum_j 4 sin^2(pi j / (2n)) s_j^2; the Adam steps and the
+ *                final refinement (least squares with that penalty) use it,
+ *                the selection does not.  Served where the refinement runs
+ *                as the in-LDS QR ((m + k_eff) * k_eff within about 24K
+ *                floats), else clomp_solve_batch returns NOT_SUPPORTED.
+ *                0 (default): no prior.
  */
 typedef struct {
   int32_t method;
@@ -127,6 +138,7 @@ typedef struct {
   float refine_tol;
   uint32_t flags;
   float select_threshold;
+  float prior_tv;
 } clomp_params_t;
 
 /*

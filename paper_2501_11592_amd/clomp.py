@@ -39,7 +39,7 @@ class Params(ctypes.Structure):
                 ("beta2", ctypes.c_float), ("eps_rel", ctypes.c_float),
                 ("resid_tol", ctypes.c_float), ("refine_iters", ctypes.c_int32),
                 ("refine_tol", ctypes.c_float), ("flags", ctypes.c_uint32),
-                ("select_threshold", ctypes.c_float)]
+                ("select_threshold", ctypes.c_float), ("prior_tv", ctypes.c_float)]
 
 
 class Instance(ctypes.Structure):
@@ -174,7 +174,7 @@ class Solver:
 
     def __init__(self, device=0, method="clomp", inner_steps=None, lr_rel=0.05,
                  beta1=0.9, beta2=0.999, eps_rel=1e-8, refine_iters=0,
-                 refine_tol=0.0, flags=0, select_threshold=0.7):
+                 refine_tol=0.0, flags=0, select_threshold=0.7, prior_tv=0.0):
         lib = load_library()
         if not torch.cuda.is_available():
             raise ClompError("no GPU available: the CLOMP library runs only on the device")
@@ -188,6 +188,7 @@ class Solver:
         p.inner_steps, p.lr_rel, p.beta1, p.beta2 = inner_steps, lr_rel, beta1, beta2
         p.eps_rel, p.refine_iters, p.refine_tol, p.flags = eps_rel, refine_iters, refine_tol, flags
         p.select_threshold = select_threshold
+        p.prior_tv = prior_tv
         self.params = p
         h = ctypes.c_void_p()
         _check(None, lib.clomp_create(ctypes.byref(h), self.device.index or 0, ctypes.byref(p)),

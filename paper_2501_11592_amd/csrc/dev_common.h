@@ -80,7 +80,7 @@ struct Inst {
   float* H;            // [ldh * k_eff] columns A^T a_{S_l} (correlation-update schedule)
   long long ldh;
   int nslice;          // IHT: slices of m in the gradient scan (>= 1)
-  int pad_ns;
+  float tvw;           // 2w/n for the total-variation prior of weight w (0: none)
   unsigned long long* team;   // [2*k_eff + 2*kTeamMax] tagged words exchanged by a team
                               // (correlation-update schedule; zeroed at solve start)
   float* gbuf;         // IHT: [nslice * ldh] per-slice partial dots; g = A^T r of the
@@ -94,6 +94,16 @@ struct Inst {
   unsigned* bitmap;
   InstState* st;
 };
+
+// Total-variation prior (Eq. (5)) on x = D s with D the orthonormal DCT-II
+// synthesis basis: that basis diagonalises the neighbour-difference operator,
+// so TV(D s) = (1/n) sum_j 4 sin^2(pi j / (2n)) s_j^2 and the prior adds
+// (2w/n) * 4 sin^2(pi j / (2n)) to the Gram diagonal of atom j.
+__device__ inline float tv_diag(const Inst& I, int j) {
+  if (I.tvw == 0.f) return 0.f;
+  const float sn = sinf(1.5707963267948966f * (float)j / (float)I.n);
+  return I.tvw * 4.f * sn * sn;
+}
 
 // A scan tile: atoms [j0, j1) of instance `inst`.
 struct ScanTile {

@@ -187,6 +187,10 @@ clomp_status_t check_params(clomp_ctx* h, const clomp_params_t* p) {
     return fail(h, CLOMP_INVALID_ARGUMENT, "IHT and paper mode need inner_steps (iterations) >= 1");
   if (p->method == CLOMP_METHOD_PAPER && !(p->select_threshold > 0.f && p->select_threshold <= 1.f))
     return fail(h, CLOMP_INVALID_ARGUMENT, "select_threshold must lie in (0, 1]");
+  if (!(p->prior_tv >= 0.f && p->prior_tv <= 3.402823466e38f))
+    return fail(h, CLOMP_INVALID_ARGUMENT, "prior_tv must be finite and >= 0");
+  if (p->prior_tv > 0.f && p->method != CLOMP_METHOD_CLOMP)
+    return fail(h, CLOMP_NOT_SUPPORTED, "the total-variation prior is served for CLOMP only");
   if (p->inner_steps < 0 || p->inner_steps > 100000)
     return fail(h, CLOMP_INVALID_ARGUMENT, "inner_steps %d out of range", p->inner_steps);
   if (!(p->beta1 >= 0.f && p->beta1 < 1.f) || !(p->beta2 >= 0.f && p->beta2 < 1.f))
@@ -335,7 +339,10 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     d.ldg = round_up_int(d.k_eff, 4);
     d.m_pad = round_up_int(d.m, 8);
     d.n_rowtiles = (d.m + 63) / 64;
-    const bool use_qr = (size_t)d.m * d.k_eff + d.m + 2 * d.k_eff <= (size_t)qr_limit_floats;
+    // with the prior the refinement's QR holds k_eff stacked rows more
+    d.tvw = (prm.prior_tv > 0.f) ? 2.f * prm.prior_tv / (float)d.n : 0.f;
+    const size_t qr_rows = (size_t)d.m + (d.tvw != 0.f ? d.k_eff : 0);
+    const bool use_qr = qr_rows * d.k_eff + qr_rows + 2 * d.k_eff <= (size_t)qr_limit_floats;
     d.cg_slot = use_qr ? -1 : 0;
     // workspace offsets (relative; rebased after allocation)
     auto take = [&](size_t bytes) {
@@ -507,7 +514,8 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     const Inst& d = P.insts[q];
     if (d.cg_slot < 0) {
       P.qr_list.push_back(q);
-      P.qr_lds = std::max(P.qr_lds, sizeof(float) * ((size_t)d.m * d.k_eff + d.m + 2 * d.k_eff));
+      const size_t qr_rows = (size_t)d.m + (d.tvw != 0.f ? d.k_eff : 0);
+      P.qr_lds = std::max(P.qr_lds, sizeof(float) * (qr_rows * d.k_eff + qr_rows + 2 * d.k_eff));
     } else {
       P.insts[q].cg_slot = (int)P.cg_list.size();
       P.cg_list.push_back(q);
@@ -1102,6 +1110,7 @@ void clomp_default_params(clomp_params_t* p) {
   p->refine_tol = 0.f;
   p->flags = 0u;
   p->select_threshold = 0.7f;
+  p->prior_tv = 0.f;
 }
 
 const char* clomp_status_string(clomp_status_t s) {
@@ -1246,6 +1255,10 @@ clomp_status_t clomp_solve_batch(clomp_handle_t h, const clomp_instance_t* inst,
   const Plan& PP = h->pcache.P;
   h->last_scan_kb = scan_kb;
   h->last_pass_kb = pass_kb;
+  if (h->params.prior_tv > 0.f && !PP.cg_list.empty())
+    return fail(h, CLOMP_NOT_SUPPORTED,
+                "the total-variation prior needs the in-LDS QR refinement: (m + k_eff) * k_eff "
+                "of a signal exceeds it");
   if ((size_t)PP.cg_mpad_max * sizeof(float) + 1024 > (size_t)h->lds_limit)
     return fail(h, CLOMP_NOT_SUPPORTED,
                 "m = %d needs %zu bytes of LDS for the refinement; the device allows %d",

@@ -320,6 +320,7 @@ __global__ __launch_bounds__(kBlock) void gram_kernel(const Inst* __restrict__ i
         v = group_sum<LPA>(acc);
       }
       if (gl == 0) {
+        if (l == t) v += tv_diag(I, j);
         I.G[l + (long long)t * I.ldg] = v;
         I.G[t + (long long)l * I.ldg] = v;
       }
@@ -421,8 +422,9 @@ __global__ __launch_bounds__(kBlock) void gram_reg_kernel(const Inst* __restrict
       if (ydot) {
         I.b[t] = d;
       } else {
-        I.G[l + (long long)t * I.ldg] = d;
-        I.G[t + (long long)l * I.ldg] = d;
+        const float dd = (l == t) ? d + tv_diag(I, j) : d;
+        I.G[l + (long long)t * I.ldg] = dd;
+        I.G[t + (long long)l * I.ldg] = dd;
       }
     }
   }
@@ -1012,24 +1014,28 @@ __global__ __launch_bounds__(kBlock) void qr_refine_kernel(const Inst* __restric
   if (I.st->done) return;
   const int m = I.m;
   const int t1 = *I.nsel;
-  float* M = qsh;                  // m x t1 column-major (ld m)
-  float* yv = qsh + (long long)m * t1;   // m
-  float* Rd = yv + m;              // t1 diagonal of R
+  // with the total-variation prior the system is stacked: t1 more rows
+  // holding sqrt((2w/n) lambda_{S_c}) on the diagonal, right-hand side 0
+  const int mr = (I.tvw != 0.f) ? m + t1 : m;
+  float* M = qsh;                  // mr x t1 column-major (ld mr)
+  float* yv = qsh + (long long)mr * t1;   // mr
+  float* Rd = yv + mr;             // t1 diagonal of R
   float* xs = Rd + t1;             // t1 solution
-  for (int idx = threadIdx.x; idx < m * t1; idx += kBlock) {
-    const int c = idx / m, i = idx - c * m;
-    M[idx] = I.Am[(long long)I.support[c] * I.ldam + i];
+  for (int idx = threadIdx.x; idx < mr * t1; idx += kBlock) {
+    const int c = idx / mr, i = idx - c * mr;
+    M[idx] = (i < m) ? I.Am[(long long)I.support[c] * I.ldam + i]
+                     : ((i - m == c) ? sqrtf(tv_diag(I, I.support[c])) : 0.f);
   }
   const float* yw = I.r + I.m_pad;
-  for (int i = threadIdx.x; i < m; i += kBlock) yv[i] = yw[i];
+  for (int i = threadIdx.x; i < mr; i += kBlock) yv[i] = (i < m) ? yw[i] : 0.f;
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   bool rank_def = false;
   for (int c = 0; c < t1; ++c) {
-    float* Mc = M + (long long)c * m;
+    float* Mc = M + (long long)c * mr;
     float p = 0.f;
-    for (int i = c + threadIdx.x; i < m; i += kBlock) p = fmaf(Mc[i], Mc[i], p);
+    for (int i = c + threadIdx.x; i < mr; i += kBlock) p = fmaf(Mc[i], Mc[i], p);
     const float nrm2 = block_sum(p, red);
     const float x0 = Mc[c];
     const float nrm = sqrtf(nrm2);
@@ -1038,7 +1044,7 @@ __global__ __launch_bounds__(kBlock) void qr_refine_kernel(const Inst* __restric
     const float vn2 = nrm2 - x0 * x0 + v0 * v0;   // ||v||^2
     __syncthreads();
     if (threadIdx.x == 0) {
-      Mc[c] = v0;        // v stored in place (rows c..m-1)
+      Mc[c] = v0;        // v stored in place (rows c..mr-1)
       diag[0] = alpha;
     }
     __syncthreads();
@@ -1052,11 +1058,11 @@ __global__ __launch_bounds__(kBlock) void qr_refine_kernel(const Inst* __restric
     // apply H = I - 2 v v^T / (v^T v) to columns c+1..t1-1 and y: one wave per
     // target, lanes over rows
     for (int cc = c + 1 + wv; cc <= t1; cc += kWaves) {
-      float* tgt = (cc < t1) ? (M + (long long)cc * m) : yv;
+      float* tgt = (cc < t1) ? (M + (long long)cc * mr) : yv;
       float d = 0.f;
-      for (int i = c + lane; i < m; i += 64) d = fmaf(Mc[i], tgt[i], d);
+      for (int i = c + lane; i < mr; i += 64) d = fmaf(Mc[i], tgt[i], d);
       d = wave_sum(d) * inv;
-      for (int i = c + lane; i < m; i += 64) tgt[i] = fmaf(-d, Mc[i], tgt[i]);
+      for (int i = c + lane; i < mr; i += 64) tgt[i] = fmaf(-d, Mc[i], tgt[i]);
     }
     __syncthreads();
   }
@@ -1065,7 +1071,7 @@ __global__ __launch_bounds__(kBlock) void qr_refine_kernel(const Inst* __restric
   for (int c = t1 - 1; c >= 0; --c) {
     if (wv == 0) {
       float sacc = 0.f;
-      for (int cc = c + 1 + lane; cc < t1; cc += 64) sacc = fmaf(M[c + (long long)cc * m], xs[cc], sacc);
+      for (int cc = c + 1 + lane; cc < t1; cc += 64) sacc = fmaf(M[c + (long long)cc * mr], xs[cc], sacc);
       sacc = wave_sum(sacc);
       if (lane == 0) {
         const float d = Rd[c];
@@ -1734,7 +1740,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_loop_kernel(
 #pragma unroll
         for (int q = 0; q < kSmallDots; ++q) {
           const int l = w + q * kSmallWaves;
-          if (l < t + 2) gcol[l] = part[q];
+          if (l < t + 2) gcol[l] = (l == t) ? part[q] + tv_diag(I, j) : part[q];
         }
       }
     }
@@ -1973,7 +1979,7 @@ __device__ void pass_tile_body(const Inst& I, const ScanTile& tile, int t, float
       nrm = group_sum<LPA>(nrm);
       if (gl == 0) {
         I.c0[j] = acc;
-        I.dg[j] = nrm;
+        I.dg[j] = nrm + tv_diag(I, j);   // Gram diagonal (prior included)
       }
       const unsigned long long key = pack_key(acc, j);
       best = key > best ? key : best;
