@@ -8,7 +8,8 @@ non-zeros +-(1+|N(0,1)|), y = A s + N(0, 1e-4); batch of one, so every greedy
 iteration streams the whole 268 MB dictionary (HBM-bound).
 
 Other workloads (--workload): small1d (1000 signals n=256 m=64 k=8), image
-(256 columns sharing A, sampling rate 0.1/0.3/0.5), uneven (4096 signals of
+(256 columns sharing A, sampling rate 0.1/0.3/0.5), image4k (3840 columns of
+n=2160 sharing A, k=108: the shared-dictionary schedule), uneven (4096 signals of
 uneven size, BF16 bulk + FP32 master), flat (n=65536, m=19661, k=2048, BF16
 CLOMP vs FP32 OMP).
 
@@ -43,7 +44,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large1d",
-                    choices=["large1d", "small1d", "image", "uneven", "flat"])
+                    choices=["large1d", "small1d", "image", "image4k", "uneven", "flat"])
     ap.add_argument("--sr", type=float, default=0.3, help="image workload sampling rate")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
@@ -113,6 +114,17 @@ def build_workload(args, torch, W):
                     desc=f"256 columns of a synthetic 256x256 image sharing one Gaussian A, "
                          f"sampling rate {args.sr} (m={b.m}), power-law k=32, float32",
                     cfg=dict(n=b.n, m=b.m, k=b.k, batch=256, shared_A=True),
+                    clomp_items=items, omp_items=items, dtype="f32", host=b)
+    if args.workload == "image4k":
+        log("drawing the 4K-scale image batch (3840 columns, n=2160)")
+        b = W.image4k_batch(args.sr)
+        At = torch.from_numpy(b.At).to(dev)
+        Y = torch.from_numpy(b.Y).to(dev)
+        items = [dict(At=At, m=b.m, y=Y[c], k=b.k) for c in range(Y.shape[0])]
+        return dict(name=f"image4k_sr{args.sr}",
+                    desc=f"3840 columns of a synthetic 3840x2160 image sharing one Gaussian A, "
+                         f"sampling rate {args.sr} (m={b.m}), power-law k={b.k}, float32",
+                    cfg=dict(n=b.n, m=b.m, k=b.k, batch=3840, shared_A=True),
                     clomp_items=items, omp_items=items, dtype="f32", host=b)
     if args.workload == "uneven":
         log("drawing the uneven batch on the device (4096 signals, ~89 GB)")

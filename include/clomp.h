@@ -87,6 +87,14 @@ typedef enum {
                                         iterated signals fits in 16 GB and the
                                         staged vector in LDS; the flag only
                                         documents the choice)                 */
+#define CLOMP_FLAG_NO_SHARED_GRAM 64u/* when every iterated signal of a batch
+                                        has the same A (pointer, layout and
+                                        master), the library by default forms
+                                        the full Gram matrix A^T A and every
+                                        c0 = A^T y once (n^2 floats, up to
+                                        4 GB) and iterates without passes over
+                                        A; this flag keeps the per-signal
+                                        passes                                 */
 
 /*
  * Solver parameters.  The paper states the optimiser only as automatic

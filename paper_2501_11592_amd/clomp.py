@@ -26,7 +26,7 @@ METHODS = {"clomp": METHOD_CLOMP, "omp": METHOD_OMP, "iht": METHOD_IHT,
            "clomp_paper": METHOD_PAPER}
 ST_NAN, ST_K_CAPPED, ST_ZERO_Y, ST_REFINE_INACCURATE, ST_WATCHDOG = 1, 2, 4, 8, 32
 FLAG_GRAPH, FLAG_NO_FUSED_SMALL, FLAG_AUTOTUNE, FLAG_PROFILE = 1, 2, 4, 8
-FLAG_RESIDUAL_FLOW, FLAG_CORR_FLOW = 16, 32
+FLAG_RESIDUAL_FLOW, FLAG_CORR_FLOW, FLAG_NO_SHARED_GRAM = 16, 32, 64
 PHASES = ("scan", "gram", "coef", "resid", "refine", "norm", "init", "pass", "fused")
 
 STATUS_NAMES = {0: "CLOMP_OK", 1: "CLOMP_INVALID_ARGUMENT", 2: "CLOMP_OUT_OF_MEMORY",

@@ -78,6 +78,8 @@ struct Inst {
   float* c0;           // [ldh] A^T y (correlation-update schedule)
   float* dg;           // [ldh] ||a_j||^2 (correlation-update schedule)
   float* H;            // [ldh * k_eff] columns A^T a_{S_l} (correlation-update schedule)
+  const float* Gf;     // shared dictionary: [ldh * ldh] full Gram A^T A of the batch's one
+                       // matrix (column j = A^T a_j); H is then not stored
   long long ldh;
   int nslice;          // IHT: slices of m in the gradient scan (>= 1)
   float tvw;           // 2w/n for the total-variation prior of weight w (0: none)
@@ -103,6 +105,12 @@ __device__ inline float tv_diag(const Inst& I, int j) {
   if (I.tvw == 0.f) return 0.f;
   const float sn = sinf(1.5707963267948966f * (float)j / (float)I.n);
   return I.tvw * 4.f * sn * sn;
+}
+
+// Column l of H = A^T a_{S_l} (valid rows 0..n-1, padded to ldh): stored per
+// signal, or column S_l of the shared full Gram matrix.
+__device__ inline const float* hcol(const Inst& I, int l) {
+  return I.Gf ? I.Gf + (long long)I.support[l] * I.ldh : I.H + (long long)l * I.ldh;
 }
 
 // A scan tile: atoms [j0, j1) of instance `inst`.

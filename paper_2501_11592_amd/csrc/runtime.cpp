@@ -75,6 +75,8 @@ struct Plan {
   size_t qr_lds = 0;
   int kmax = 0, cg_tmax = 0, cg_mpad_max = 0, cg_lpa = 64;
   bool hflow = false;                 // correlation-update schedule
+  bool gflow = false;                 // ... with a shared dictionary: full Gram, no passes
+  size_t off_gf = 0, off_gdg = 0;     // shared Gram matrix and diagonal (workspace)
   int nbig = 0;                       // sorted instances [0, nbig) use the iterated kernels;
                                       // [nbig, count) run the fused small-signal loop
   std::vector<int> small_list;
@@ -304,16 +306,39 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
                       (size_t)mpad_max * 4 + 34 * 1024 <= (size_t)h->lds_limit &&
                       hbytes <= (size_t)16 << 30;
     const uint32_t fl = prm.flags;
+    // shared dictionary: every iterated signal has the same A (pointer, layout,
+    // master) and the full Gram matrix fits in 4 GB; an iteration then reads
+    // columns of A^T A instead of streaming A
+    bool shared = P.nbig >= 2 && !iht && !(fl & CLOMP_FLAG_RESIDUAL_FLOW) &&
+                  !(fl & CLOMP_FLAG_NO_SHARED_GRAM);
+    for (int s = 1; s < P.nbig && shared; ++s) {
+      const clomp_instance_t& a = inst[order[0]];
+      const clomp_instance_t& b = inst[order[s]];
+      shared = a.A == b.A && a.lda == b.lda && a.n == b.n && a.m == b.m &&
+               a.A_master == b.A_master && a.lda_master == b.lda_master;
+    }
+    if (shared) {
+      const size_t l = (size_t)round_up_int(inst[order[0]].n, 256);
+      shared = l * l * sizeof(float) <= ((size_t)4 << 30);
+    }
+    P.gflow = shared;
     // measured faster than the residual schedule on every iterated workload
     // (the pass and the coefficient update share one launch per iteration)
-    P.hflow = P.nbig > 0 && fits && !(fl & CLOMP_FLAG_RESIDUAL_FLOW) && !iht;
+    P.hflow = P.nbig > 0 && (P.gflow || (fits && !(fl & CLOMP_FLAG_RESIDUAL_FLOW) && !iht));
   }
-  snprintf(sigbuf, sizeof sigbuf, "h%d;f%d;", (int)P.hflow, count - P.nbig);
+  snprintf(sigbuf, sizeof sigbuf, "h%d;g%d;f%d;", (int)P.hflow, (int)P.gflow, count - P.nbig);
   P.sig += sigbuf;
   P.insts.resize(count);
   P.keff.resize(count);
   P.kmax = 0;
   size_t ws = 0;
+  if (P.gflow) {
+    const size_t l = (size_t)round_up_int(inst[order[0]].n, 256);
+    P.off_gf = ws;
+    ws = align_up(ws + sizeof(float) * l * l, kAlign);
+    P.off_gdg = ws;
+    ws = align_up(ws + sizeof(float) * l, kAlign);
+  }
   snprintf(sigbuf, sizeof sigbuf, "d%d;m%d;T%d;s%d;p%d;w%d;", bf16, prm.method,
            prm.inner_steps, scan_kb, pass_kb, h->team_min_rows);
   P.sig += sigbuf;
@@ -377,8 +402,9 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     if (hf) {
       d.ldh = round_up_int(d.n, 256);
       o_c0 = take(sizeof(float) * d.ldh);
-      o_dg = take(sizeof(float) * d.ldh);
-      o_H = take(sizeof(float) * (size_t)d.ldh * d.k_eff);
+      // the shared-dictionary schedule keeps one diagonal and no H
+      o_dg = P.gflow ? P.off_gdg : take(sizeof(float) * d.ldh);
+      o_H = P.gflow ? 0 : take(sizeof(float) * (size_t)d.ldh * d.k_eff);
       o_team = take(sizeof(unsigned long long) * (2 * (size_t)d.k_eff + 2 * kTeamMax));
     }
     const size_t o_np = take(sizeof(double) * d.n_rowtiles);
@@ -404,7 +430,8 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     d.vden = paper ? (float*)(o_vd + 1) : nullptr;
     d.dg = hf ? (float*)(o_dg + 1) : nullptr;
     d.team = hf ? (unsigned long long*)(o_team + 1) : nullptr;
-    d.H = hf ? (float*)(o_H + 1) : nullptr;
+    d.H = (hf && !P.gflow) ? (float*)(o_H + 1) : nullptr;
+    d.Gf = (hf && P.gflow) ? (const float*)(P.off_gf + 1) : nullptr;
     d.npart = (double*)(o_np + 1);
     d.qpart = (float*)(o_qp + 1);
     d.key = (unsigned long long*)(o_key + 1);
@@ -635,8 +662,27 @@ clomp_status_t launch_hflow(clomp_ctx* h, const Plan& P, int bf16, hipStream_t s
     while (c.i0 + q < c.i1 && P.keff[c.i0 + q] > t) ++q;
     return q;
   };
+  if (P.gflow) {
+    // shared dictionary: Gf = A^T A, every c0 = A^T y and the diagonal once,
+    // then the first argmax from c0
+    char* wsb = reinterpret_cast<char*>(h->ws.p);
+    {
+      PhaseScope ps(h, PH_SCAN, st);
+      HIP_TRY(launch_shared_gram(bf16, d_insts, P.nbig, P.insts[0].n,
+                                 reinterpret_cast<float*>(wsb + P.off_gf),
+                                 reinterpret_cast<float*>(wsb + P.off_gdg), st),
+              "shared gram");
+    }
+    for (const Class& c : P.classes) {
+      const int nall = c.i1 - c.i0;
+      PhaseScope ps(h, PH_SCAN, st);
+      HIP_TRY(launch_cscan(d_insts, d_ctiles + c.ctile_off, c.ctile_prefix[nall], 0, st),
+              "cscan");
+    }
+  }
   // c0 = A^T y and the first argmax
   for (const Class& c : P.classes) {
+    if (P.gflow) break;
     const int nall = c.i1 - c.i0;
     const size_t lds = (size_t)c.m_pad_max * sizeof(float);
     PhaseScope ps(h, PH_SCAN, st);
@@ -670,12 +716,13 @@ clomp_status_t launch_hflow(clomp_ctx* h, const Plan& P, int bf16, hipStream_t s
         if (!omp && t1 > 256 && t1 <= 1024) lds = std::max(lds, (size_t)2048 * sizeof(float));
         if (W > 1) lds = std::max(lds, (t1 + 4 + 32) * sizeof(float));
         PhaseScope ps(h, PH_PASS, st);
+        // a shared dictionary has every column of H already (no pass tiles)
         HIP_TRY(launch_coef_pass(bf16, c.lpa, omp, d_insts + c.i0, nact, W, d_insts,
-                                 d_htiles + c.htile_off, c.htile_prefix[nnext], t,
+                                 d_htiles + c.htile_off, P.gflow ? 0 : c.htile_prefix[nnext], t,
                                  prm.inner_steps, prm.beta1, prm.beta2, prm.lr_rel, prm.eps_rel,
                                  lds, st),
                 "coef_pass");
-        if (h->profiling)
+        if (h->profiling && !P.gflow)
           for (int q = c.i0; q < c.i0 + nnext; ++q)
             h->pass_bytes += (double)P.insts[q].m * P.insts[q].n * esz + 4.0 * P.insts[q].n;
       }
@@ -965,7 +1012,7 @@ clomp_status_t stage_plan(clomp_ctx* h, const Plan& P, hipStream_t st) {
     };
     rb(d.r); rb(d.G); rb(d.b); rb(d.s); rb(d.mo); rb(d.ve); rb(d.xf); rb(d.z);
     rb(d.Linv); rb(d.cg); rb(d.c0); rb(d.dg); rb(d.H); rb(d.team); rb(d.gbuf); rb(d.sfull);
-    rb(d.mden); rb(d.vden);
+    rb(d.mden); rb(d.vden); rb(d.Gf);
     rb(d.npart);
     rb(d.qpart); rb(d.key);
     rb(d.bitmap);

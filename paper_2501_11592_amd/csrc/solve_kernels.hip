@@ -2051,13 +2051,97 @@ __device__ inline void team_retire(const Inst& I, int w) {
     I.st->done = 1;
 }
 
+// ---- shared dictionary (every iterated signal of the batch has the same A)
+// The batch computes the full Gram matrix Gf = A^T A and c0 = A^T y of every
+// signal once; an iteration then needs no pass over A: column S_l of Gf is
+// H's column l, and the new Gram row of the coefficient update is a lookup.
+// C[i, q] = sum_k A[i][k] B_q[k] over 64 x 64 output tiles (4 x 4 per thread),
+// k in chunks of 32 staged in LDS.  MODE 0: B_q = atom q, C = Gf (ld ldh);
+// MODE 1: B_q = y of signal q (the workspace copy), C[:, q] = c0 of signal q.
+constexpr int kGemmTile = 64, kGemmK = 32;
+
+template <typename TA, int MODE>
+__global__ __launch_bounds__(256) void shared_gemm_kernel(const Inst* __restrict__ insts, int nsig,
+                                                          float* __restrict__ Gf) {
+  __shared__ __align__(16) float As[kGemmK][kGemmTile + 4];
+  __shared__ __align__(16) float Bs[kGemmK][kGemmTile + 4];
+  const Inst& I0 = insts[0];
+  const TA* A = reinterpret_cast<const TA*>(I0.A);
+  const long long lda = I0.lda, ldh = I0.ldh;
+  const int n = I0.n, m = I0.m;
+  const int ncols = (MODE == 0) ? n : nsig;
+  const int i0 = blockIdx.x * kGemmTile, q0 = blockIdx.y * kGemmTile;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  float acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.f;
+  for (int k0 = 0; k0 < m; k0 += kGemmK) {
+    // consecutive threads walk k along one row (contiguous in memory)
+    for (int e = threadIdx.x; e < kGemmTile * kGemmK; e += 256) {
+      const int r = e / kGemmK, kk = e - r * kGemmK;
+      const int k = k0 + kk;
+      const int i = i0 + r, q = q0 + r;
+      As[kk][r] = (i < n && k < m) ? Vec<TA>::one(A + (long long)i * lda + k) : 0.f;
+      float bv = 0.f;
+      if (q < ncols && k < m) {
+        if (MODE == 0) {
+          bv = Vec<TA>::one(A + (long long)q * lda + k);
+        } else {
+          const Inst& Iq = insts[q];
+          bv = Iq.r[Iq.m_pad + k];
+        }
+      }
+      Bs[kk][r] = bv;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < kGemmK; ++kk) {
+      const float4 a = *reinterpret_cast<const float4*>(&As[kk][4 * ty]);
+      const float4 b = *reinterpret_cast<const float4*>(&Bs[kk][4 * tx]);
+      const float av[4] = {a.x, a.y, a.z, a.w};
+      const float bw[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fmaf(av[u], bw[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = i0 + 4 * ty + u;
+    if (i >= n) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int q = q0 + 4 * tx + v;
+      if (q >= ncols) continue;
+      if (MODE == 0)
+        Gf[i + (long long)q * ldh] = acc[u][v];
+      else
+        insts[q].c0[i] = acc[u][v];
+    }
+  }
+}
+
+// The shared Gram diagonal (prior included) for the coefficient updates.
+__global__ __launch_bounds__(kBlock) void shared_diag_kernel(const Inst* __restrict__ insts,
+                                                             const float* __restrict__ Gf,
+                                                             float* __restrict__ dg) {
+  const Inst& I0 = insts[0];
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j < I0.n) dg[j] = Gf[j + (long long)j * I0.ldh] + tv_diag(I0, j);
+}
+
+
 // Entry G[r, c] of the Gram matrix during iteration t (atom j selected):
 // entries of earlier iterations from G, the new row / column from H and the
 // norms (member 0 writes them to G in this same launch).
 __device__ inline float gram_at(const Inst& I, int j, int t, int r, int c) {
   if (r < t && c < t) return I.G[c + (long long)r * I.ldg];
   if (r == t && c == t) return I.dg[j];
-  return I.H[j + (long long)(r < t ? r : c) * I.ldh];
+  return hcol(I, r < t ? r : c)[j];
 }
 
 // Adam on rows [16w, 16w+16) of a support of t+1 atoms (same update as the
@@ -2156,7 +2240,7 @@ __device__ void omp_team_body(const Inst& I, int j, int t, int W, int w, float* 
   float* Gi = I.Linv;
   float* g = lds;                                    // [t+1]
   float* red = lds + t + 1;                          // [32]
-  for (int c = tid; c <= t; c += kPassThreads) g[c] = (c < t) ? I.H[j + (long long)c * I.ldh] : I.dg[j];
+  for (int c = tid; c <= t; c += kPassThreads) g[c] = (c < t) ? hcol(I, c)[j] : I.dg[j];
   __syncthreads();
   unsigned long long* vbuf = I.team;                 // [k_eff]
   unsigned long long* pbuf = I.team + 2 * (size_t)I.k_eff;   // [2][kTeamMax]
@@ -2264,7 +2348,7 @@ __global__ __launch_bounds__(kPassThreads) void coef_pass_kernel(
     constexpr bool team = COEF == COEF_ADAM_TEAM || COEF == COEF_OMP_TEAM;
     if (member == 0) {
       for (int l = threadIdx.x; l < t; l += kPassThreads) {
-        const float g = I.H[j + (long long)l * I.ldh];
+        const float g = hcol(I, l)[j];
         I.G[l + (long long)t * I.ldg] = g;
         I.G[t + (long long)l * I.ldg] = g;
       }
@@ -2333,7 +2417,6 @@ __global__ __launch_bounds__(kCscanThreads) void cscan_kernel(const Inst* __rest
   const int q = lane & 15;
   const int L = 4 * w + (lane >> 4);
   const float* ssh = I.s;                  // t coefficients, read through L2
-  const long long ldh = I.ldh;
   unsigned long long key = 0ull;
   // the tile spans one or more 64-atom sub-tiles (tiles start at multiples
   // of 64); one atomicMax per tile
@@ -2349,11 +2432,10 @@ __global__ __launch_bounds__(kCscanThreads) void cscan_kernel(const Inst* __rest
     }
     float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
     if (j < tile.j1) {
-      const float* Hj = I.H + j;
       int l = L;
       for (; l + 64 < t; l += 128) {
-        const float4 h0 = *reinterpret_cast<const float4*>(Hj + (long long)l * ldh);
-        const float4 h1 = *reinterpret_cast<const float4*>(Hj + (long long)(l + 64) * ldh);
+        const float4 h0 = *reinterpret_cast<const float4*>(hcol(I, l) + j);
+        const float4 h1 = *reinterpret_cast<const float4*>(hcol(I, l + 64) + j);
         const float s0 = ssh[l], s1 = ssh[l + 64];
         a0.x = fmaf(h0.x, s0, a0.x); a0.y = fmaf(h0.y, s0, a0.y);
         a0.z = fmaf(h0.z, s0, a0.z); a0.w = fmaf(h0.w, s0, a0.w);
@@ -2361,7 +2443,7 @@ __global__ __launch_bounds__(kCscanThreads) void cscan_kernel(const Inst* __rest
         a1.z = fmaf(h1.z, s1, a1.z); a1.w = fmaf(h1.w, s1, a1.w);
       }
       if (l < t) {
-        const float4 h0 = *reinterpret_cast<const float4*>(Hj + (long long)l * ldh);
+        const float4 h0 = *reinterpret_cast<const float4*>(hcol(I, l) + j);
         const float s0 = ssh[l];
         a0.x = fmaf(h0.x, s0, a0.x); a0.y = fmaf(h0.y, s0, a0.y);
         a0.z = fmaf(h0.z, s0, a0.z); a0.w = fmaf(h0.w, s0, a0.w);
@@ -2858,6 +2940,22 @@ hipError_t launch_coef_pass(int bf16, int lpa, int omp, const Inst* dc, int nact
                                              beta1, beta2, lr_rel, eps_rel, lds, s)
               : coef_pass_dispatch<float>(lpa, coef, dc, nact, W, d, tiles, ntiles, t, T, beta1,
                                           beta2, lr_rel, eps_rel, lds, s);
+}
+
+hipError_t launch_shared_gram(int bf16, const Inst* d, int nsig, int n, float* Gf, float* dg,
+                              hipStream_t s) {
+  if (nsig <= 0) return nothing_to_launch(s);
+  const int nt = (n + kGemmTile - 1) / kGemmTile;
+  const dim3 g0(nt, nt), g1(nt, (nsig + kGemmTile - 1) / kGemmTile);
+  if (bf16) {
+    CLOMP_LAUNCH((shared_gemm_kernel<uint16_t, 0>), g0, dim3(256), 0, s, d, nsig, Gf);
+    CLOMP_LAUNCH((shared_gemm_kernel<uint16_t, 1>), g1, dim3(256), 0, s, d, nsig, Gf);
+  } else {
+    CLOMP_LAUNCH((shared_gemm_kernel<float, 0>), g0, dim3(256), 0, s, d, nsig, Gf);
+    CLOMP_LAUNCH((shared_gemm_kernel<float, 1>), g1, dim3(256), 0, s, d, nsig, Gf);
+  }
+  CLOMP_LAUNCH(shared_diag_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, d, Gf, dg);
+  return hipGetLastError();
 }
 
 hipError_t launch_cscan(const Inst* d, const ScanTile* tiles, int ntiles, int t, hipStream_t s) {

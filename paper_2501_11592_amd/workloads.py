@@ -156,6 +156,29 @@ def image_batch(sr=0.3, n=256, a=256, k=32, lda=None):
     return SharedBatch(At, m, Y, k, sup, S)
 
 
+IMAGE4K_SR = (0.1, 0.3, 0.5)
+
+
+def image4k_batch(sr=0.3, n=2160, a=3840, k=108, lda=None):
+    """A 4K-scale image (3840 x 2160) as a columns batch: 3840 signals of n =
+    2160 rows sharing one Gaussian A with m = round(sr * n) (216 / 648 / 1080),
+    each column k-sparse with power-law coefficients |c_i| ~ i^-1.5 (k = 5% of
+    n, the low sparse rate of 4K images); Y = A S."""
+    m = int(round(sr * n))
+    g = rng_for(6, IMAGE4K_SR.index(sr))
+    At = (g.standard_normal((n, m)) / math.sqrt(m)).astype(np.float32)
+    lda = lda or pad_lda(m)
+    At = _pack(At, lda, np.float32)
+    A64 = At[:, :m].T.astype(np.float64)
+    sup, S = [], np.zeros((a, n))
+    for c in range(a):
+        sp, s = power_law_coeffs(g, n, k)
+        sup.append(sp)
+        S[c] = s
+    Y = (S @ A64.T).astype(np.float32)
+    return SharedBatch(At, m, Y, k, sup, S)
+
+
 # ---------------------------------------------------------------- workload 4
 @dataclass
 class UnevenSpec:
