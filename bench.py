@@ -53,6 +53,8 @@ def parse():
                     help="skip the paper-mode CLOMP leg (T_h = 0.7, 200 iterations)")
     ap.add_argument("--flow", default="auto", choices=["auto", "resid", "corr"],
                     help="schedule: library default, residual, or correlation update")
+    ap.add_argument("--no-shared-gram", action="store_true",
+                    help="keep per-signal passes over a shared A (no full Gram matrix)")
     ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 5 device copies of 1 GiB (reference for HBM counters)")
@@ -244,6 +246,7 @@ def main():
     torch.cuda.synchronize()
     stream = torch.cuda.Stream(torch.device("cuda", 0))
     flow_flag = {"auto": 0, "resid": C.FLAG_RESIDUAL_FLOW, "corr": C.FLAG_CORR_FLOW}[args.flow]
+    flow_flag |= C.FLAG_NO_SHARED_GRAM if args.no_shared_gram else 0
     flags = (0 if args.no_graph else C.FLAG_GRAPH) | flow_flag
     methods = ("clomp", "omp") + (() if args.no_iht else ("iht",)) + (
         () if args.no_paper else ("clomp_paper",))

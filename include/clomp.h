@@ -307,6 +307,11 @@ clomp_status_t clomp_profile_reset(clomp_handle_t h);
  *                  only while the teams of all active signals fit on the
  *                  device at once); smaller supports use one workgroup
  *                  (default 256; a value >= k disables teams)
+ *   rscan_min_t    shared-dictionary batches: from the iteration whose
+ *                  support has this many atoms on, the correlation scan is
+ *                  one contraction C = A^T R over the batch's residuals
+ *                  (argmax fused); before it, c = c0 - Gf[:, S] s per signal
+ *                  (default 16; 1 always contracts, a value >= k never)
  * clomp_get_tuning returns the values in use for the last solve.
  * Errors: INVALID_ARGUMENT (NULL, negative or > 65536 values).
  */
@@ -314,7 +319,8 @@ typedef struct {
   int32_t scan_tile_kb;
   int32_t pass_tile_kb;
   int32_t team_min_rows;
-  int32_t reserved[5];
+  int32_t rscan_min_t;
+  int32_t reserved[4];
 } clomp_tuning_t;
 
 clomp_status_t clomp_set_tuning(clomp_handle_t h, const clomp_tuning_t* t /*host*/);

@@ -79,6 +79,9 @@ hipError_t launch_coef_pass(int bf16, int lpa, int omp, const Inst* dc, int nact
 // every signal, dg = diag(Gf) (+ the prior); d[0..nsig) share A, n, m.
 hipError_t launch_shared_gram(int bf16, const Inst* d, int nsig, int n, float* Gf, float* dg,
                               hipStream_t s);
+// shared dictionary: the correlation scan of iteration t of signals
+// d[0..nsig) as C = A^T R over their residuals (argmax keys, slot t & 1).
+hipError_t launch_shared_rscan(int bf16, const Inst* d, int nsig, int n, int t, hipStream_t s);
 hipError_t launch_cscan(const Inst* d, const ScanTile* tiles, int ntiles, int t, hipStream_t s);
 hipError_t set_max_lds_pass(size_t bytes);
 

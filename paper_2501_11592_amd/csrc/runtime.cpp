@@ -144,6 +144,7 @@ struct clomp_ctx {
   int scan_tile_kb = kScanTargetKB;
   int pass_tile_kb = kPassTargetKB;
   int team_min_rows = 256;            // larger supports use coefficient teams
+  int rscan_min_t = 16;               // shared dictionary: A^T R scan from this support size
   int last_scan_kb = kScanTargetKB, last_pass_kb = kPassTargetKB;   // of the last solve
   std::map<std::string, int> tuned;   // autotuned tile size per size class
   PlanCache pcache;
@@ -340,7 +341,7 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     ws = align_up(ws + sizeof(float) * l, kAlign);
   }
   snprintf(sigbuf, sizeof sigbuf, "d%d;m%d;T%d;s%d;p%d;w%d;", bf16, prm.method,
-           prm.inner_steps, scan_kb, pass_kb, h->team_min_rows);
+           prm.inner_steps, scan_kb, pass_kb, h->team_min_rows * 65536 + h->rscan_min_t);
   P.sig += sigbuf;
   for (int s = 0; s < count; ++s) {
     const int i = order[s];
@@ -656,6 +657,7 @@ clomp_status_t launch_hflow(clomp_ctx* h, const Plan& P, int bf16, hipStream_t s
   const Inst* d_insts = reinterpret_cast<const Inst*>(tb + P.off_insts);
   const ScanTile* d_htiles = reinterpret_cast<const ScanTile*>(tb + P.off_htiles);
   const ScanTile* d_ctiles = reinterpret_cast<const ScanTile*>(tb + P.off_ctiles);
+  const RowTile* d_rows = reinterpret_cast<const RowTile*>(tb + P.off_rows);
   const double esz = bf16 ? 2.0 : 4.0;
   auto nactive = [&](const Class& c, int t) {
     int q = 0;
@@ -726,7 +728,20 @@ clomp_status_t launch_hflow(clomp_ctx* h, const Plan& P, int bf16, hipStream_t s
           for (int q = c.i0; q < c.i0 + nnext; ++q)
             h->pass_bytes += (double)P.insts[q].m * P.insts[q].n * esz + 4.0 * P.insts[q].n;
       }
-      if (nnext > 0) {
+      if (nnext > 0 && P.gflow && t + 1 >= h->rscan_min_t) {
+        // shared dictionary: residuals of the active signals, then the scan
+        // of all of them as one contraction C = A^T R with the argmax fused
+        {
+          PhaseScope ps(h, PH_RESID, st);
+          HIP_TRY(launch_resid(bf16, d_insts, d_rows + c.row_off, c.row_prefix[nnext], t, st),
+                  "resid");
+        }
+        PhaseScope ps(h, PH_SCAN, st);
+        HIP_TRY(launch_shared_rscan(bf16, d_insts + c.i0, nnext, P.insts[c.i0].n, t + 1, st),
+                "rscan");
+        if (h->profiling)
+          h->scan_bytes += 4.0 * P.insts[c.i0].m * P.insts[c.i0].n;
+      } else if (nnext > 0) {
         PhaseScope ps(h, PH_SCAN, st);
         HIP_TRY(launch_cscan(d_insts, d_ctiles + c.ctile_off, c.ctile_prefix[nnext], t + 1, st),
                 "cscan");
@@ -1377,13 +1392,14 @@ clomp_status_t clomp_grad(clomp_handle_t h, int32_t n, int32_t m, int64_t lda, i
 clomp_status_t clomp_set_tuning(clomp_handle_t h, const clomp_tuning_t* t) {
   if (!h || !t) return CLOMP_INVALID_ARGUMENT;
   if (t->scan_tile_kb < 0 || t->scan_tile_kb > 65536 || t->pass_tile_kb < 0 ||
-      t->pass_tile_kb > 65536 || t->team_min_rows < 0)
+      t->pass_tile_kb > 65536 || t->team_min_rows < 0 || t->rscan_min_t < 0)
     return fail(h, CLOMP_INVALID_ARGUMENT,
-                "tile sizes must lie in [0, 65536] KB and team_min_rows must be >= 0");
+                "tile sizes must lie in [0, 65536] KB; team_min_rows and rscan_min_t >= 0");
   if (t->scan_tile_kb) h->scan_tile_kb = h->last_scan_kb = t->scan_tile_kb;
   if (t->pass_tile_kb) h->pass_tile_kb = h->last_pass_kb = t->pass_tile_kb;
   h->tuned.clear();
   if (t->team_min_rows) h->team_min_rows = t->team_min_rows;
+  if (t->rscan_min_t) h->rscan_min_t = t->rscan_min_t;
   h->pcache.valid = false;
   drop_graphs(h);
   return CLOMP_OK;
@@ -1395,6 +1411,7 @@ clomp_status_t clomp_get_tuning(clomp_handle_t h, clomp_tuning_t* t) {
   t->scan_tile_kb = h->last_scan_kb;
   t->pass_tile_kb = h->last_pass_kb;
   t->team_min_rows = h->team_min_rows;
+  t->rscan_min_t = h->rscan_min_t;
   return CLOMP_OK;
 }
 

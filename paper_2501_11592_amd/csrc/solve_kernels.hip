@@ -1586,6 +1586,130 @@ __global__ __launch_bounds__(NT) void paper_select_kernel(const Inst* __restrict
   }
 }
 
+// ============================================================ shared dictionary
+// (every iterated signal of the batch has the same A)
+// The batch computes the full Gram matrix Gf = A^T A and c0 = A^T y of every
+// signal once; an iteration then needs no pass over A: column S_l of Gf is
+// H's column l, and the new Gram row of the coefficient update is a lookup.
+// C[i, q] = sum_k A[i][k] B_q[k] over 64 x 64 output tiles (4 x 4 per thread),
+// k in chunks of 32 staged in LDS.  MODE 0: B_q = atom q, C = Gf (ld ldh);
+// MODE 1: B_q = y of signal q (the workspace copy), C[:, q] = c0 of signal q;
+// MODE 2: B_q = the residual r of signal q, and instead of C each signal gets
+// the argmax key of its column over unselected atoms (key slot `t & 1`): the
+// correlation scan of a whole batch as one contraction C = A^T R.
+constexpr int kGemmTile = 64, kGemmK = 32;
+
+template <typename TA, int MODE>
+__global__ __launch_bounds__(256) void shared_gemm_kernel(const Inst* __restrict__ insts, int nsig,
+                                                          float* __restrict__ Gf, int t) {
+  __shared__ __align__(16) float As[kGemmK][kGemmTile + 4];
+  __shared__ __align__(16) float Bs[kGemmK][kGemmTile + 4];
+  __shared__ unsigned long long kbest[4][kGemmTile];
+  const Inst& I0 = insts[0];
+  const TA* A = reinterpret_cast<const TA*>(I0.A);
+  const long long lda = I0.lda, ldh = I0.ldh;
+  const int n = I0.n, m = I0.m;
+  const int ncols = (MODE == 0) ? n : nsig;
+  const int i0 = blockIdx.x * kGemmTile, q0 = blockIdx.y * kGemmTile;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  float acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.f;
+  for (int k0 = 0; k0 < m; k0 += kGemmK) {
+    // consecutive threads walk k along one row (contiguous in memory)
+    for (int e = threadIdx.x; e < kGemmTile * kGemmK; e += 256) {
+      const int r = e / kGemmK, kk = e - r * kGemmK;
+      const int k = k0 + kk;
+      const int i = i0 + r, q = q0 + r;
+      As[kk][r] = (i < n && k < m) ? Vec<TA>::one(A + (long long)i * lda + k) : 0.f;
+      float bv = 0.f;
+      if (q < ncols && k < m) {
+        if (MODE == 0) {
+          bv = Vec<TA>::one(A + (long long)q * lda + k);
+        } else {
+          const Inst& Iq = insts[q];
+          bv = Iq.r[(MODE == 1 ? Iq.m_pad : 0) + k];
+        }
+      }
+      Bs[kk][r] = bv;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < kGemmK; ++kk) {
+      const float4 a = *reinterpret_cast<const float4*>(&As[kk][4 * ty]);
+      const float4 b = *reinterpret_cast<const float4*>(&Bs[kk][4 * tx]);
+      const float av[4] = {a.x, a.y, a.z, a.w};
+      const float bw[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fmaf(av[u], bw[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+  if (MODE == 2) {
+    // per signal column: the best unselected atom of this thread's four, then
+    // of the wave's four row groups (lanes tx, tx+16, tx+32, tx+48), then of
+    // the four waves; one atomicMax per signal and tile
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int q = q0 + 4 * tx + v;
+      unsigned long long best = 0ull;
+      if (q < ncols) {
+        const unsigned* bm = insts[q].bitmap;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = i0 + 4 * ty + u;
+          if (i < n && !((bm[i >> 5] >> (i & 31)) & 1u)) {
+            const unsigned long long kk = pack_key(acc[u][v], i);
+            best = kk > best ? kk : best;
+          }
+        }
+      }
+      for (int o = 16; o < 64; o <<= 1) {
+        const unsigned long long other = __shfl_xor(best, o, 64);
+        best = other > best ? other : best;
+      }
+      if (lane < 16) kbest[w][4 * lane + v] = best;
+    }
+    __syncthreads();
+    if (threadIdx.x < kGemmTile) {
+      const int q = q0 + threadIdx.x;
+      unsigned long long best = kbest[0][threadIdx.x];
+#pragma unroll
+      for (int ww = 1; ww < 4; ++ww) best = kbest[ww][threadIdx.x] > best ? kbest[ww][threadIdx.x] : best;
+      if (q < ncols && best) atomicMax(&insts[q].key[t & 1], best);
+    }
+    return;
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = i0 + 4 * ty + u;
+    if (i >= n) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int q = q0 + 4 * tx + v;
+      if (q >= ncols) continue;
+      if (MODE == 0)
+        Gf[i + (long long)q * ldh] = acc[u][v];
+      else
+        insts[q].c0[i] = acc[u][v];
+    }
+  }
+}
+
+// The shared Gram diagonal (prior included) for the coefficient updates.
+__global__ __launch_bounds__(kBlock) void shared_diag_kernel(const Inst* __restrict__ insts,
+                                                             const float* __restrict__ Gf,
+                                                             float* __restrict__ dg) {
+  const Inst& I0 = insts[0];
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j < I0.n) dg[j] = Gf[j + (long long)j * I0.ldh] + tv_diag(I0, j);
+}
+
 // ============================================================ fused small-signal loop
 // One workgroup runs the whole greedy loop of one signal whose dictionary fits
 // in LDS: A is converted to FP32 once (row j of the LDS image is atom j, with
@@ -2049,89 +2173,6 @@ __device__ inline void team_retire(const Inst& I, int w) {
   if (w == 0 && threadIdx.x == 0 &&
       (__hip_atomic_load(I.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ST_WATCHDOG))
     I.st->done = 1;
-}
-
-// ---- shared dictionary (every iterated signal of the batch has the same A)
-// The batch computes the full Gram matrix Gf = A^T A and c0 = A^T y of every
-// signal once; an iteration then needs no pass over A: column S_l of Gf is
-// H's column l, and the new Gram row of the coefficient update is a lookup.
-// C[i, q] = sum_k A[i][k] B_q[k] over 64 x 64 output tiles (4 x 4 per thread),
-// k in chunks of 32 staged in LDS.  MODE 0: B_q = atom q, C = Gf (ld ldh);
-// MODE 1: B_q = y of signal q (the workspace copy), C[:, q] = c0 of signal q.
-constexpr int kGemmTile = 64, kGemmK = 32;
-
-template <typename TA, int MODE>
-__global__ __launch_bounds__(256) void shared_gemm_kernel(const Inst* __restrict__ insts, int nsig,
-                                                          float* __restrict__ Gf) {
-  __shared__ __align__(16) float As[kGemmK][kGemmTile + 4];
-  __shared__ __align__(16) float Bs[kGemmK][kGemmTile + 4];
-  const Inst& I0 = insts[0];
-  const TA* A = reinterpret_cast<const TA*>(I0.A);
-  const long long lda = I0.lda, ldh = I0.ldh;
-  const int n = I0.n, m = I0.m;
-  const int ncols = (MODE == 0) ? n : nsig;
-  const int i0 = blockIdx.x * kGemmTile, q0 = blockIdx.y * kGemmTile;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  float acc[4][4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.f;
-  for (int k0 = 0; k0 < m; k0 += kGemmK) {
-    // consecutive threads walk k along one row (contiguous in memory)
-    for (int e = threadIdx.x; e < kGemmTile * kGemmK; e += 256) {
-      const int r = e / kGemmK, kk = e - r * kGemmK;
-      const int k = k0 + kk;
-      const int i = i0 + r, q = q0 + r;
-      As[kk][r] = (i < n && k < m) ? Vec<TA>::one(A + (long long)i * lda + k) : 0.f;
-      float bv = 0.f;
-      if (q < ncols && k < m) {
-        if (MODE == 0) {
-          bv = Vec<TA>::one(A + (long long)q * lda + k);
-        } else {
-          const Inst& Iq = insts[q];
-          bv = Iq.r[Iq.m_pad + k];
-        }
-      }
-      Bs[kk][r] = bv;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int kk = 0; kk < kGemmK; ++kk) {
-      const float4 a = *reinterpret_cast<const float4*>(&As[kk][4 * ty]);
-      const float4 b = *reinterpret_cast<const float4*>(&Bs[kk][4 * tx]);
-      const float av[4] = {a.x, a.y, a.z, a.w};
-      const float bw[4] = {b.x, b.y, b.z, b.w};
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fmaf(av[u], bw[v], acc[u][v]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int i = i0 + 4 * ty + u;
-    if (i >= n) continue;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int q = q0 + 4 * tx + v;
-      if (q >= ncols) continue;
-      if (MODE == 0)
-        Gf[i + (long long)q * ldh] = acc[u][v];
-      else
-        insts[q].c0[i] = acc[u][v];
-    }
-  }
-}
-
-// The shared Gram diagonal (prior included) for the coefficient updates.
-__global__ __launch_bounds__(kBlock) void shared_diag_kernel(const Inst* __restrict__ insts,
-                                                             const float* __restrict__ Gf,
-                                                             float* __restrict__ dg) {
-  const Inst& I0 = insts[0];
-  const int j = blockIdx.x * kBlock + threadIdx.x;
-  if (j < I0.n) dg[j] = Gf[j + (long long)j * I0.ldh] + tv_diag(I0, j);
 }
 
 
@@ -2948,13 +2989,23 @@ hipError_t launch_shared_gram(int bf16, const Inst* d, int nsig, int n, float* G
   const int nt = (n + kGemmTile - 1) / kGemmTile;
   const dim3 g0(nt, nt), g1(nt, (nsig + kGemmTile - 1) / kGemmTile);
   if (bf16) {
-    CLOMP_LAUNCH((shared_gemm_kernel<uint16_t, 0>), g0, dim3(256), 0, s, d, nsig, Gf);
-    CLOMP_LAUNCH((shared_gemm_kernel<uint16_t, 1>), g1, dim3(256), 0, s, d, nsig, Gf);
+    CLOMP_LAUNCH((shared_gemm_kernel<uint16_t, 0>), g0, dim3(256), 0, s, d, nsig, Gf, 0);
+    CLOMP_LAUNCH((shared_gemm_kernel<uint16_t, 1>), g1, dim3(256), 0, s, d, nsig, Gf, 0);
   } else {
-    CLOMP_LAUNCH((shared_gemm_kernel<float, 0>), g0, dim3(256), 0, s, d, nsig, Gf);
-    CLOMP_LAUNCH((shared_gemm_kernel<float, 1>), g1, dim3(256), 0, s, d, nsig, Gf);
+    CLOMP_LAUNCH((shared_gemm_kernel<float, 0>), g0, dim3(256), 0, s, d, nsig, Gf, 0);
+    CLOMP_LAUNCH((shared_gemm_kernel<float, 1>), g1, dim3(256), 0, s, d, nsig, Gf, 0);
   }
   CLOMP_LAUNCH(shared_diag_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, d, Gf, dg);
+  return hipGetLastError();
+}
+
+hipError_t launch_shared_rscan(int bf16, const Inst* d, int nsig, int n, int t, hipStream_t s) {
+  if (nsig <= 0) return nothing_to_launch(s);
+  const dim3 g((n + kGemmTile - 1) / kGemmTile, (nsig + kGemmTile - 1) / kGemmTile);
+  if (bf16)
+    CLOMP_LAUNCH((shared_gemm_kernel<uint16_t, 2>), g, dim3(256), 0, s, d, nsig, nullptr, t);
+  else
+    CLOMP_LAUNCH((shared_gemm_kernel<float, 2>), g, dim3(256), 0, s, d, nsig, nullptr, t);
   return hipGetLastError();
 }
 

@@ -22,22 +22,30 @@ f32 = lambda v: float(np.float32(v))
 ITER = C.FLAG_NO_FUSED_SMALL   # keep the image columns out of the fused loop
 
 
-def _solve(method, b, flags, **kw):
+def _solve(method, b, flags, rscan_min_t=0, **kw):
     sol = C.Solver(0, method=method, flags=flags, **kw)
+    if rscan_min_t:
+        sol.set_tuning(rscan_min_t=rscan_min_t)
     out = sol.solve_shared(dev(b.At), b.m, dev(b.Y), b.k)
     torch.cuda.synchronize()
     sol.close()
     return out
 
 
+# the correlation scan: always C = A^T R over the batch's residuals, or
+# always c0 - Gf[:, S] s per signal
+SCANS = {"atr": 1, "gram": 1 << 20}
+
+
+@pytest.mark.parametrize("scan", sorted(SCANS))
 @pytest.mark.parametrize("method", ["clomp", "omp"])
 @pytest.mark.parametrize("sr", [0.3, 0.5])
-def test_shared_gram_image_batch(method, sr):
+def test_shared_gram_image_batch(method, sr, scan):
     """256 columns sharing A (m = 77 / 128), iterated: the shared schedule
-    against the oracle, and the same supports as the per-signal schedule on
-    the columns both match the oracle."""
+    (either scan) against the oracle, and the same supports as the per-signal
+    schedule on the columns both match the oracle."""
     b = W.image_batch(sr)
-    out = _solve(method, b, ITER)
+    out = _solve(method, b, ITER, rscan_min_t=SCANS[scan])
     ref_sched = _solve(method, b, ITER | C.FLAG_NO_SHARED_GRAM)
     kinds = []
     for c in range(0, 256, 8):
@@ -47,7 +55,7 @@ def test_shared_gram_image_batch(method, sr):
         kinds.append(kind)
         if kind == "identical":
             assert out.support[c].tolist() == ref_sched.support[c].tolist()
-    print(f"{method} sr={sr}: identical {kinds.count('identical')}/{len(kinds)}")
+    print(f"{method} sr={sr} {scan}: identical {kinds.count('identical')}/{len(kinds)}")
     assert kinds.count("identical") >= len(kinds) // 2
     assert (out.status.cpu().numpy() == 0).all()
 
