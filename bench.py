@@ -211,6 +211,21 @@ def roofline(p, items=None, method="clomp"):
                 "frac": ach / VALU_PEAK_TFLOPS, "traffic": None, "avg_launch_us": 1e3 * k_ms,
                 "flops_per_launch": fl, "hbm_bytes_per_launch": p["fused_bytes"] / nl,
                 "launches": nl}
+    if p["launches"]["pass"] > 0 and p["ms"]["pass"] >= p["ms"]["scan"] and p["pass_bytes"] == 0:
+        # shared dictionary: the launches carry coefficient workgroups only
+        nl, ms = p["launches"]["pass"], p["ms"]["pass"]
+        fl = 0.0
+        for it in items:
+            ke = min(int(it["k"]), int(it["m"]), int(it["At"].shape[0]))
+            for t in range(ke):
+                fl += (32 * (2.0 * (t + 1) ** 2 + 10.0 * (t + 1)) if method == "clomp"
+                       else 6.0 * t * t)
+        k_ms = ms / nl
+        ach = fl / nl / (k_ms * 1e-3) / 1e12
+        return {"kernel": "coef_pass_kernel (coefficient workgroups only: shared dictionary)",
+                "bound": "alu", "achieved": ach, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / VALU_PEAK_TFLOPS, "traffic": None, "avg_launch_us": 1e3 * k_ms,
+                "flops_per_launch": fl / nl, "launches": nl}
     if p["launches"]["pass"] > 0 and p["ms"]["pass"] >= p["ms"]["scan"]:
         name = "coef_pass_kernel (Adam/OMP block + pass h = A^T a_j over A)"
         nl, ms, byt = p["launches"]["pass"], p["ms"]["pass"], p["pass_bytes"]
