@@ -79,6 +79,10 @@ hipError_t launch_coef_pass(int bf16, int lpa, int omp, const Inst* dc, int nact
 // every signal, dg = diag(Gf) (+ the prior); d[0..nsig) share A, n, m.
 hipError_t launch_shared_gram(int bf16, const Inst* d, int nsig, int n, float* Gf, float* dg,
                               hipStream_t s);
+// shared dictionary, CLOMP, t+1 <= 256: selection record and Adam of
+// iteration t with ceil((t+1)/16) waves per signal.
+hipError_t launch_coef_reg(const Inst* dc, int nact, int t, int T, float beta1, float beta2,
+                            float lr_rel, float eps_rel, hipStream_t s);
 // shared dictionary: the correlation scan of iteration t of signals
 // d[0..nsig) as C = A^T R over their residuals (argmax keys, slot t & 1).
 hipError_t launch_shared_rscan(int bf16, const Inst* d, int nsig, int n, int t, hipStream_t s);

@@ -718,15 +718,23 @@ clomp_status_t launch_hflow(clomp_ctx* h, const Plan& P, int bf16, hipStream_t s
         if (!omp && t1 > 256 && t1 <= 1024) lds = std::max(lds, (size_t)2048 * sizeof(float));
         if (W > 1) lds = std::max(lds, (t1 + 4 + 32) * sizeof(float));
         PhaseScope ps(h, PH_PASS, st);
-        // a shared dictionary has every column of H already (no pass tiles)
-        HIP_TRY(launch_coef_pass(bf16, c.lpa, omp, d_insts + c.i0, nact, W, d_insts,
-                                 d_htiles + c.htile_off, P.gflow ? 0 : c.htile_prefix[nnext], t,
-                                 prm.inner_steps, prm.beta1, prm.beta2, prm.lr_rel, prm.eps_rel,
-                                 lds, st),
-                "coef_pass");
-        if (h->profiling && !P.gflow)
-          for (int q = c.i0; q < c.i0 + nnext; ++q)
-            h->pass_bytes += (double)P.insts[q].m * P.insts[q].n * esz + 4.0 * P.insts[q].n;
+        if (P.gflow && !omp && W == 1 && t1 <= 256) {
+          // no pass shares the launch: a workgroup sized to the support
+          HIP_TRY(launch_coef_reg(d_insts + c.i0, nact, t, prm.inner_steps, prm.beta1, prm.beta2,
+                                  prm.lr_rel, prm.eps_rel, st),
+                  "coef_reg");
+        } else {
+          // (a shared dictionary has every column of H already: no pass tiles)
+          HIP_TRY(launch_coef_pass(bf16, c.lpa, omp, d_insts + c.i0, nact, W, d_insts,
+                                   d_htiles + c.htile_off, P.gflow ? 0 : c.htile_prefix[nnext], t,
+                                   prm.inner_steps, prm.beta1, prm.beta2, prm.lr_rel,
+                                   prm.eps_rel, lds, st),
+                  "coef_pass");
+          if (h->profiling && !P.gflow)
+            for (int q = c.i0; q < c.i0 + nnext; ++q)
+              h->pass_bytes +=
+                  (double)P.insts[q].m * P.insts[q].n * esz + 4.0 * P.insts[q].n;
+        }
       }
       if (nnext > 0 && P.gflow && t + 1 >= h->rscan_min_t) {
         // shared dictionary: residuals of the active signals, then the scan

@@ -625,6 +625,10 @@ __global__ __launch_bounds__(kBlock) void adam_kernel(const Inst* __restrict__ i
 // row's 16 partials are then added in a fixed order.
 constexpr int kRegRows = 256;
 
+// RPL rows per lane (1, 2 or 4; rows RPL*l .. RPL*l+RPL-1 of lane l): a
+// support of t+1 <= 64*RPL atoms; fewer rows per lane keep the tile of G
+// within the registers of a full-occupancy wave.
+template <int RPL = 4>
 __device__ void adam_reg_body(const Inst& I, int t, int T, float beta1, float beta2,
                               float4 (*part)[16][64], int nw, bool clear_key = true) {
   if (I.st->done) {
@@ -637,18 +641,25 @@ __device__ void adam_reg_body(const Inst& I, int t, int T, float beta1, float be
   const int c0 = 16 * w;
   const bool active = c0 < t1;          // wave-uniform
   const long long ldg = I.ldg;
-  float Gr[4][16];
+  float Gr[RPL][16];
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
-    float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (active && 4 * lane < t1 && c0 + c < t1)
-      q = *reinterpret_cast<const float4*>(I.G + (long long)(c0 + c) * ldg + 4 * lane);
-    // rows beyond t1 inside the last float4 hold stale values: zero them
-    const int rb = 4 * lane;
-    Gr[0][c] = (rb + 0 < t1) ? q.x : 0.f;
-    Gr[1][c] = (rb + 1 < t1) ? q.y : 0.f;
-    Gr[2][c] = (rb + 2 < t1) ? q.z : 0.f;
-    Gr[3][c] = (rb + 3 < t1) ? q.w : 0.f;
+    const int rb = RPL * lane;
+    // rows at or beyond t1 hold stale values: zero them
+    if constexpr (RPL == 4) {
+      float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (active && rb < t1 && c0 + c < t1)
+        q = *reinterpret_cast<const float4*>(I.G + (long long)(c0 + c) * ldg + rb);
+      Gr[0][c] = (rb + 0 < t1) ? q.x : 0.f;
+      Gr[1][c] = (rb + 1 < t1) ? q.y : 0.f;
+      Gr[2][c] = (rb + 2 < t1) ? q.z : 0.f;
+      Gr[3][c] = (rb + 3 < t1) ? q.w : 0.f;
+    } else {
+      const float* gc = I.G + (long long)(c0 + c) * ldg + rb;
+      const bool colok = active && c0 + c < t1;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) Gr[i][c] = (colok && rb + i < t1) ? gc[i] : 0.f;
+    }
   }
   // Adam state of row R = 16w + lane (lanes 0..15)
   const int R = c0 + lane;
@@ -679,9 +690,9 @@ __device__ void adam_reg_body(const Inst& I, int t, int T, float beta1, float be
     const float ibc1 = __builtin_amdgcn_rcpf((float)(1.0 - b1p));
     const float ibc2 = __builtin_amdgcn_rcpf((float)(1.0 - b2p));
     // per-row sums over the wave's 16 columns, four interleaved chains each
-    float acc[4][4];
+    float acc[RPL][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < RPL; ++i)
 #pragma unroll
       for (int u = 0; u < 4; ++u) acc[i][u] = 0.f;
     if (active) {
@@ -690,13 +701,20 @@ __device__ void adam_reg_body(const Inst& I, int t, int T, float beta1, float be
       for (int c = 0; c < 16; ++c) {
         const float sc = __int_as_float(__builtin_amdgcn_readlane(sbits, c));
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i][c & 3] = fmaf(Gr[i][c], sc, acc[i][c & 3]);
+        for (int i = 0; i < RPL; ++i) acc[i][c & 3] = fmaf(Gr[i][c], sc, acc[i][c & 3]);
       }
     }
-    float rs[4];
+    // the wave's partial of row r sits at float r of its slot
+    if constexpr (RPL == 4) {
+      float rs[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) rs[i] = (acc[i][0] + acc[i][1]) + (acc[i][2] + acc[i][3]);
-    part[buf][w][lane] = make_float4(rs[0], rs[1], rs[2], rs[3]);
+      for (int i = 0; i < 4; ++i) rs[i] = (acc[i][0] + acc[i][1]) + (acc[i][2] + acc[i][3]);
+      part[buf][w][lane] = make_float4(rs[0], rs[1], rs[2], rs[3]);
+    } else {
+      float* pw = reinterpret_cast<float*>(&part[buf][w][0]) + RPL * lane;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) pw[i] = (acc[i][0] + acc[i][1]) + (acc[i][2] + acc[i][3]);
+    }
     __syncthreads();
     if (own) {
       // partials of row R: element (R & 3) of part[buf][w'][R >> 2], w' = 0..15,
@@ -2176,6 +2194,46 @@ __device__ inline void team_retire(const Inst& I, int w) {
 }
 
 
+// Selection record of iteration t (atom j of `key`, all threads of the
+// workgroup): support, bitmap and count, the new Gram row and column from H
+// and the diagonal, b_t = c0[j], the step size and eps, and the next scan's
+// key slot cleared.  NT: threads of the workgroup (0: read blockDim).
+template <int NT>
+__device__ inline void record_selection(const Inst& I, unsigned long long key, int t,
+                                        float lr_rel, float eps_rel) {
+  const int j = key_index(key);
+  const int stride = NT > 0 ? NT : (int)blockDim.x;
+  // two loops, so that the per-signal H path issues no support load
+  if (I.Gf) {
+    for (int l = threadIdx.x; l < t; l += stride) {
+      const float g = I.Gf[j + (long long)I.support[l] * I.ldh];
+      I.G[l + (long long)t * I.ldg] = g;
+      I.G[t + (long long)l * I.ldg] = g;
+    }
+  } else {
+    for (int l = threadIdx.x; l < t; l += stride) {
+      const float g = I.H[j + (long long)l * I.ldh];
+      I.G[l + (long long)t * I.ldg] = g;
+      I.G[t + (long long)l * I.ldg] = g;
+    }
+  }
+  if (threadIdx.x == 0) {
+    I.G[t + (long long)t * I.ldg] = I.dg[j];
+    I.b[t] = I.c0[j];
+    I.support[t] = j;
+    I.bitmap[j >> 5] |= (1u << (j & 31));
+    *I.nsel = t + 1;
+    const float cj = key_value(key);
+    if (!(cj <= 3.402823466e38f)) atomicOr(I.status, ST_NAN);
+    if (t == 0) {
+      I.st->sigma = cj;
+      I.st->eps = eps_rel * cj;
+    }
+    I.st->lr = lr_rel * cj;   // step size follows the selected correlation
+    I.key[(t + 1) & 1] = 0ull;   // slot of the next scan
+  }
+}
+
 // Entry G[r, c] of the Gram matrix during iteration t (atom j selected):
 // entries of earlier iterations from G, the new row / column from H and the
 // norms (member 0 writes them to G in this same launch).
@@ -2387,28 +2445,7 @@ __global__ __launch_bounds__(kPassThreads) void coef_pass_kernel(
       return;
     }
     constexpr bool team = COEF == COEF_ADAM_TEAM || COEF == COEF_OMP_TEAM;
-    if (member == 0) {
-      for (int l = threadIdx.x; l < t; l += kPassThreads) {
-        const float g = hcol(I, l)[j];
-        I.G[l + (long long)t * I.ldg] = g;
-        I.G[t + (long long)l * I.ldg] = g;
-      }
-      if (threadIdx.x == 0) {
-        I.G[t + (long long)t * I.ldg] = I.dg[j];
-        I.b[t] = I.c0[j];
-        I.support[t] = j;
-        I.bitmap[j >> 5] |= (1u << (j & 31));
-        *I.nsel = t + 1;
-        const float cj = key_value(key);
-        if (!(cj <= 3.402823466e38f)) atomicOr(I.status, ST_NAN);
-        if (t == 0) {
-          I.st->sigma = cj;
-          I.st->eps = eps_rel * cj;
-        }
-        I.st->lr = lr_rel * cj;   // step size follows the selected correlation
-        I.key[(t + 1) & 1] = 0ull;   // slot of the next scan
-      }
-    }
+    if (member == 0) record_selection<kPassThreads>(I, key, t, lr_rel, eps_rel);
     if (team) {
       // members take the new Gram row / column and b_t from H, dg and c0
       if (COEF == COEF_OMP_TEAM)
@@ -2527,6 +2564,32 @@ __global__ __launch_bounds__(kCscanThreads) void cscan_kernel(const Inst* __rest
     key = wave_max_u64(key);
     if (lane == 0 && key) atomicMax(&I.key[t & 1], key);
   }
+}
+
+// Coefficient update of iteration t when no pass shares the launch (shared
+// dictionary, CLOMP, t+1 <= 256): one workgroup of ceil((t+1)/16) waves per
+// signal, so small supports do not hold a 16-wave workgroup each and several
+// signals share a CU; RPL rows of G per lane for supports up to 64*RPL.  The
+// selection record, then the register-tile Adam.
+template <int RPL>
+__global__ __launch_bounds__(1024) void coef_reg_kernel(const Inst* __restrict__ insts_c, int t,
+                                                        int T, float beta1, float beta2,
+                                                        float lr_rel, float eps_rel) {
+  __shared__ float4 part[2][16][64];
+  const Inst& I = insts_c[blockIdx.x];
+  if (I.st->done) return;
+  const unsigned long long key = I.key[t & 1];
+  const int j = key_index(key);
+  if (key == 0ull || j < 0 || j >= I.n) {
+    if (threadIdx.x == 0) {
+      I.st->done = 1;
+      atomicOr(I.status, ST_WATCHDOG);
+    }
+    return;
+  }
+  record_selection<0>(I, key, t, lr_rel, eps_rel);
+  __syncthreads();
+  adam_reg_body<RPL>(I, t, T, beta1, beta2, part, blockDim.x >> 6, false);
 }
 
 // ============================================================ launchers
@@ -2996,6 +3059,21 @@ hipError_t launch_shared_gram(int bf16, const Inst* d, int nsig, int n, float* G
     CLOMP_LAUNCH((shared_gemm_kernel<float, 1>), g1, dim3(256), 0, s, d, nsig, Gf, 0);
   }
   CLOMP_LAUNCH(shared_diag_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, d, Gf, dg);
+  return hipGetLastError();
+}
+
+hipError_t launch_coef_reg(const Inst* dc, int nact, int t, int T, float beta1, float beta2,
+                            float lr_rel, float eps_rel, hipStream_t s) {
+  if (nact <= 0) return nothing_to_launch(s);
+  if (t + 1 > kRegRows) return hipErrorInvalidValue;
+  const int waves = (t + 1 + 15) / 16;
+  const dim3 g(nact), b(64 * waves);
+  if (t + 1 <= 64)
+    CLOMP_LAUNCH(coef_reg_kernel<1>, g, b, 0, s, dc, t, T, beta1, beta2, lr_rel, eps_rel);
+  else if (t + 1 <= 128)
+    CLOMP_LAUNCH(coef_reg_kernel<2>, g, b, 0, s, dc, t, T, beta1, beta2, lr_rel, eps_rel);
+  else
+    CLOMP_LAUNCH(coef_reg_kernel<4>, g, b, 0, s, dc, t, T, beta1, beta2, lr_rel, eps_rel);
   return hipGetLastError();
 }
 
