@@ -311,7 +311,7 @@ clomp_status_t clomp_profile_reset(clomp_handle_t h);
  *                  support has this many atoms on, the correlation scan is
  *                  one contraction C = A^T R over the batch's residuals
  *                  (argmax fused); before it, c = c0 - Gf[:, S] s per signal
- *                  (default 16; 1 always contracts, a value >= k never)
+ *                  (default 1: always contract; a value >= k never)
  * clomp_get_tuning returns the values in use for the last solve.
  * Errors: INVALID_ARGUMENT (NULL, negative or > 65536 values).
  */

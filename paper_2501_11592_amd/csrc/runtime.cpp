@@ -144,7 +144,7 @@ struct clomp_ctx {
   int scan_tile_kb = kScanTargetKB;
   int pass_tile_kb = kPassTargetKB;
   int team_min_rows = 256;            // larger supports use coefficient teams
-  int rscan_min_t = 16;               // shared dictionary: A^T R scan from this support size
+  int rscan_min_t = 1;                // shared dictionary: A^T R scan from this support size
   int last_scan_kb = kScanTargetKB, last_pass_kb = kPassTargetKB;   // of the last solve
   std::map<std::string, int> tuned;   // autotuned tile size per size class
   PlanCache pcache;
@@ -678,8 +678,12 @@ clomp_status_t launch_hflow(clomp_ctx* h, const Plan& P, int bf16, hipStream_t s
     for (const Class& c : P.classes) {
       const int nall = c.i1 - c.i0;
       PhaseScope ps(h, PH_SCAN, st);
-      HIP_TRY(launch_cscan(d_insts, d_ctiles + c.ctile_off, c.ctile_prefix[nall], 0, st),
-              "cscan");
+      // r = y at the start: the first scan is c0's argmax either way
+      if (h->rscan_min_t <= 1)
+        HIP_TRY(launch_shared_rscan(bf16, d_insts + c.i0, nall, P.insts[c.i0].n, 0, st), "rscan");
+      else
+        HIP_TRY(launch_cscan(d_insts, d_ctiles + c.ctile_off, c.ctile_prefix[nall], 0, st),
+                "cscan");
     }
   }
   // c0 = A^T y and the first argmax

@@ -1609,114 +1609,172 @@ __global__ __launch_bounds__(NT) void paper_select_kernel(const Inst* __restrict
 // The batch computes the full Gram matrix Gf = A^T A and c0 = A^T y of every
 // signal once; an iteration then needs no pass over A: column S_l of Gf is
 // H's column l, and the new Gram row of the coefficient update is a lookup.
-// C[i, q] = sum_k A[i][k] B_q[k] over 64 x 64 output tiles (4 x 4 per thread),
-// k in chunks of 32 staged in LDS.  MODE 0: B_q = atom q, C = Gf (ld ldh);
-// MODE 1: B_q = y of signal q (the workspace copy), C[:, q] = c0 of signal q;
-// MODE 2: B_q = the residual r of signal q, and instead of C each signal gets
-// the argmax key of its column over unselected atoms (key slot `t & 1`): the
-// correlation scan of a whole batch as one contraction C = A^T R.
-constexpr int kGemmTile = 64, kGemmK = 32;
+// C[i, q] = sum_k A[i][k] B_q[k] over 128 x 128 output tiles on the FP32
+// matrix cores (v_mfma_f32_16x16x4f32): four waves of 64 x 64, each a 4 x 4
+// grid of 16 x 16 blocks; k staged through LDS in chunks of 32 (row stride
+// 145 floats: the transposed stores of the eight k groups of a row fall in
+// distinct banks), the next chunk's loads in flight during the current
+// chunk's products.
+// Operand layout of the instruction: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; register v of lane l holds D[4 (l / 16) + v][l % 16].
+// MODE 0: B_q = atom q, C = Gf (ld ldh);  MODE 1: B_q = y of signal q (the
+// workspace copy), C[:, q] = c0 of signal q;  MODE 2: B_q = the residual r of
+// signal q, and instead of C each signal gets the argmax key of its column
+// over unselected atoms (key slot `t & 1`): the correlation scan of a whole
+// batch as one contraction C = A^T R.
+constexpr int kMfmaTile = 128, kMfmaK = 32, kMfmaLd = 145;
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 
 template <typename TA, int MODE>
-__global__ __launch_bounds__(256) void shared_gemm_kernel(const Inst* __restrict__ insts, int nsig,
+__global__ __launch_bounds__(256) void shared_mfma_kernel(const Inst* __restrict__ insts, int nsig,
                                                           float* __restrict__ Gf, int t) {
-  __shared__ __align__(16) float As[kGemmK][kGemmTile + 4];
-  __shared__ __align__(16) float Bs[kGemmK][kGemmTile + 4];
-  __shared__ unsigned long long kbest[4][kGemmTile];
+  // two buffers: chunk c is staged into buffer c & 1 while the loads of chunk
+  // c + 1 are in flight, one barrier per chunk
+  __shared__ __align__(16) float As[2][kMfmaK][kMfmaLd];
+  __shared__ __align__(16) float Bs[2][kMfmaK][kMfmaLd];
+  __shared__ unsigned long long kbest[2][kMfmaTile];
+  __shared__ const float* bsrc[kMfmaTile];   // MODE 1/2: the columns' y or r
   const Inst& I0 = insts[0];
   const TA* A = reinterpret_cast<const TA*>(I0.A);
   const long long lda = I0.lda, ldh = I0.ldh;
-  const int n = I0.n, m = I0.m;
+  const int n = I0.n, m = I0.m, m_pad = I0.m_pad;   // shared by every signal
   const int ncols = (MODE == 0) ? n : nsig;
-  const int i0 = blockIdx.x * kGemmTile, q0 = blockIdx.y * kGemmTile;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  float acc[4][4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.f;
-  for (int k0 = 0; k0 < m; k0 += kGemmK) {
-    // consecutive threads walk k along one row (contiguous in memory)
-    for (int e = threadIdx.x; e < kGemmTile * kGemmK; e += 256) {
-      const int r = e / kGemmK, kk = e - r * kGemmK;
-      const int k = k0 + kk;
-      const int i = i0 + r, q = q0 + r;
-      As[kk][r] = (i < n && k < m) ? Vec<TA>::one(A + (long long)i * lda + k) : 0.f;
-      float bv = 0.f;
-      if (q < ncols && k < m) {
-        if (MODE == 0) {
-          bv = Vec<TA>::one(A + (long long)q * lda + k);
-        } else {
-          const Inst& Iq = insts[q];
-          bv = Iq.r[(MODE == 1 ? Iq.m_pad : 0) + k];
-        }
-      }
-      Bs[kk][r] = bv;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int kk = 0; kk < kGemmK; ++kk) {
-      const float4 a = *reinterpret_cast<const float4*>(&As[kk][4 * ty]);
-      const float4 b = *reinterpret_cast<const float4*>(&Bs[kk][4 * tx]);
-      const float av[4] = {a.x, a.y, a.z, a.w};
-      const float bw[4] = {b.x, b.y, b.z, b.w};
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fmaf(av[u], bw[v], acc[u][v]);
-    }
-    __syncthreads();
+  const int i0 = blockIdx.x * kMfmaTile, q0 = blockIdx.y * kMfmaTile;
+  if (MODE != 0 && threadIdx.x < kMfmaTile) {
+    const int q = q0 + threadIdx.x;
+    bsrc[threadIdx.x] = (q < ncols) ? insts[q].r + (MODE == 1 ? m_pad : 0) : nullptr;
   }
-  if (MODE == 2) {
-    // per signal column: the best unselected atom of this thread's four, then
-    // of the wave's four row groups (lanes tx, tx+16, tx+32, tx+48), then of
-    // the four waves; one atomicMax per signal and tile
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w >> 1, wc = w & 1;          // the wave's 64-row / 64-column half
+  mfma_f4 acc[4][4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int q = q0 + 4 * tx + v;
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+  // four consecutive k of row r (zero at or beyond m and outside the matrix)
+  auto load_a = [&](int row, int k, float v[4]) {
+    if (row < n && k + 3 < m && sizeof(TA) == 4) {
+      const float4 q = *reinterpret_cast<const float4*>(A + (long long)row * lda + k);
+      v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        v[e] = (row < n && k + e < m) ? Vec<TA>::one(A + (long long)row * lda + k + e) : 0.f;
+    }
+  };
+  // each thread stages groups g = tid + 256 u (u < 4): row g / 8, k offset 4 (g % 8)
+  constexpr int kGroups = kMfmaTile * (kMfmaK / 4) / 256;
+  float av[kGroups][4], bv[kGroups][4];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < kGroups; ++u) {
+      const int g = threadIdx.x + 256 * u;
+      const int r = g / (kMfmaK / 4), kq = (g % (kMfmaK / 4)) * 4;
+      const int k = k0 + kq;
+      load_a(i0 + r, k, av[u]);
+      const int q = q0 + r;
+      if (MODE == 0) {
+        load_a(q, k, bv[u]);
+      } else if (q < ncols) {
+        // y and r are zero padded to m_pad (a multiple of 8)
+        const float* src = bsrc[r];
+        if (k < m_pad) {
+          const float4 v4 = *reinterpret_cast<const float4*>(src + k);
+          bv[u][0] = v4.x; bv[u][1] = v4.y; bv[u][2] = v4.z; bv[u][3] = v4.w;
+        } else {
+          bv[u][0] = bv[u][1] = bv[u][2] = bv[u][3] = 0.f;
+        }
+      } else {
+        bv[u][0] = bv[u][1] = bv[u][2] = bv[u][3] = 0.f;
+      }
+    }
+  };
+  fetch(0);
+  int buf = 0;
+  for (int k0 = 0; k0 < m; k0 += kMfmaK) {
+#pragma unroll
+    for (int u = 0; u < kGroups; ++u) {
+      const int g = threadIdx.x + 256 * u;
+      const int r = g / (kMfmaK / 4), kq = (g % (kMfmaK / 4)) * 4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        As[buf][kq + e][r] = av[u][e];
+        Bs[buf][kq + e][r] = bv[u][e];
+      }
+    }
+    __syncthreads();
+    if (k0 + kMfmaK < m) fetch(k0 + kMfmaK);   // in flight during the products
+#pragma unroll
+    for (int ks = 0; ks < kMfmaK; ks += 4) {
+      const int kk = ks + (lane >> 4);
+      float a[4], b[4];
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi) a[bi] = As[buf][kk][64 * wr + 16 * bi + (lane & 15)];
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj) b[bj] = Bs[buf][kk][64 * wc + 16 * bj + (lane & 15)];
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+          acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+    }
+    buf ^= 1;
+  }
+  // element (bi, bj, v) of this lane: atom i0 + 64 wr + 16 bi + 4 (lane / 16) + v,
+  // column q0 + 64 wc + 16 bj + lane % 16
+  const int ib = i0 + 64 * wr + 4 * (lane >> 4);
+  const int qb = q0 + 64 * wc + (lane & 15);
+  if (MODE == 2) {
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) {
+      const int q = qb + 16 * bj;
       unsigned long long best = 0ull;
       if (q < ncols) {
         const unsigned* bm = insts[q].bitmap;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int i = i0 + 4 * ty + u;
-          if (i < n && !((bm[i >> 5] >> (i & 31)) & 1u)) {
-            const unsigned long long kk = pack_key(acc[u][v], i);
-            best = kk > best ? kk : best;
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = ib + 16 * bi + v;
+            if (i < n && !((bm[i >> 5] >> (i & 31)) & 1u)) {
+              const unsigned long long kk = pack_key(acc[bi][bj][v], i);
+              best = kk > best ? kk : best;
+            }
           }
-        }
       }
+      // lanes l, l+16, l+32, l+48 hold the same column
       for (int o = 16; o < 64; o <<= 1) {
         const unsigned long long other = __shfl_xor(best, o, 64);
         best = other > best ? other : best;
       }
-      if (lane < 16) kbest[w][4 * lane + v] = best;
+      if (lane < 16) kbest[wr][64 * wc + 16 * bj + lane] = best;
     }
     __syncthreads();
-    if (threadIdx.x < kGemmTile) {
+    if (threadIdx.x < kMfmaTile) {
       const int q = q0 + threadIdx.x;
       unsigned long long best = kbest[0][threadIdx.x];
-#pragma unroll
-      for (int ww = 1; ww < 4; ++ww) best = kbest[ww][threadIdx.x] > best ? kbest[ww][threadIdx.x] : best;
+      if (kbest[1][threadIdx.x] > best) best = kbest[1][threadIdx.x];
       if (q < ncols && best) atomicMax(&insts[q].key[t & 1], best);
     }
     return;
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int i = i0 + 4 * ty + u;
-    if (i >= n) continue;
+  for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int q = q0 + 4 * tx + v;
+    for (int bj = 0; bj < 4; ++bj) {
+      const int q = qb + 16 * bj;
       if (q >= ncols) continue;
-      if (MODE == 0)
-        Gf[i + (long long)q * ldh] = acc[u][v];
-      else
-        insts[q].c0[i] = acc[u][v];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = ib + 16 * bi + v;
+        if (i >= n) continue;
+        if (MODE == 0)
+          Gf[i + (long long)q * ldh] = acc[bi][bj][v];
+        else
+          insts[q].c0[i] = acc[bi][bj][v];
+      }
     }
-  }
 }
 
 // The shared Gram diagonal (prior included) for the coefficient updates.
@@ -3049,14 +3107,14 @@ hipError_t launch_coef_pass(int bf16, int lpa, int omp, const Inst* dc, int nact
 hipError_t launch_shared_gram(int bf16, const Inst* d, int nsig, int n, float* Gf, float* dg,
                               hipStream_t s) {
   if (nsig <= 0) return nothing_to_launch(s);
-  const int nt = (n + kGemmTile - 1) / kGemmTile;
-  const dim3 g0(nt, nt), g1(nt, (nsig + kGemmTile - 1) / kGemmTile);
+  const int nt = (n + kMfmaTile - 1) / kMfmaTile;
+  const dim3 g0(nt, nt), g1(nt, (nsig + kMfmaTile - 1) / kMfmaTile);
   if (bf16) {
-    CLOMP_LAUNCH((shared_gemm_kernel<uint16_t, 0>), g0, dim3(256), 0, s, d, nsig, Gf, 0);
-    CLOMP_LAUNCH((shared_gemm_kernel<uint16_t, 1>), g1, dim3(256), 0, s, d, nsig, Gf, 0);
+    CLOMP_LAUNCH((shared_mfma_kernel<uint16_t, 0>), g0, dim3(256), 0, s, d, nsig, Gf, 0);
+    CLOMP_LAUNCH((shared_mfma_kernel<uint16_t, 1>), g1, dim3(256), 0, s, d, nsig, Gf, 0);
   } else {
-    CLOMP_LAUNCH((shared_gemm_kernel<float, 0>), g0, dim3(256), 0, s, d, nsig, Gf, 0);
-    CLOMP_LAUNCH((shared_gemm_kernel<float, 1>), g1, dim3(256), 0, s, d, nsig, Gf, 0);
+    CLOMP_LAUNCH((shared_mfma_kernel<float, 0>), g0, dim3(256), 0, s, d, nsig, Gf, 0);
+    CLOMP_LAUNCH((shared_mfma_kernel<float, 1>), g1, dim3(256), 0, s, d, nsig, Gf, 0);
   }
   CLOMP_LAUNCH(shared_diag_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, d, Gf, dg);
   return hipGetLastError();
@@ -3079,11 +3137,11 @@ hipError_t launch_coef_reg(const Inst* dc, int nact, int t, int T, float beta1, 
 
 hipError_t launch_shared_rscan(int bf16, const Inst* d, int nsig, int n, int t, hipStream_t s) {
   if (nsig <= 0) return nothing_to_launch(s);
-  const dim3 g((n + kGemmTile - 1) / kGemmTile, (nsig + kGemmTile - 1) / kGemmTile);
+  const dim3 g((n + kMfmaTile - 1) / kMfmaTile, (nsig + kMfmaTile - 1) / kMfmaTile);
   if (bf16)
-    CLOMP_LAUNCH((shared_gemm_kernel<uint16_t, 2>), g, dim3(256), 0, s, d, nsig, nullptr, t);
+    CLOMP_LAUNCH((shared_mfma_kernel<uint16_t, 2>), g, dim3(256), 0, s, d, nsig, nullptr, t);
   else
-    CLOMP_LAUNCH((shared_gemm_kernel<float, 2>), g, dim3(256), 0, s, d, nsig, nullptr, t);
+    CLOMP_LAUNCH((shared_mfma_kernel<float, 2>), g, dim3(256), 0, s, d, nsig, nullptr, t);
   return hipGetLastError();
 }
 
