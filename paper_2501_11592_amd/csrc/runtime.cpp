@@ -722,11 +722,26 @@ clomp_status_t launch_hflow(clomp_ctx* h, const Plan& P, int bf16, hipStream_t s
         if (!omp && t1 > 256 && t1 <= 1024) lds = std::max(lds, (size_t)2048 * sizeof(float));
         if (W > 1) lds = std::max(lds, (t1 + 4 + 32) * sizeof(float));
         PhaseScope ps(h, PH_PASS, st);
-        if (P.gflow && !omp && W == 1 && t1 <= 256) {
-          // no pass shares the launch: a workgroup sized to the support
+        // Split launch: with a shared dictionary no pass shares the launch, and
+        // with more active signals than CUs the 16-wave coefficient workgroups
+        // of a fused launch would hold the device before any pass tile runs.
+        // The update then runs in workgroups sized to the support, and the
+        // pass (which reads the same key slot) follows in a launch of its own.
+        if (!omp && W == 1 && t1 <= 256 && (P.gflow || nact > h->num_cu)) {
           HIP_TRY(launch_coef_reg(d_insts + c.i0, nact, t, prm.inner_steps, prm.beta1, prm.beta2,
                                   prm.lr_rel, prm.eps_rel, st),
                   "coef_reg");
+          if (!P.gflow && nnext > 0) {
+            HIP_TRY(launch_coef_pass(bf16, c.lpa, omp, d_insts + c.i0, 0, 1, d_insts,
+                                     d_htiles + c.htile_off, c.htile_prefix[nnext], t,
+                                     prm.inner_steps, prm.beta1, prm.beta2, prm.lr_rel,
+                                     prm.eps_rel, lds, st),
+                    "pass");
+            if (h->profiling)
+              for (int q = c.i0; q < c.i0 + nnext; ++q)
+                h->pass_bytes +=
+                    (double)P.insts[q].m * P.insts[q].n * esz + 4.0 * P.insts[q].n;
+          }
         } else {
           // (a shared dictionary has every column of H already: no pass tiles)
           HIP_TRY(launch_coef_pass(bf16, c.lpa, omp, d_insts + c.i0, nact, W, d_insts,
