@@ -176,6 +176,7 @@ def measured_traffic(workload, kernel):
 
 
 VALU_PEAK_TFLOPS = 157.3   # FP32 vector, 256 CUs at 2.4 GHz
+MFMA_FP32_PEAK_TFLOPS = 157.3   # dense FP32 matrix cores (published)
 
 
 def fused_flops(items, method, inner_steps=32):
@@ -211,6 +212,20 @@ def roofline(p, items=None, method="clomp"):
                 "frac": ach / VALU_PEAK_TFLOPS, "traffic": None, "avg_launch_us": 1e3 * k_ms,
                 "flops_per_launch": fl, "hbm_bytes_per_launch": p["fused_bytes"] / nl,
                 "launches": nl}
+    shared = (items is not None and len(items) > 1 and p["pass_bytes"] == 0 and
+              len({it["At"].data_ptr() for it in items}) == 1)
+    if shared and p["ms"]["scan"] > p["ms"]["pass"]:
+        # shared dictionary: the scan is the contraction C = A^T R of the whole
+        # batch on the FP32 matrix cores (plus the once-per-solve A^T A, A^T Y)
+        n, m = int(items[0]["At"].shape[0]), int(items[0]["m"])
+        nl, ms = p["launches"]["scan"], p["ms"]["scan"]
+        fl = 2.0 * n * m * len(items)
+        k_ms = ms / nl
+        ach = fl / (k_ms * 1e-3) / 1e12
+        return {"kernel": "shared_mfma_kernel (C = A^T R over the batch, argmax epilogue)",
+                "bound": "mfma", "achieved": ach, "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / MFMA_FP32_PEAK_TFLOPS, "traffic": None,
+                "avg_launch_us": 1e3 * k_ms, "flops_per_launch": fl, "launches": nl}
     if p["launches"]["pass"] > 0 and p["ms"]["pass"] >= p["ms"]["scan"] and p["pass_bytes"] == 0:
         # shared dictionary: the launches carry coefficient workgroups only
         nl, ms = p["launches"]["pass"], p["ms"]["pass"]
