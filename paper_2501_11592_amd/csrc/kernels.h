@@ -83,6 +83,10 @@ hipError_t launch_shared_gram(int bf16, const Inst* d, int nsig, int n, float* G
 // iteration t with ceil((t+1)/16) waves per signal.
 hipError_t launch_coef_reg(const Inst* dc, int nact, int t, int T, float beta1, float beta2,
                             float lr_rel, float eps_rel, hipStream_t s);
+// OMP, no pass in the launch: selection record and bordered-inverse update of
+// iteration t in one 256-thread workgroup per signal.
+hipError_t launch_coef_omp(const Inst* dc, int nact, int t, float lr_rel, float eps_rel,
+                           hipStream_t s);
 // shared dictionary: the correlation scan of iteration t of signals
 // d[0..nsig) as C = A^T R over their residuals (argmax keys, slot t & 1).
 hipError_t launch_shared_rscan(int bf16, const Inst* d, int nsig, int n, int t, hipStream_t s);

@@ -727,10 +727,16 @@ clomp_status_t launch_hflow(clomp_ctx* h, const Plan& P, int bf16, hipStream_t s
         // of a fused launch would hold the device before any pass tile runs.
         // The update then runs in workgroups sized to the support, and the
         // pass (which reads the same key slot) follows in a launch of its own.
-        if (!omp && W == 1 && t1 <= 256 && (P.gflow || nact > h->num_cu)) {
-          HIP_TRY(launch_coef_reg(d_insts + c.i0, nact, t, prm.inner_steps, prm.beta1, prm.beta2,
-                                  prm.lr_rel, prm.eps_rel, st),
-                  "coef_reg");
+        // (OMP's update is short enough to hide under the pass of a fused
+        // launch: it splits only for a shared dictionary)
+        if (W == 1 && t1 <= 256 && (P.gflow || (!omp && nact > h->num_cu))) {
+          if (omp)
+            HIP_TRY(launch_coef_omp(d_insts + c.i0, nact, t, prm.lr_rel, prm.eps_rel, st),
+                    "coef_omp");
+          else
+            HIP_TRY(launch_coef_reg(d_insts + c.i0, nact, t, prm.inner_steps, prm.beta1,
+                                    prm.beta2, prm.lr_rel, prm.eps_rel, st),
+                    "coef_reg");
           if (!P.gflow && nnext > 0) {
             HIP_TRY(launch_coef_pass(bf16, c.lpa, omp, d_insts + c.i0, 0, 1, d_insts,
                                      d_htiles + c.htile_off, c.htile_prefix[nnext], t,

@@ -765,8 +765,12 @@ __global__ __launch_bounds__(1024) void adam_reg_kernel(const Inst* __restrict__
 // updated by consecutive rows r); there is no sequential triangular solve.
 constexpr int kOmpThreads = 1024;
 
+// NT threads: NT / 256 column groups of 256 row lanes; osh holds g[t+1] |
+// v[t+1] | vpart[NT / 256][t+1], red and red2 NT / 64 floats each.
+template <int NT = kOmpThreads>
 __device__ void omp_ginv_body(const Inst& I, int t, float* osh, float* red, float* red2,
                               bool clear_key = true) {
+  constexpr int NCG = NT / 256;
   if (I.st->done) {
     if (threadIdx.x == 0) *I.key = 0ull;
     return;
@@ -779,29 +783,33 @@ __device__ void omp_ginv_body(const Inst& I, int t, float* osh, float* red, floa
   float* vpart = osh + 2 * t1;
   const int tid = threadIdx.x;
   const int rl = tid & 255;      // row lane
-  const int cg = tid >> 8;       // column group: columns c = cg, cg+4, ...
-  for (int r = tid; r < t1; r += kOmpThreads) g[r] = I.G[r + (long long)t * ld];
+  const int cg = tid >> 8;       // column group: columns c = cg, cg+NCG, ...
+  for (int r = tid; r < t1; r += NT) g[r] = I.G[r + (long long)t * ld];
   __syncthreads();
-  // v = Ginv g over the first t rows / columns: 4 column groups, rows strided
+  // v = Ginv g over the first t rows / columns: NCG column groups, rows strided
   for (int r = rl; r < t; r += 256) {
     float a0 = 0.f, a1 = 0.f;
     int c = cg;
-    for (; c + 4 < t; c += 8) {
+    for (; c + NCG < t; c += 2 * NCG) {
       a0 = fmaf(Gi[r + (long long)c * ld], g[c], a0);
-      a1 = fmaf(Gi[r + (long long)(c + 4) * ld], g[c + 4], a1);
+      a1 = fmaf(Gi[r + (long long)(c + NCG) * ld], g[c + NCG], a1);
     }
     if (c < t) a0 = fmaf(Gi[r + (long long)c * ld], g[c], a0);
     vpart[cg * t1 + r] = a0 + a1;
   }
   __syncthreads();
   float pv = 0.f, px = 0.f;
-  for (int r = tid; r < t; r += kOmpThreads) {
-    const float vr = (vpart[r] + vpart[t1 + r]) + (vpart[2 * t1 + r] + vpart[3 * t1 + r]);
+  for (int r = tid; r < t; r += NT) {
+    float vr;
+    if constexpr (NCG == 4)
+      vr = (vpart[r] + vpart[t1 + r]) + (vpart[2 * t1 + r] + vpart[3 * t1 + r]);
+    else
+      vr = vpart[r];
     v[r] = vr;
     pv = fmaf(g[r], vr, pv);
     px = fmaf(g[r], I.s[r], px);
   }
-  // block sums (fixed order over the 16 waves)
+  // block sums (fixed order over the waves)
   pv = wave_sum(pv);
   px = wave_sum(px);
   if ((tid & 63) == 0) {
@@ -811,7 +819,7 @@ __device__ void omp_ginv_body(const Inst& I, int t, float* osh, float* red, floa
   __syncthreads();
   float gv = 0.f, gx = 0.f;
 #pragma unroll
-  for (int q = 0; q < kOmpThreads / 64; ++q) {
+  for (int q = 0; q < NT / 64; ++q) {
     gv += red[q];
     gx += red2[q];
   }
@@ -821,14 +829,14 @@ __device__ void omp_ginv_body(const Inst& I, int t, float* osh, float* red, floa
   if (bad) delta = fmaxf(1e-7f * gamma, 1e-30f);
   const float inv = 1.f / delta;
   const float alpha = (I.b[t] - gx) * inv;
-  for (int r = tid; r < t; r += kOmpThreads) {
+  for (int r = tid; r < t; r += NT) {
     I.s[r] = fmaf(-alpha, v[r], I.s[r]);
     const float w = -v[r] * inv;
     Gi[r + (long long)t * ld] = w;
     Gi[t + (long long)r * ld] = w;
   }
   // rank-one update Ginv += v v^T / delta: column groups x rows, coalesced
-  for (int c = cg; c < t; c += 4) {
+  for (int c = cg; c < t; c += NCG) {
     const float vc = v[c] * inv;
     float* col = Gi + (long long)c * ld;
     for (int r = rl; r < t; r += 256) col[r] = fmaf(v[r], vc, col[r]);
@@ -2650,6 +2658,29 @@ __global__ __launch_bounds__(1024) void coef_reg_kernel(const Inst* __restrict__
   adam_reg_body<RPL>(I, t, T, beta1, beta2, part, blockDim.x >> 6, false);
 }
 
+// OMP counterpart of coef_reg_kernel: the selection record and the
+// bordered-inverse update of iteration t in one 256-thread workgroup per
+// signal (no pass in the launch).
+__global__ __launch_bounds__(256) void coef_omp_kernel(const Inst* __restrict__ insts_c, int t,
+                                                       float lr_rel, float eps_rel) {
+  extern __shared__ __align__(16) float osh[];   // g[t+1] | v[t+1] | vpart[t+1]
+  __shared__ float red[4], red2[4];
+  const Inst& I = insts_c[blockIdx.x];
+  if (I.st->done) return;
+  const unsigned long long key = I.key[t & 1];
+  const int j = key_index(key);
+  if (key == 0ull || j < 0 || j >= I.n) {
+    if (threadIdx.x == 0) {
+      I.st->done = 1;
+      atomicOr(I.status, ST_WATCHDOG);
+    }
+    return;
+  }
+  record_selection<256>(I, key, t, lr_rel, eps_rel);
+  __syncthreads();
+  omp_ginv_body<256>(I, t, osh, red, red2, false);
+}
+
 // ============================================================ launchers
 // A launcher with nothing to launch still records pending profiling events,
 // so every recorded interval is valid (and empty).
@@ -3117,6 +3148,14 @@ hipError_t launch_shared_gram(int bf16, const Inst* d, int nsig, int n, float* G
     CLOMP_LAUNCH((shared_mfma_kernel<float, 1>), g1, dim3(256), 0, s, d, nsig, Gf, 0);
   }
   CLOMP_LAUNCH(shared_diag_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, d, Gf, dg);
+  return hipGetLastError();
+}
+
+hipError_t launch_coef_omp(const Inst* dc, int nact, int t, float lr_rel, float eps_rel,
+                           hipStream_t s) {
+  if (nact <= 0) return nothing_to_launch(s);
+  const size_t lds = (size_t)3 * (t + 1) * sizeof(float);
+  CLOMP_LAUNCH(coef_omp_kernel, dim3(nact), dim3(256), lds, s, dc, t, lr_rel, eps_rel);
   return hipGetLastError();
 }
 

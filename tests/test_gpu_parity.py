@@ -242,26 +242,27 @@ def test_large_support_single_workgroup():
     sol.close()
 
 
-def test_many_iterated_signals_split_launch():
+@pytest.mark.parametrize("method", ["clomp", "omp"])
+def test_many_iterated_signals_split_launch(method):
     """More active signals than CUs under the correlation-update schedule: the
-    coefficient update runs in support-sized workgroups and the pass in a
-    launch of its own.  600 distinct small signals (n=256, m=64, k=8, and
+    CLOMP coefficient update runs in support-sized workgroups and the pass in
+    a launch of its own (OMP keeps the fused launch).  600 distinct small signals (n=256, m=64, k=8, and
     k=24 for every fifth) kept out of the fused loop; every fifteenth against
     the oracle, the rest against the fused path's supports."""
     sigs = [W.single_small(1600 + i, k=24 if i % 5 == 0 else 8) for i in range(600)]
     items = _items(sigs)
-    sol = C.Solver(0, method="clomp", flags=C.FLAG_CORR_FLOW | C.FLAG_NO_FUSED_SMALL)
+    sol = C.Solver(0, method=method, flags=C.FLAG_CORR_FLOW | C.FLAG_NO_FUSED_SMALL)
     out = sol.solve_batch(items)
-    fused = C.Solver(0, method="clomp")
+    fused = C.Solver(0, method=method)
     ref = fused.solve_batch(items)
     torch.cuda.synchronize()
     assert (out.status.cpu().numpy() == 0).all()
     kinds = []
     for i in range(0, 600, 15):
-        res = oracle_final_x("clomp", sigs[i].A, sigs[i].y, sigs[i].k)
+        res = oracle_final_x(method, sigs[i].A, sigs[i].y, sigs[i].k)
         kinds.append(compare(out, i, res, sigs[i].A, sigs[i].y, delta=FP32_DELTA, u=FP32_U,
-                             method="clomp", A_sel=sigs[i].A, k=sigs[i].k, tol_x=1e-5))
-    print(f"split launch: identical {kinds.count('identical')}/{len(kinds)}")
+                             method=method, A_sel=sigs[i].A, k=sigs[i].k, tol_x=1e-5))
+    print(f"{method} split launch: identical {kinds.count('identical')}/{len(kinds)}")
     assert kinds.count("identical") >= len(kinds) * 3 // 4
     same = sum(out.support[i].tolist() == ref.support[i].tolist() for i in range(600))
     assert same >= 570, same

@@ -90,3 +90,28 @@ def test_shared_gram_image4k_sampled():
                              method="clomp", A_sel=b.A, k=b.k, tol_x=1e-5))
     print(f"image4k: identical {kinds.count('identical')}/{len(kinds)}")
     assert kinds.count("identical") >= 4
+
+
+@pytest.mark.parametrize("method", ["clomp", "omp"])
+def test_shared_gram_graph_replay(method):
+    """The shared-dictionary launch sequence captured into a HIP graph on a
+    created stream and replayed (new output buffers each call): every replay
+    equals the eager solve bit for bit."""
+    b = W.image_batch(0.3)
+    At, Y = dev(b.At), dev(b.Y)
+    eager = _solve(method, b, ITER)
+    sol = C.Solver(0, method=method, flags=ITER | C.FLAG_GRAPH)
+    stream = torch.cuda.Stream()
+    outs = []
+    for _ in range(3):
+        with torch.cuda.stream(stream):
+            outs.append(sol.solve_batch([dict(At=At, m=b.m, y=Y[c], k=b.k)
+                                         for c in range(Y.shape[0])], stream=stream))
+        stream.synchronize()
+        torch.cuda.synchronize()   # eager work of the program between replays
+    for out in outs:
+        for c in range(0, 256, 5):
+            assert out.support[c].tolist() == eager.support[c].tolist(), c
+            assert torch.equal(out.x[c], eager.x[c]), c
+        assert torch.equal(out.resid_norm, eager.resid_norm)
+    sol.close()
