@@ -87,6 +87,9 @@ hipError_t launch_coef_reg(const Inst* dc, int nact, int t, int T, float beta1, 
 // iteration t in one 256-thread workgroup per signal.
 hipError_t launch_coef_omp(const Inst* dc, int nact, int t, float lr_rel, float eps_rel,
                            hipStream_t s);
+// shared dictionary: r = y - A_S s of iteration t (t+1 <= 256), one
+// workgroup per signal d[0..nsig).
+hipError_t launch_shared_resid(int bf16, const Inst* d, int nsig, int t, hipStream_t s);
 // shared dictionary: the correlation scan of iteration t of signals
 // d[0..nsig) as C = A^T R over their residuals (argmax keys, slot t & 1).
 hipError_t launch_shared_rscan(int bf16, const Inst* d, int nsig, int n, int t, hipStream_t s);

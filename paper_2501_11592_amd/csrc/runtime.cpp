@@ -766,8 +766,11 @@ clomp_status_t launch_hflow(clomp_ctx* h, const Plan& P, int bf16, hipStream_t s
         // of all of them as one contraction C = A^T R with the argmax fused
         {
           PhaseScope ps(h, PH_RESID, st);
-          HIP_TRY(launch_resid(bf16, d_insts, d_rows + c.row_off, c.row_prefix[nnext], t, st),
-                  "resid");
+          if (t + 1 <= 256)
+            HIP_TRY(launch_shared_resid(bf16, d_insts + c.i0, nnext, t, st), "resid");
+          else
+            HIP_TRY(launch_resid(bf16, d_insts, d_rows + c.row_off, c.row_prefix[nnext], t, st),
+                    "resid");
         }
         PhaseScope ps(h, PH_SCAN, st);
         HIP_TRY(launch_shared_rscan(bf16, d_insts + c.i0, nnext, P.insts[c.i0].n, t + 1, st),

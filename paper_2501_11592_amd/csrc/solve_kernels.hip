@@ -1785,6 +1785,39 @@ __global__ __launch_bounds__(256) void shared_mfma_kernel(const Inst* __restrict
     }
 }
 
+// Residual of iteration t (t+1 <= 256 atoms) of one signal per 256-thread
+// workgroup: r = y - A_S s, the support and coefficients staged in LDS, each
+// thread's rows summed over four independent chains (the shared A is cache
+// resident; one workgroup per signal keeps the launch small).
+template <typename TA>
+__global__ __launch_bounds__(256) void shared_resid_kernel(const Inst* __restrict__ insts, int t) {
+  __shared__ float ssh[256];
+  __shared__ int jsh[256];
+  const Inst& I = insts[blockIdx.x];
+  if (I.st->done) return;
+  const int t1 = t + 1;
+  for (int l = threadIdx.x; l < t1; l += 256) {
+    ssh[l] = I.s[l];
+    jsh[l] = I.support[l];
+  }
+  __syncthreads();
+  const TA* A = reinterpret_cast<const TA*>(I.A);
+  const long long lda = I.lda;
+  const float* yw = I.r + I.m_pad;
+  for (int i = threadIdx.x; i < I.m; i += 256) {
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    int l = 0;
+    for (; l + 3 < t1; l += 4) {
+      a0 = fmaf(Vec<TA>::one(A + (long long)jsh[l] * lda + i), ssh[l], a0);
+      a1 = fmaf(Vec<TA>::one(A + (long long)jsh[l + 1] * lda + i), ssh[l + 1], a1);
+      a2 = fmaf(Vec<TA>::one(A + (long long)jsh[l + 2] * lda + i), ssh[l + 2], a2);
+      a3 = fmaf(Vec<TA>::one(A + (long long)jsh[l + 3] * lda + i), ssh[l + 3], a3);
+    }
+    for (; l < t1; ++l) a0 = fmaf(Vec<TA>::one(A + (long long)jsh[l] * lda + i), ssh[l], a0);
+    I.r[i] = yw[i] - ((a0 + a1) + (a2 + a3));
+  }
+}
+
 // The shared Gram diagonal (prior included) for the coefficient updates.
 __global__ __launch_bounds__(kBlock) void shared_diag_kernel(const Inst* __restrict__ insts,
                                                              const float* __restrict__ Gf,
@@ -3171,6 +3204,16 @@ hipError_t launch_coef_reg(const Inst* dc, int nact, int t, int T, float beta1, 
     CLOMP_LAUNCH(coef_reg_kernel<2>, g, b, 0, s, dc, t, T, beta1, beta2, lr_rel, eps_rel);
   else
     CLOMP_LAUNCH(coef_reg_kernel<4>, g, b, 0, s, dc, t, T, beta1, beta2, lr_rel, eps_rel);
+  return hipGetLastError();
+}
+
+hipError_t launch_shared_resid(int bf16, const Inst* d, int nsig, int t, hipStream_t s) {
+  if (nsig <= 0) return nothing_to_launch(s);
+  if (t + 1 > 256) return hipErrorInvalidValue;
+  if (bf16)
+    CLOMP_LAUNCH(shared_resid_kernel<uint16_t>, dim3(nsig), dim3(256), 0, s, d, t);
+  else
+    CLOMP_LAUNCH(shared_resid_kernel<float>, dim3(nsig), dim3(256), 0, s, d, t);
   return hipGetLastError();
 }
 
