@@ -115,3 +115,37 @@ def test_shared_gram_graph_replay(method):
             assert torch.equal(out.x[c], eager.x[c]), c
         assert torch.equal(out.resid_norm, eager.resid_norm)
     sol.close()
+
+
+@pytest.mark.parametrize("method", ["clomp", "omp"])
+def test_shared_gram_edges(method):
+    """A shared A whose lda padding holds NaN, columns with k = 32, 16 and 8
+    (signals leave the active prefix at different iterations) and one zero
+    column y: the zero column returns x = 0 with the zero-y bit, the others
+    match the oracle where well separated."""
+    b = W.image_batch(0.3, lda=96)
+    At = b.At.copy()
+    At[:, b.m:] = np.nan
+    Y = b.Y.copy()
+    Y[7] = 0.0
+    ks = [(32, 16, 8)[c % 3] for c in range(256)]
+    sol = C.Solver(0, method=method, flags=ITER)
+    At_d, Y_d = dev(At), dev(Y)
+    out = sol.solve_batch([dict(At=At_d, m=b.m, y=Y_d[c], k=ks[c]) for c in range(256)])
+    torch.cuda.synchronize()
+    st = out.status.cpu().numpy()
+    assert st[7] & C.ST_ZERO_Y and int(out.n_selected[7]) == 0 and not out.x[7].any()
+    assert not (st & C.ST_NAN).any()
+    for c in range(256):
+        if c != 7:
+            assert int(out.n_selected[c]) == ks[c], c
+    kinds = []
+    for c in range(0, 256, 9):
+        if c == 7:
+            continue
+        res = oracle_final_x(method, b.A, Y[c], ks[c])
+        kinds.append(compare(out, c, res, b.A, Y[c], delta=FP32_DELTA, u=FP32_U, method=method,
+                             A_sel=b.A, k=ks[c], tol_x=1e-5))
+    print(f"{method} edges: identical {kinds.count('identical')}/{len(kinds)}")
+    assert kinds.count("identical") >= len(kinds) // 2
+    sol.close()
