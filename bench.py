@@ -260,9 +260,8 @@ def roofline(p, items=None, method="clomp"):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not served "
-              "(independent signals shard across GPUs without communication; see the "
-              "design notes)", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not served "
+              "(independent signals shard across GPUs without communication)", file=sys.stderr)
         sys.exit(2)
     import torch
     if args.copy_calibration:

@@ -42,7 +42,7 @@ typedef enum {
   CLOMP_INVALID_ARGUMENT = 1,  /* null pointer, bad size, layout or alignment */
   CLOMP_OUT_OF_MEMORY = 2,     /* workspace allocation failed */
   CLOMP_DEVICE_ERROR = 3,      /* a HIP call failed (message in last_error) */
-  CLOMP_NOT_SUPPORTED = 4      /* valid request this build does not serve */
+  CLOMP_NOT_SUPPORTED = 4      /* valid request the library does not serve */
 } clomp_status_t;
 
 typedef enum { CLOMP_F32 = 0, CLOMP_BF16 = 1, CLOMP_F64 = 2 } clomp_dtype_t;
