@@ -149,3 +149,31 @@ def test_shared_gram_edges(method):
     print(f"{method} edges: identical {kinds.count('identical')}/{len(kinds)}")
     assert kinds.count("identical") >= len(kinds) // 2
     sol.close()
+
+
+@pytest.mark.parametrize("method", ["clomp", "omp"])
+def test_shared_gram_large_support_teams(method):
+    """Four signals sharing A (n=2048, m=1024) with k = 300: supports beyond
+    256 atoms run the coefficient teams, reading the Gram row through the
+    shared matrix, and the residual by row tiles."""
+    g = np.random.default_rng(1777)
+    n, m, k = 2048, 1024, 300
+    A = g.standard_normal((m, n)) / np.sqrt(m)
+    At = np.ascontiguousarray(A.T.astype(np.float32))
+    A = At.T.astype(np.float64)
+    sigs = []
+    for i in range(4):
+        x = np.zeros(n)
+        x[g.choice(n, k, replace=False)] = g.standard_normal(k)
+        sigs.append((A @ x).astype(np.float32))
+    At_d = dev(At)
+    sol = C.Solver(0, method=method)
+    out = sol.solve_batch([dict(At=At_d, m=m, y=dev(y), k=k) for y in sigs])
+    torch.cuda.synchronize()
+    assert (out.status.cpu().numpy() == 0).all()
+    assert (out.n_selected.cpu().numpy() == k).all()
+    res = oracle_final_x(method, A, sigs[0].astype(np.float64), k)
+    kind = compare(out, 0, res, A, sigs[0].astype(np.float64), delta=FP32_DELTA, u=FP32_U,
+                   method=method, A_sel=A, k=k, tol_x=1e-5)
+    print(f"{method} k=300 shared: {kind}")
+    sol.close()
