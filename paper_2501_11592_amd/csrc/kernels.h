@@ -87,6 +87,10 @@ hipError_t launch_coef_reg(const Inst* dc, int nact, int t, int T, float beta1, 
 // iteration t in one 256-thread workgroup per signal.
 hipError_t launch_coef_omp(const Inst* dc, int nact, int t, float lr_rel, float eps_rel,
                            hipStream_t s);
+// shared dictionary, IHT / paper mode: g = A^T r of signals d[0..nsig) into
+// gbuf (and c0 when `first`), one contraction for the batch.
+hipError_t launch_shared_grad(int bf16, const Inst* d, int nsig, int n, int first,
+                              hipStream_t s);
 // shared dictionary: r = y - A_S s of iteration t (t+1 <= 256), one
 // workgroup per signal d[0..nsig).
 hipError_t launch_shared_resid(int bf16, const Inst* d, int nsig, int t, hipStream_t s);

@@ -76,6 +76,8 @@ struct Plan {
   int kmax = 0, cg_tmax = 0, cg_mpad_max = 0, cg_lpa = 64;
   bool hflow = false;                 // correlation-update schedule
   bool gflow = false;                 // ... with a shared dictionary: full Gram, no passes
+  bool ishared = false;               // IHT / paper mode with a shared dictionary: one
+                                      // A^T R contraction per iteration
   size_t off_gf = 0, off_gdg = 0;     // shared Gram matrix and diagonal (workspace)
   int nbig = 0;                       // sorted instances [0, nbig) use the iterated kernels;
                                       // [nbig, count) run the fused small-signal loop
@@ -310,14 +312,15 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     // shared dictionary: every iterated signal has the same A (pointer, layout,
     // master) and the full Gram matrix fits in 4 GB; an iteration then reads
     // columns of A^T A instead of streaming A
-    bool shared = P.nbig >= 2 && !iht && !(fl & CLOMP_FLAG_RESIDUAL_FLOW) &&
-                  !(fl & CLOMP_FLAG_NO_SHARED_GRAM);
-    for (int s = 1; s < P.nbig && shared; ++s) {
+    bool sameA = P.nbig >= 2 && !(fl & CLOMP_FLAG_NO_SHARED_GRAM);
+    for (int s = 1; s < P.nbig && sameA; ++s) {
       const clomp_instance_t& a = inst[order[0]];
       const clomp_instance_t& b = inst[order[s]];
-      shared = a.A == b.A && a.lda == b.lda && a.n == b.n && a.m == b.m &&
-               a.A_master == b.A_master && a.lda_master == b.lda_master;
+      sameA = a.A == b.A && a.lda == b.lda && a.n == b.n && a.m == b.m &&
+              a.A_master == b.A_master && a.lda_master == b.lda_master;
     }
+    P.ishared = iht && sameA;
+    bool shared = sameA && !iht && !(fl & CLOMP_FLAG_RESIDUAL_FLOW);
     if (shared) {
       const size_t l = (size_t)round_up_int(inst[order[0]].n, 256);
       shared = l * l * sizeof(float) <= ((size_t)4 << 30);
@@ -327,7 +330,8 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     // (the pass and the coefficient update share one launch per iteration)
     P.hflow = P.nbig > 0 && (P.gflow || (fits && !(fl & CLOMP_FLAG_RESIDUAL_FLOW) && !iht));
   }
-  snprintf(sigbuf, sizeof sigbuf, "h%d;g%d;f%d;", (int)P.hflow, (int)P.gflow, count - P.nbig);
+  snprintf(sigbuf, sizeof sigbuf, "h%d;g%d;i%d;f%d;", (int)P.hflow, (int)P.gflow, (int)P.ishared,
+           count - P.nbig);
   P.sig += sigbuf;
   P.insts.resize(count);
   P.keff.resize(count);
@@ -391,7 +395,8 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     d.nslice = 1;
     if (iht) {
       d.ldh = round_up_int(d.n, 256);
-      d.nslice = std::max(1, (d.m_pad + kIhtSliceFloats - 1) / kIhtSliceFloats);
+      // (a shared dictionary's gradient is one contraction: no slices)
+      d.nslice = P.ishared ? 1 : std::max(1, (d.m_pad + kIhtSliceFloats - 1) / kIhtSliceFloats);
       o_c0 = take(sizeof(float) * d.ldh);
       o_gb = take(sizeof(float) * d.ldh * d.nslice);
       o_sf = take(sizeof(float) * d.ldh);
@@ -811,9 +816,13 @@ clomp_status_t launch_iht(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st)
       }
       {
         PhaseScope ps(h, PH_SCAN, st);
-        HIP_TRY(launch_iht_grad(bf16, c.lpa, d_insts, d_tiles + c.tile_off, ntiles, c.nslice,
-                                r_lds, it == 0, st),
-                "iht grad");
+        if (P.ishared)
+          HIP_TRY(launch_shared_grad(bf16, d_insts + c.i0, nall, P.insts[c.i0].n, it == 0, st),
+                  "iht grad");
+        else
+          HIP_TRY(launch_iht_grad(bf16, c.lpa, d_insts, d_tiles + c.tile_off, ntiles, c.nslice,
+                                  r_lds, it == 0, st),
+                  "iht grad");
         if (h->profiling)
           for (int q = c.i0; q < c.i1; ++q)
             h->scan_bytes += (double)P.insts[q].m * P.insts[q].n * esz + 4.0 * P.insts[q].m +
@@ -869,9 +878,13 @@ clomp_status_t launch_paper(clomp_ctx* h, const Plan& P, int bf16, hipStream_t s
       }
       {
         PhaseScope ps(h, PH_SCAN, st);
-        HIP_TRY(launch_iht_grad(bf16, c.lpa, d_insts, d_tiles + c.tile_off, ntiles, c.nslice,
-                                r_lds, it == 0, st),
-                "paper scan");
+        if (P.ishared)
+          HIP_TRY(launch_shared_grad(bf16, d_insts + c.i0, nall, P.insts[c.i0].n, it == 0, st),
+                  "paper scan");
+        else
+          HIP_TRY(launch_iht_grad(bf16, c.lpa, d_insts, d_tiles + c.tile_off, ntiles, c.nslice,
+                                  r_lds, it == 0, st),
+                  "paper scan");
         if (h->profiling)
           for (int q = c.i0; q < c.i1; ++q)
             h->scan_bytes += (double)P.insts[q].m * P.insts[q].n * esz + 4.0 * P.insts[q].m +

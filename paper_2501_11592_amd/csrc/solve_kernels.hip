@@ -1629,7 +1629,9 @@ __global__ __launch_bounds__(NT) void paper_select_kernel(const Inst* __restrict
 // workspace copy), C[:, q] = c0 of signal q;  MODE 2: B_q = the residual r of
 // signal q, and instead of C each signal gets the argmax key of its column
 // over unselected atoms (key slot `t & 1`): the correlation scan of a whole
-// batch as one contraction C = A^T R.
+// batch as one contraction C = A^T R;  MODE 3: B_q = the residual r of
+// signal q, C[:, q] = the gradient g of IHT / paper mode (gbuf), and when
+// t != 0 (the first iteration, r = y) also c0.
 constexpr int kMfmaTile = 128, kMfmaK = 32, kMfmaLd = 145;
 typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 
@@ -1686,7 +1688,7 @@ __global__ __launch_bounds__(256) void shared_mfma_kernel(const Inst* __restrict
         load_a(q, k, bv[u]);
       } else if (q < ncols) {
         // y and r are zero padded to m_pad (a multiple of 8)
-        const float* src = bsrc[r];
+        const float* src = bsrc[r];   // (MODE 3 reads r like MODE 2)
         if (k < m_pad) {
           const float4 v4 = *reinterpret_cast<const float4*>(src + k);
           bv[u][0] = v4.x; bv[u][1] = v4.y; bv[u][2] = v4.z; bv[u][3] = v4.w;
@@ -1777,10 +1779,14 @@ __global__ __launch_bounds__(256) void shared_mfma_kernel(const Inst* __restrict
       for (int v = 0; v < 4; ++v) {
         const int i = ib + 16 * bi + v;
         if (i >= n) continue;
-        if (MODE == 0)
+        if (MODE == 0) {
           Gf[i + (long long)q * ldh] = acc[bi][bj][v];
-        else
+        } else if (MODE == 1) {
           insts[q].c0[i] = acc[bi][bj][v];
+        } else {
+          insts[q].gbuf[i] = acc[bi][bj][v];
+          if (t) insts[q].c0[i] = acc[bi][bj][v];
+        }
       }
     }
 }
@@ -3214,6 +3220,17 @@ hipError_t launch_shared_resid(int bf16, const Inst* d, int nsig, int t, hipStre
     CLOMP_LAUNCH(shared_resid_kernel<uint16_t>, dim3(nsig), dim3(256), 0, s, d, t);
   else
     CLOMP_LAUNCH(shared_resid_kernel<float>, dim3(nsig), dim3(256), 0, s, d, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_shared_grad(int bf16, const Inst* d, int nsig, int n, int first,
+                              hipStream_t s) {
+  if (nsig <= 0) return nothing_to_launch(s);
+  const dim3 g((n + kMfmaTile - 1) / kMfmaTile, (nsig + kMfmaTile - 1) / kMfmaTile);
+  if (bf16)
+    CLOMP_LAUNCH((shared_mfma_kernel<uint16_t, 3>), g, dim3(256), 0, s, d, nsig, nullptr, first);
+  else
+    CLOMP_LAUNCH((shared_mfma_kernel<float, 3>), g, dim3(256), 0, s, d, nsig, nullptr, first);
   return hipGetLastError();
 }
 

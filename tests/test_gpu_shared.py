@@ -177,3 +177,41 @@ def test_shared_gram_large_support_teams(method):
                    method=method, A_sel=A, k=k, tol_x=1e-5)
     print(f"{method} k=300 shared: {kind}")
     sol.close()
+
+
+@pytest.mark.parametrize("method", ["iht", "clomp_paper"])
+def test_shared_gradient_iht_and_paper_mode(method):
+    """IHT and paper mode on 256 columns sharing A: the gradient of each
+    iteration is one contraction A^T R for the batch.  Against the oracle on
+    well-separated columns and against the per-signal scan (supports equal
+    where the oracle asserts them)."""
+    from oracle import iht_fp64, clomp_paper_fp64, PaperParams, well_separated
+    from tests.gpu_helpers import rel_err
+    R = 20
+    b = W.image_batch(0.3)
+    out = _solve(method, b, 0, inner_steps=R)
+    per = _solve(method, b, C.FLAG_NO_SHARED_GRAM, inner_steps=R)
+    prm = PaperParams(threshold=f32(0.7), max_iters=R, lr_rel=f32(0.05), beta1=f32(0.9),
+                      beta2=f32(0.999), eps_rel=f32(1e-8))
+    ident = total = 0
+    for c in range(0, 256, 8):
+        y = b.Y[c].astype(np.float64)
+        if method == "iht":
+            ref = iht_fp64(b.A, y, b.k, max_iters=R)
+            from types import SimpleNamespace
+            sep = SimpleNamespace(max_iters=R)
+        else:
+            ref = clomp_paper_fp64(b.A, y, b.k, prm)
+            sep = prm
+        ok, _ = well_separated(b.A, y, b.k, method=method, params=sep, delta=FP32_DELTA,
+                               u=FP32_U, base=ref)
+        total += 1
+        if not ok:
+            continue
+        supp = out.support[c][:int(out.n_selected[c])].tolist()
+        assert supp == ref.support, (c, supp, ref.support)
+        assert supp == per.support[c][:int(per.n_selected[c])].tolist(), c
+        assert rel_err(out.x[c].cpu().numpy().astype(np.float64), ref.x) <= 1e-5, c
+        ident += 1
+    print(f"{method} shared gradient: identical {ident}/{total}")
+    assert ident >= total // 3
