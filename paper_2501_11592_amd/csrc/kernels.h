@@ -91,9 +91,11 @@ hipError_t launch_coef_omp(const Inst* dc, int nact, int t, float lr_rel, float 
 // gbuf (and c0 when `first`), one contraction for the batch.
 hipError_t launch_shared_grad(int bf16, const Inst* d, int nsig, int n, int first,
                               hipStream_t s);
-// shared dictionary: r = y - A_S s of iteration t (t+1 <= 256), one
-// workgroup per signal d[0..nsig).
-hipError_t launch_shared_resid(int bf16, const Inst* d, int nsig, int t, hipStream_t s);
+// shared dictionary, one workgroup per signal d[0..nsig), supports of t1 <=
+// 256 atoms (0: each signal's own count): mode 0 r = y - A_S s, mode 1 the
+// IHT step denominator ||A_S g_S||^2 as row partials.
+hipError_t launch_shared_rows(int bf16, int mode, const Inst* d, int nsig, int t1,
+                              hipStream_t s);
 // shared dictionary: the correlation scan of iteration t of signals
 // d[0..nsig) as C = A^T R over their residuals (argmax keys, slot t & 1).
 hipError_t launch_shared_rscan(int bf16, const Inst* d, int nsig, int n, int t, hipStream_t s);

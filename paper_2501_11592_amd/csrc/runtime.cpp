@@ -772,7 +772,7 @@ clomp_status_t launch_hflow(clomp_ctx* h, const Plan& P, int bf16, hipStream_t s
         {
           PhaseScope ps(h, PH_RESID, st);
           if (t + 1 <= 256)
-            HIP_TRY(launch_shared_resid(bf16, d_insts + c.i0, nnext, t, st), "resid");
+            HIP_TRY(launch_shared_rows(bf16, 0, d_insts + c.i0, nnext, t + 1, st), "resid");
           else
             HIP_TRY(launch_resid(bf16, d_insts, d_rows + c.row_off, c.row_prefix[nnext], t, st),
                     "resid");
@@ -809,10 +809,15 @@ clomp_status_t launch_iht(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st)
       const int ntiles = c.tile_prefix[nall];
       const int nrows = c.row_prefix[nall];
       const int r_lds = (c.slice_floats <= lds_cap) ? c.slice_floats : 0;
+      // a shared dictionary forms each signal's products in one workgroup
+      const bool srows = P.ishared && c.kmax <= 256;
       if (it > 0) {
         PhaseScope ps(h, PH_RESID, st);
-        HIP_TRY(launch_iht_rows(bf16, 0, d_insts, d_rows + c.row_off, nrows, c.kmax, st),
-                "iht resid");
+        if (srows)
+          HIP_TRY(launch_shared_rows(bf16, 0, d_insts + c.i0, nall, 0, st), "iht resid");
+        else
+          HIP_TRY(launch_iht_rows(bf16, 0, d_insts, d_rows + c.row_off, nrows, c.kmax, st),
+                  "iht resid");
       }
       {
         PhaseScope ps(h, PH_SCAN, st);
@@ -839,8 +844,11 @@ clomp_status_t launch_iht(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st)
       }
       {
         PhaseScope ps(h, PH_GRAM, st);
-        HIP_TRY(launch_iht_rows(bf16, 1, d_insts, d_rows + c.row_off, nrows, c.kmax, st),
-                "iht step");
+        if (srows)
+          HIP_TRY(launch_shared_rows(bf16, 1, d_insts + c.i0, nall, 0, st), "iht step");
+        else
+          HIP_TRY(launch_iht_rows(bf16, 1, d_insts, d_rows + c.row_off, nrows, c.kmax, st),
+                  "iht step");
       }
       {
         PhaseScope ps(h, PH_COEF, st);
@@ -873,8 +881,11 @@ clomp_status_t launch_paper(clomp_ctx* h, const Plan& P, int bf16, hipStream_t s
       const int r_lds = (c.slice_floats <= lds_cap) ? c.slice_floats : 0;
       if (it > 0) {
         PhaseScope ps(h, PH_RESID, st);
-        HIP_TRY(launch_iht_rows(bf16, 0, d_insts, d_rows + c.row_off, nrows, c.kmax, st),
-                "paper resid");
+        if (P.ishared && c.kmax <= 256)
+          HIP_TRY(launch_shared_rows(bf16, 0, d_insts + c.i0, nall, 0, st), "paper resid");
+        else
+          HIP_TRY(launch_iht_rows(bf16, 0, d_insts, d_rows + c.row_off, nrows, c.kmax, st),
+                  "paper resid");
       }
       {
         PhaseScope ps(h, PH_SCAN, st);

@@ -1791,25 +1791,32 @@ __global__ __launch_bounds__(256) void shared_mfma_kernel(const Inst* __restrict
     }
 }
 
-// Residual of iteration t (t+1 <= 256 atoms) of one signal per 256-thread
-// workgroup: r = y - A_S s, the support and coefficients staged in LDS, each
-// thread's rows summed over four independent chains (the shared A is cache
-// resident; one workgroup per signal keeps the launch small).
-template <typename TA>
-__global__ __launch_bounds__(256) void shared_resid_kernel(const Inst* __restrict__ insts, int t) {
+// Products over one signal's support, one 256-thread workgroup per signal
+// (t1 <= 256 atoms: the given count, or the signal's own when 0), the support
+// and coefficients staged in LDS, each thread's rows summed over four
+// independent chains (the shared A is cache resident; one workgroup per
+// signal keeps the launch small).  MODE 0: r = y - A_S s;  MODE 1: the IHT
+// step denominator ||A_S g_S||^2 (g from gbuf) as the signal's row partials
+// (the total in the first, zeros in the others).
+template <typename TA, int MODE>
+__global__ __launch_bounds__(256) void shared_rows_kernel(const Inst* __restrict__ insts,
+                                                          int t1_arg) {
   __shared__ float ssh[256];
   __shared__ int jsh[256];
+  __shared__ float red[4];
   const Inst& I = insts[blockIdx.x];
-  if (I.st->done) return;
-  const int t1 = t + 1;
+  if (I.st->done || I.st->stop) return;
+  const int t1 = t1_arg > 0 ? t1_arg : *I.nsel;
   for (int l = threadIdx.x; l < t1; l += 256) {
-    ssh[l] = I.s[l];
-    jsh[l] = I.support[l];
+    const int j = I.support[l];
+    jsh[l] = j;
+    ssh[l] = (MODE == 0) ? I.s[l] : I.gbuf[j];
   }
   __syncthreads();
   const TA* A = reinterpret_cast<const TA*>(I.A);
   const long long lda = I.lda;
   const float* yw = I.r + I.m_pad;
+  float sq = 0.f;
   for (int i = threadIdx.x; i < I.m; i += 256) {
     float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
     int l = 0;
@@ -1820,7 +1827,15 @@ __global__ __launch_bounds__(256) void shared_resid_kernel(const Inst* __restric
       a3 = fmaf(Vec<TA>::one(A + (long long)jsh[l + 3] * lda + i), ssh[l + 3], a3);
     }
     for (; l < t1; ++l) a0 = fmaf(Vec<TA>::one(A + (long long)jsh[l] * lda + i), ssh[l], a0);
-    I.r[i] = yw[i] - ((a0 + a1) + (a2 + a3));
+    const float u = (a0 + a1) + (a2 + a3);
+    if (MODE == 0)
+      I.r[i] = yw[i] - u;
+    else
+      sq = fmaf(u, u, sq);
+  }
+  if (MODE == 1) {
+    const float tot = block_sum(sq, red);
+    for (int q = threadIdx.x; q < I.n_rowtiles; q += 256) I.qpart[q] = (q == 0) ? tot : 0.f;
   }
 }
 
@@ -3213,13 +3228,22 @@ hipError_t launch_coef_reg(const Inst* dc, int nact, int t, int T, float beta1, 
   return hipGetLastError();
 }
 
-hipError_t launch_shared_resid(int bf16, const Inst* d, int nsig, int t, hipStream_t s) {
+hipError_t launch_shared_rows(int bf16, int mode, const Inst* d, int nsig, int t1,
+                              hipStream_t s) {
   if (nsig <= 0) return nothing_to_launch(s);
-  if (t + 1 > 256) return hipErrorInvalidValue;
-  if (bf16)
-    CLOMP_LAUNCH(shared_resid_kernel<uint16_t>, dim3(nsig), dim3(256), 0, s, d, t);
-  else
-    CLOMP_LAUNCH(shared_resid_kernel<float>, dim3(nsig), dim3(256), 0, s, d, t);
+  if (t1 > 256) return hipErrorInvalidValue;
+  const dim3 g(nsig), b(256);
+  if (bf16) {
+    if (mode == 0)
+      CLOMP_LAUNCH((shared_rows_kernel<uint16_t, 0>), g, b, 0, s, d, t1);
+    else
+      CLOMP_LAUNCH((shared_rows_kernel<uint16_t, 1>), g, b, 0, s, d, t1);
+  } else {
+    if (mode == 0)
+      CLOMP_LAUNCH((shared_rows_kernel<float, 0>), g, b, 0, s, d, t1);
+    else
+      CLOMP_LAUNCH((shared_rows_kernel<float, 1>), g, b, 0, s, d, t1);
+  }
   return hipGetLastError();
 }
 
