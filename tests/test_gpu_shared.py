@@ -215,3 +215,40 @@ def test_shared_gradient_iht_and_paper_mode(method):
         ident += 1
     print(f"{method} shared gradient: identical {ident}/{total}")
     assert ident >= total // 3
+
+
+@pytest.mark.parametrize("method", ["clomp", "omp"])
+def test_shared_gram_bf16_with_master(method):
+    """BF16 bulk with an FP32 master on a shared dictionary (n=512, m=128, 64
+    signals of 10 Gaussian non-zeros): the full Gram matrix, c0 and the A^T R
+    scan contract the BF16 values (FP32 accumulation), the refinement uses the
+    master.  Against the oracle run on the BF16 values (selection) and the
+    master (refinement); the BF16 separation criterion holds for about two
+    thirds of such signals."""
+    from tests.gpu_helpers import BF16_DELTA, BF16_U
+    g = np.random.default_rng(2024)
+    n, m, k, a = 512, 128, 10, 64
+    A32 = (g.standard_normal((m, n)) / np.sqrt(m)).astype(np.float32)
+    At = np.ascontiguousarray(A32.T)
+    A = A32.astype(np.float64)
+    Abf = torch.from_numpy(A32).to(torch.bfloat16).to(torch.float64).numpy()
+    ys = []
+    for _ in range(a):
+        x = np.zeros(n)
+        x[g.choice(n, k, replace=False)] = g.standard_normal(k)
+        ys.append((A @ x).astype(np.float32))
+    At32 = dev(At)
+    Atb = At32.to(torch.bfloat16)
+    sol = C.Solver(0, method=method, flags=ITER)
+    out = sol.solve_batch([dict(At=Atb, At_master=At32, m=m, y=dev(y), k=k) for y in ys])
+    torch.cuda.synchronize()
+    assert (out.status.cpu().numpy() == 0).all()
+    kinds = []
+    for c in range(0, a, 4):
+        y = ys[c].astype(np.float64)
+        res = oracle_final_x(method, Abf, y, k, A_refine=A)
+        kinds.append(compare(out, c, res, A, y, delta=BF16_DELTA, u=BF16_U, method=method,
+                             A_sel=Abf, k=k, tol_x=1e-3))
+    print(f"{method} bf16 shared: identical {kinds.count('identical')}/{len(kinds)}")
+    assert kinds.count("identical") >= len(kinds) // 3
+    sol.close()
