@@ -128,29 +128,59 @@ enum : unsigned {
   ST_WATCHDOG = 32u
 };
 
+// ---- global-memory views of device pointers ---------------------------------
+// Pointers read from the descriptors are generic, so loads through them become
+// flat loads, which also count against the LDS wait counter: a wait for an LDS
+// read then drains every memory load in flight.  Loads through these views are
+// global loads, waited for on their own counter.
+typedef float gvf4 __attribute__((ext_vector_type(4)));
+typedef unsigned gvu2 __attribute__((ext_vector_type(2)));
+typedef unsigned gvu4 __attribute__((ext_vector_type(4)));
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) const T* gmem(const T* p) {
+  return (__attribute__((address_space(1))) const T*)p;
+}
+// 16 bytes (p 16-byte aligned)
+template <typename T>
+__device__ __forceinline__ uint4 gload16(const T* p) {
+  const gvu4 q = *(__attribute__((address_space(1))) const gvu4*)gmem(p);
+  return make_uint4(q.x, q.y, q.z, q.w);
+}
+
+// four consecutive elements as float (p 16-byte aligned for float, 8 for bf16)
+__device__ __forceinline__ float4 gload4(const float* p) {
+  const gvf4 q = *(__attribute__((address_space(1))) const gvf4*)gmem(p);
+  return make_float4(q.x, q.y, q.z, q.w);
+}
+__device__ __forceinline__ float4 gload4(const uint16_t* p) {
+  const gvu2 q = *(__attribute__((address_space(1))) const gvu2*)gmem(p);
+  return make_float4(__uint_as_float(q.x << 16), __uint_as_float(q.x & 0xffff0000u),
+                     __uint_as_float(q.y << 16), __uint_as_float(q.y & 0xffff0000u));
+}
+
 // ---- vector loads of the bulk matrix: 16 bytes per lane per load ----------
 template <typename TA> struct Vec;
 
 template <> struct Vec<float> {
   static constexpr int W = 4;
   __device__ static inline void load(const float* p, float v[4]) {
-    const float4 q = *reinterpret_cast<const float4*>(p);
+    const gvf4 q = *(__attribute__((address_space(1))) const gvf4*)gmem(p);
     v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
   }
-  __device__ static inline float one(const float* p) { return *p; }
+  __device__ static inline float one(const float* p) { return *gmem(p); }
 };
 
 template <> struct Vec<uint16_t> {   // bfloat16 bit patterns
   static constexpr int W = 8;
   __device__ static inline void load(const uint16_t* p, float v[8]) {
-    const uint4 q = *reinterpret_cast<const uint4*>(p);
+    const uint4 q = gload16(p);
     v[0] = __uint_as_float(q.x << 16); v[1] = __uint_as_float(q.x & 0xffff0000u);
     v[2] = __uint_as_float(q.y << 16); v[3] = __uint_as_float(q.y & 0xffff0000u);
     v[4] = __uint_as_float(q.z << 16); v[5] = __uint_as_float(q.z & 0xffff0000u);
     v[6] = __uint_as_float(q.w << 16); v[7] = __uint_as_float(q.w & 0xffff0000u);
   }
   __device__ static inline float one(const uint16_t* p) {
-    return __uint_as_float(((unsigned)*p) << 16);
+    return __uint_as_float(((unsigned)*gmem(p)) << 16);
   }
 };
 

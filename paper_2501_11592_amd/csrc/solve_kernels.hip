@@ -1643,18 +1643,12 @@ __global__ __launch_bounds__(256) void shared_mfma_kernel(const Inst* __restrict
   __shared__ __align__(16) float As[2][kMfmaK][kMfmaLd];
   __shared__ __align__(16) float Bs[2][kMfmaK][kMfmaLd];
   __shared__ unsigned long long kbest[2][kMfmaTile];
-  __shared__ const float* bsrc[kMfmaTile];   // MODE 1/2: the columns' y or r
   const Inst& I0 = insts[0];
   const TA* A = reinterpret_cast<const TA*>(I0.A);
   const long long lda = I0.lda, ldh = I0.ldh;
   const int n = I0.n, m = I0.m, m_pad = I0.m_pad;   // shared by every signal
   const int ncols = (MODE == 0) ? n : nsig;
   const int i0 = blockIdx.x * kMfmaTile, q0 = blockIdx.y * kMfmaTile;
-  if (MODE != 0 && threadIdx.x < kMfmaTile) {
-    const int q = q0 + threadIdx.x;
-    bsrc[threadIdx.x] = (q < ncols) ? insts[q].r + (MODE == 1 ? m_pad : 0) : nullptr;
-  }
-  __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w >> 1, wc = w & 1;          // the wave's 64-row / 64-column half
   mfma_f4 acc[4][4];
@@ -1662,56 +1656,59 @@ __global__ __launch_bounds__(256) void shared_mfma_kernel(const Inst* __restrict
   for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mfma_f4{0.f, 0.f, 0.f, 0.f};
-  // four consecutive k of row r (zero at or beyond m and outside the matrix)
-  auto load_a = [&](int row, int k, float v[4]) {
-    if (row < n && k + 3 < m && sizeof(TA) == 4) {
-      const float4 q = *reinterpret_cast<const float4*>(A + (long long)row * lda + k);
-      v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-    } else {
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        v[e] = (row < n && k + e < m) ? Vec<TA>::one(A + (long long)row * lda + k + e) : 0.f;
-    }
-  };
-  // each thread stages groups g = tid + 256 u (u < 4): row g / 8, k offset 4 (g % 8)
+  // each thread stages rows rb + 32 u (u < 4) of both operands at k offset kq
+  // of every chunk; the row and column pointers are fixed for the launch, and
+  // rows or columns outside the matrix read a valid one and are zeroed
   constexpr int kGroups = kMfmaTile * (kMfmaK / 4) / 256;
-  float av[kGroups][4], bv[kGroups][4];
+  const int rb = threadIdx.x / (kMfmaK / 4), kq = (threadIdx.x % (kMfmaK / 4)) * 4;
+  const TA* arow[kGroups];
+  const TA* brow[kGroups];      // MODE 0: atoms
+  const float* bsig[kGroups];   // MODE 1-3: y (MODE 1) or r of the column's signal
+  bool aok[kGroups], bok[kGroups];
+#pragma unroll
+  for (int u = 0; u < kGroups; ++u) {
+    const int i = i0 + rb + 32 * u, q = q0 + rb + 32 * u;
+    aok[u] = i < n;
+    bok[u] = q < ncols;
+    arow[u] = A + (long long)(aok[u] ? i : i0) * lda;
+    if (MODE == 0) brow[u] = A + (long long)(bok[u] ? q : q0) * lda;
+    else bsig[u] = insts[bok[u] ? q : q0].r + (MODE == 1 ? m_pad : 0);
+  }
+  // four consecutive k of each staged row, loaded raw (A below m only: lda >= m,
+  // both multiples of 4, so the load stays in the row; y and r below m_pad,
+  // zero padded) and masked only when staged, so that nothing waits for the
+  // loads before the products of the current chunk
+  const int kbend = (MODE == 0) ? m : m_pad;
+  float4 av[kGroups], bv[kGroups];
   auto fetch = [&](int k0) {
+    const int k = k0 + kq;
+    const int ksa = k < m ? k : 0, ksb = k < kbend ? k : 0;
 #pragma unroll
     for (int u = 0; u < kGroups; ++u) {
-      const int g = threadIdx.x + 256 * u;
-      const int r = g / (kMfmaK / 4), kq = (g % (kMfmaK / 4)) * 4;
-      const int k = k0 + kq;
-      load_a(i0 + r, k, av[u]);
-      const int q = q0 + r;
-      if (MODE == 0) {
-        load_a(q, k, bv[u]);
-      } else if (q < ncols) {
-        // y and r are zero padded to m_pad (a multiple of 8)
-        const float* src = bsrc[r];   // (MODE 3 reads r like MODE 2)
-        if (k < m_pad) {
-          const float4 v4 = *reinterpret_cast<const float4*>(src + k);
-          bv[u][0] = v4.x; bv[u][1] = v4.y; bv[u][2] = v4.z; bv[u][3] = v4.w;
-        } else {
-          bv[u][0] = bv[u][1] = bv[u][2] = bv[u][3] = 0.f;
-        }
-      } else {
-        bv[u][0] = bv[u][1] = bv[u][2] = bv[u][3] = 0.f;
-      }
+      av[u] = gload4(arow[u] + ksa);
+      bv[u] = (MODE == 0) ? gload4(brow[u] + ksb) : gload4(bsig[u] + ksb);
     }
   };
   fetch(0);
   int buf = 0;
   for (int k0 = 0; k0 < m; k0 += kMfmaK) {
+    const int k = k0 + kq;
+    // element e of a staged A row (or atom) is used while k + e < m; y and r
+    // rows whole below m_pad
+    const bool a0 = k < m, a1 = k + 1 < m, a2 = k + 2 < m, a3 = k + 3 < m;
+    const bool kb = k < kbend;
 #pragma unroll
     for (int u = 0; u < kGroups; ++u) {
-      const int g = threadIdx.x + 256 * u;
-      const int r = g / (kMfmaK / 4), kq = (g % (kMfmaK / 4)) * 4;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        As[buf][kq + e][r] = av[u][e];
-        Bs[buf][kq + e][r] = bv[u][e];
-      }
+      const int r = rb + 32 * u;
+      const bool ua = aok[u], ub = bok[u] && kb;
+      As[buf][kq + 0][r] = (ua && a0) ? av[u].x : 0.f;
+      As[buf][kq + 1][r] = (ua && a1) ? av[u].y : 0.f;
+      As[buf][kq + 2][r] = (ua && a2) ? av[u].z : 0.f;
+      As[buf][kq + 3][r] = (ua && a3) ? av[u].w : 0.f;
+      Bs[buf][kq + 0][r] = ub ? bv[u].x : 0.f;
+      Bs[buf][kq + 1][r] = (ub && (MODE != 0 || a1)) ? bv[u].y : 0.f;
+      Bs[buf][kq + 2][r] = (ub && (MODE != 0 || a2)) ? bv[u].z : 0.f;
+      Bs[buf][kq + 3][r] = (ub && (MODE != 0 || a3)) ? bv[u].w : 0.f;
     }
     __syncthreads();
     if (k0 + kMfmaK < m) fetch(k0 + kMfmaK);   // in flight during the products
@@ -1741,13 +1738,18 @@ __global__ __launch_bounds__(256) void shared_mfma_kernel(const Inst* __restrict
       const int q = qb + 16 * bj;
       unsigned long long best = 0ull;
       if (q < ncols) {
+        // the wave's 64 rows start at a multiple of 64: two bitmap words
         const unsigned* bm = insts[q].bitmap;
+        const int wbase = i0 + 64 * wr;
+        const unsigned bw0 = wbase < n ? gmem(bm)[wbase >> 5] : ~0u;
+        const unsigned bw1 = wbase + 32 < n ? gmem(bm)[(wbase >> 5) + 1] : ~0u;
 #pragma unroll
         for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int i = ib + 16 * bi + v;
-            if (i < n && !((bm[i >> 5] >> (i & 31)) & 1u)) {
+            const unsigned word = (16 * bi + 4 * (lane >> 4) + v) < 32 ? bw0 : bw1;
+            if (i < n && !((word >> (i & 31)) & 1u)) {
               const unsigned long long kk = pack_key(acc[bi][bj][v], i);
               best = kk > best ? kk : best;
             }
@@ -2189,7 +2191,7 @@ __device__ void pass_tile_body(const Inst& I, const ScanTile& tile, int t, float
     const TA* colj = A + (long long)jt * lda;
     for (int c = threadIdx.x; c < nvec; c += NT) {
       if constexpr (BF) {
-        uint4 q = *reinterpret_cast<const uint4*>(colj + (long long)c * VW);
+        uint4 q = gload16(colj + (long long)c * VW);
         vsh4[c] = (c == nvec - 1) ? mask_bf16_tail(q, tail) : q;
       } else {
         float a[VW];
@@ -2213,7 +2215,7 @@ __device__ void pass_tile_body(const Inst& I, const ScanTile& tile, int t, float
 #pragma unroll UNR
     for (int c = gl; c < nvec; c += LPA) {
       if constexpr (BF) {
-        uint4 q = *reinterpret_cast<const uint4*>(col + (long long)c * VW);
+        uint4 q = gload16(col + (long long)c * VW);
         if (c == nvec - 1) q = mask_bf16_tail(q, tail);
         const uint4 u = vsh4[c];
         acc = dot2_bf16(q.x, u.x, acc);
