@@ -627,10 +627,15 @@ constexpr int kRegRows = 256;
 
 // RPL rows per lane (1, 2 or 4; rows RPL*l .. RPL*l+RPL-1 of lane l): a
 // support of t+1 <= 64*RPL atoms; fewer rows per lane keep the tile of G
-// within the registers of a full-occupancy wave.
+// within the registers of a full-occupancy wave.  `part` (LDS) holds two
+// buffers of 16 wave slots of 64*RPL floats: adam_part_floats<RPL>().
+template <int RPL>
+constexpr int adam_part_floats() { return 2 * 16 * 64 * RPL; }
+
 template <int RPL = 4>
 __device__ void adam_reg_body(const Inst& I, int t, int T, float beta1, float beta2,
-                              float4 (*part)[16][64], int nw, bool clear_key = true) {
+                              float* part, int nw, bool clear_key = true) {
+  constexpr int kSlot = 64 * RPL, kBuf = 16 * kSlot;
   if (I.st->done) {
     if (threadIdx.x == 0) *I.key = 0ull;
     return;
@@ -678,8 +683,11 @@ __device__ void adam_reg_body(const Inst& I, int t, int T, float beta1, float be
   // slots of waves beyond nw stay zero so every row reads 16 partials
   // unconditionally (independent LDS loads, no branches)
   for (int q = nw + w; q < 16; q += nw) {
-    part[0][q][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
-    part[1][q][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      part[q * kSlot + RPL * lane + i] = 0.f;
+      part[kBuf + q * kSlot + RPL * lane + i] = 0.f;
+    }
   }
   for (int it = 0; it < T; ++it) {
     const int buf = it & 1;
@@ -709,20 +717,21 @@ __device__ void adam_reg_body(const Inst& I, int t, int T, float beta1, float be
       float rs[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) rs[i] = (acc[i][0] + acc[i][1]) + (acc[i][2] + acc[i][3]);
-      part[buf][w][lane] = make_float4(rs[0], rs[1], rs[2], rs[3]);
+      *reinterpret_cast<float4*>(part + buf * kBuf + w * kSlot + 4 * lane) =
+          make_float4(rs[0], rs[1], rs[2], rs[3]);
     } else {
-      float* pw = reinterpret_cast<float*>(&part[buf][w][0]) + RPL * lane;
+      float* pw = part + buf * kBuf + w * kSlot + RPL * lane;
 #pragma unroll
       for (int i = 0; i < RPL; ++i) pw[i] = (acc[i][0] + acc[i][1]) + (acc[i][2] + acc[i][3]);
     }
     __syncthreads();
     if (own) {
-      // partials of row R: element (R & 3) of part[buf][w'][R >> 2], w' = 0..15,
-      // added as a balanced tree in a fixed order
-      const float* pf = reinterpret_cast<const float*>(&part[buf][0][0]) + R;
+      // partials of row R: float R of the 16 wave slots, added as a balanced
+      // tree in a fixed order
+      const float* pf = part + buf * kBuf + R;
       float p[16];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) p[q] = pf[q * 256];
+      for (int q = 0; q < 16; ++q) p[q] = pf[q * kSlot];
 #pragma unroll
       for (int h = 8; h > 0; h >>= 1)
 #pragma unroll
@@ -749,7 +758,7 @@ __device__ void adam_reg_body(const Inst& I, int t, int T, float beta1, float be
 
 __global__ __launch_bounds__(1024) void adam_reg_kernel(const Inst* __restrict__ insts, int t,
                                                         int T, float beta1, float beta2) {
-  __shared__ float4 part[2][16][64];   // [buffer][wave][lane] -> rows 4l..4l+3
+  __shared__ __align__(16) float part[adam_part_floats<4>()];
   // the launch uses ceil((t+1)/16) waves: every wave owns live columns
   adam_reg_body(insts[blockIdx.x], t, T, beta1, beta2, part, blockDim.x >> 6);
 }
@@ -2545,7 +2554,7 @@ __global__ __launch_bounds__(kPassThreads) void coef_pass_kernel(
     const ScanTile* __restrict__ tiles, int t, int T, float beta1, float beta2, float lr_rel,
     float eps_rel) {
   extern __shared__ __align__(16) float dsh[];
-  __shared__ float4 part[2][16][64];
+  __shared__ __align__(16) float part[adam_part_floats<4>()];
   __shared__ float red[kPassThreads / 64], red2[kPassThreads / 64];
   __shared__ unsigned long long wbest[kPassThreads / 64];
   if ((int)blockIdx.x < nact * W) {
@@ -2694,10 +2703,11 @@ __global__ __launch_bounds__(kCscanThreads) void cscan_kernel(const Inst* __rest
 // signals share a CU; RPL rows of G per lane for supports up to 64*RPL.  The
 // selection record, then the register-tile Adam.
 template <int RPL>
-__global__ __launch_bounds__(1024) void coef_reg_kernel(const Inst* __restrict__ insts_c, int t,
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(RPL == 2 ? 6 : 1)))
+void coef_reg_kernel(const Inst* __restrict__ insts_c, int t,
                                                         int T, float beta1, float beta2,
                                                         float lr_rel, float eps_rel) {
-  __shared__ float4 part[2][16][64];
+  __shared__ __align__(16) float part[adam_part_floats<RPL>()];
   const Inst& I = insts_c[blockIdx.x];
   if (I.st->done) return;
   const unsigned long long key = I.key[t & 1];
