@@ -1804,9 +1804,10 @@ __global__ __launch_bounds__(256) void shared_mfma_kernel(const Inst* __restrict
 
 // Products over one signal's support, one 256-thread workgroup per signal
 // (t1 <= 256 atoms: the given count, or the signal's own when 0), the support
-// and coefficients staged in LDS, each thread's rows summed over four
-// independent chains (the shared A is cache resident; one workgroup per
-// signal keeps the launch small).  MODE 0: r = y - A_S s;  MODE 1: the IHT
+// and coefficients staged in LDS, each lane's four consecutive rows read with
+// one vector load per support column and summed over four independent chains
+// (the shared A is cache resident; one workgroup per signal keeps the launch
+// small).  MODE 0: r = y - A_S s;  MODE 1: the IHT
 // step denominator ||A_S g_S||^2 (g from gbuf) as the signal's row partials
 // (the total in the first, zeros in the others).
 template <typename TA, int MODE>
@@ -1826,23 +1827,46 @@ __global__ __launch_bounds__(256) void shared_rows_kernel(const Inst* __restrict
   __syncthreads();
   const TA* A = reinterpret_cast<const TA*>(I.A);
   const long long lda = I.lda;
+  const int m = I.m;
+  // lane v takes rows 4v..4v+3 with one vector load per support column (the
+  // rows of A are padded to lda, a multiple of 4, and r, y to m_pad, a
+  // multiple of 8); each row keeps four chains over l mod 4
+  const int ng = (m + 3) >> 2;
   const float* yw = I.r + I.m_pad;
   float sq = 0.f;
-  for (int i = threadIdx.x; i < I.m; i += 256) {
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+  auto fma4 = [](float4 x, float c, float4 a) {
+    return make_float4(fmaf(x.x, c, a.x), fmaf(x.y, c, a.y), fmaf(x.z, c, a.z),
+                       fmaf(x.w, c, a.w));
+  };
+  for (int v = threadIdx.x; v < ng; v += 256) {
+    const int i = 4 * v;
+    float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0, a2 = a0, a3 = a0;
     int l = 0;
+#pragma unroll 2
     for (; l + 3 < t1; l += 4) {
-      a0 = fmaf(Vec<TA>::one(A + (long long)jsh[l] * lda + i), ssh[l], a0);
-      a1 = fmaf(Vec<TA>::one(A + (long long)jsh[l + 1] * lda + i), ssh[l + 1], a1);
-      a2 = fmaf(Vec<TA>::one(A + (long long)jsh[l + 2] * lda + i), ssh[l + 2], a2);
-      a3 = fmaf(Vec<TA>::one(A + (long long)jsh[l + 3] * lda + i), ssh[l + 3], a3);
+      const float4 x0 = gload4(A + (long long)jsh[l] * lda + i);
+      const float4 x1 = gload4(A + (long long)jsh[l + 1] * lda + i);
+      const float4 x2 = gload4(A + (long long)jsh[l + 2] * lda + i);
+      const float4 x3 = gload4(A + (long long)jsh[l + 3] * lda + i);
+      a0 = fma4(x0, ssh[l], a0);
+      a1 = fma4(x1, ssh[l + 1], a1);
+      a2 = fma4(x2, ssh[l + 2], a2);
+      a3 = fma4(x3, ssh[l + 3], a3);
     }
-    for (; l < t1; ++l) a0 = fmaf(Vec<TA>::one(A + (long long)jsh[l] * lda + i), ssh[l], a0);
-    const float u = (a0 + a1) + (a2 + a3);
-    if (MODE == 0)
-      I.r[i] = yw[i] - u;
-    else
-      sq = fmaf(u, u, sq);
+    for (; l < t1; ++l) a0 = fma4(gload4(A + (long long)jsh[l] * lda + i), ssh[l], a0);
+    const float u[4] = {(a0.x + a1.x) + (a2.x + a3.x), (a0.y + a1.y) + (a2.y + a3.y),
+                        (a0.z + a1.z) + (a2.z + a3.z), (a0.w + a1.w) + (a2.w + a3.w)};
+    if (MODE == 0) {
+      // rows at or beyond m stay zero
+      const float4 y4 = gload4(yw + i);
+      *reinterpret_cast<float4*>(I.r + i) =
+          make_float4(y4.x - u[0], i + 1 < m ? y4.y - u[1] : 0.f,
+                      i + 2 < m ? y4.z - u[2] : 0.f, i + 3 < m ? y4.w - u[3] : 0.f);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (i + e < m) sq = fmaf(u[e], u[e], sq);
+    }
   }
   if (MODE == 1) {
     const float tot = block_sum(sq, red);
