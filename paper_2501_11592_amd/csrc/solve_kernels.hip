@@ -1780,24 +1780,25 @@ __global__ __launch_bounds__(256) void shared_mfma_kernel(const Inst* __restrict
     }
     return;
   }
+  // the lane's four atoms i..i+3 of a block are consecutive: one 16-byte
+  // store per block (columns hold ldh >= 128 ceil(n / 128) entries, and atoms
+  // at or beyond n were staged as zero rows, so their entries are zero)
 #pragma unroll
   for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 4; ++bj) {
       const int q = qb + 16 * bj;
       if (q >= ncols) continue;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = ib + 16 * bi + v;
-        if (i >= n) continue;
-        if (MODE == 0) {
-          Gf[i + (long long)q * ldh] = acc[bi][bj][v];
-        } else if (MODE == 1) {
-          insts[q].c0[i] = acc[bi][bj][v];
-        } else {
-          insts[q].gbuf[i] = acc[bi][bj][v];
-          if (t) insts[q].c0[i] = acc[bi][bj][v];
-        }
+      const int i = ib + 16 * bi;
+      const float4 v4 = make_float4(acc[bi][bj][0], acc[bi][bj][1], acc[bi][bj][2],
+                                    acc[bi][bj][3]);
+      if (MODE == 0) {
+        *reinterpret_cast<float4*>(Gf + i + (long long)q * ldh) = v4;
+      } else if (MODE == 1) {
+        *reinterpret_cast<float4*>(insts[q].c0 + i) = v4;
+      } else {
+        *reinterpret_cast<float4*>(insts[q].gbuf + i) = v4;
+        if (t) *reinterpret_cast<float4*>(insts[q].c0 + i) = v4;
       }
     }
 }
