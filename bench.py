@@ -222,7 +222,9 @@ def roofline(p, items=None, method="clomp"):
         fl = 2.0 * n * m * len(items)
         k_ms = ms / nl
         ach = fl / (k_ms * 1e-3) / 1e12
-        return {"kernel": "shared_mfma_kernel (C = A^T R over the batch, argmax epilogue)",
+        what = ("C = A^T R over the batch, argmax epilogue" if method in ("clomp", "omp")
+                else "gradient G = A^T R over the batch")
+        return {"kernel": f"shared_mfma_kernel ({what})",
                 "bound": "mfma", "achieved": ach, "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": ach / MFMA_FP32_PEAK_TFLOPS, "traffic": None,
                 "avg_launch_us": 1e3 * k_ms, "flops_per_launch": fl, "launches": nl}
@@ -237,7 +239,8 @@ def roofline(p, items=None, method="clomp"):
                        else 6.0 * t * t)
         k_ms = ms / nl
         ach = fl / nl / (k_ms * 1e-3) / 1e12
-        return {"kernel": "coef_pass_kernel (coefficient workgroups only: shared dictionary)",
+        return {"kernel": ("coef_reg_kernel" if method == "clomp" else "coef_omp_kernel")
+                + " (support-sized coefficient workgroups: shared dictionary)",
                 "bound": "alu", "achieved": ach, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": ach / VALU_PEAK_TFLOPS, "traffic": None, "avg_launch_us": 1e3 * k_ms,
                 "flops_per_launch": fl / nl, "launches": nl}
