@@ -50,7 +50,8 @@ struct InstState {
   float gamma[2];  // CGLS ||A_S^T r||^2, ping-pong by iteration parity
   float gamma0;
   int stop;        // 1: the paper-mode loop ended early (max |c| = 0 or non-finite)
-  int pad[6];
+  unsigned sel_bits;   // IHT: magnitude bits of the last top-K threshold (a search hint)
+  int pad[5];
 };
 
 struct Inst {

@@ -1295,12 +1295,18 @@ __device__ inline unsigned block_excl_scan(unsigned v, unsigned* wsum, unsigned&
 // floats order like their bits and NaN ranks above +Inf.
 __device__ inline unsigned mag_bits(float z) { return __float_as_uint(z) & 0x7fffffffu; }
 
+// Threshold bits taken from the previous iteration when they still bracket
+// the K-th magnitude (bits 30..20: exponent and the top three mantissa bits)
+constexpr int kSelWarmBit = 20;
+
 // Top-K by magnitude of one signal per workgroup (ties to the lowest index).
 // Thread q owns the contiguous index chunk [q*CH, q*CH + CH) with its values
 // in registers (CH > 0; NT*CH >= n), or walks [q*C, q*C + C) in memory (CH =
 // 0).  The K-th largest magnitude Tv is built from the top bit down: Tv is
 // the largest key with #{|z| >= Tv} >= K (16 counting passes of one or two
-// bits, counts by wave ballots, one barrier each).  Every larger magnitude is taken, and the first K - #{|z| > Tv}
+// bits, counts by wave ballots, one barrier each; from the previous
+// iteration's threshold bits, when they still bracket it, one check pass and
+// ten).  Every larger magnitude is taken, and the first K - #{|z| > Tv}
 // equal ones in index order.  mode 0: z = g (support of the first
 // iteration); mode 1: the normalised step t and z = s + t g, then s = z on
 // the support; mode 2: as mode 1, then b = (A^T y)_S for the refinement
@@ -1421,8 +1427,37 @@ __global__ __launch_bounds__(NT) void iht_select_kernel(const Inst* __restrict__
     par ^= 1;   // the next pass writes the other buffer
     Tv |= dsel << b;
   };
-  resolve(30, 1);
-  for (int b = 28; b >= 0; b -= 2) resolve(b, 2);
+  // warm start: the bits of the threshold above kSelWarmBit are those of the
+  // previous threshold when at least K magnitudes reach that prefix and fewer
+  // than K reach the next one (the invariant the passes keep for every
+  // prefix); otherwise every bit is resolved.  Tv is the same either way.
+  bool warm = false;
+  const unsigned lo = I.st->sel_bits & ~((1u << kSelWarmBit) - 1u);
+  if (lo != 0u) {   // candidates must be >= 1 (absent entries hold 0)
+    const unsigned c0 = wcount(lo), c1 = wcount(lo + (1u << kSelWarmBit));
+    if ((tid & 63) == 0) {
+      ured[par][0][tid >> 6] = c0;
+      ured[par][1][tid >> 6] = c1;
+    }
+    __syncthreads();
+    unsigned t0 = 0u, t1 = 0u;
+#pragma unroll
+    for (int q = 0; q < NT / 64; ++q) {
+      t0 += ured[par][0][q];
+      t1 += ured[par][1][q];
+    }
+    par ^= 1;
+    if (t0 >= (unsigned)K && t1 < (unsigned)K) {
+      Tv = lo;
+      warm = true;
+    }
+  }
+  if (!warm) {
+    resolve(30, 1);
+    for (int b = 28; b >= kSelWarmBit; b -= 2) resolve(b, 2);
+  }
+  for (int b = kSelWarmBit - 2; b >= 0; b -= 2) resolve(b, 2);
+  if (tid == 0) I.st->sel_bits = Tv;
   // number of magnitudes above Tv
   unsigned ngt_all = 0u;
   if (Tv != 0x7fffffffu) {
