@@ -252,3 +252,51 @@ def test_shared_gram_bf16_with_master(method):
     print(f"{method} bf16 shared: identical {kinds.count('identical')}/{len(kinds)}")
     assert kinds.count("identical") >= len(kinds) // 3
     sol.close()
+
+
+@pytest.mark.parametrize("method", ["clomp", "omp", "iht"])
+def test_shared_ragged_tiles_nan_padding(method):
+    """Ragged contraction tiles on both sides (n = 300 atoms, 200 columns:
+    neither a multiple of 128) with m = 77 (a partial group of four k) and
+    NaN in every lda padding entry: every mode of the shared contraction
+    (A^T A, A^T Y, the scan or the IHT gradient) must mask the padding and the
+    rows and columns past the matrix.  No NaN status; supports and x against
+    the oracle where well separated and against the per-signal schedule."""
+    from oracle import iht_fp64, well_separated
+    from tests.gpu_helpers import rel_err
+    b = W.image_batch(0.3, n=300, a=200, k=24, lda=96)
+    b.At = b.At.copy()
+    b.At[:, b.m:] = np.nan   # b.A reads the first m entries of each row only
+    R = 20
+    flags = ITER if method != "iht" else 0
+    kw = {} if method != "iht" else dict(inner_steps=R)
+    out = _solve(method, b, flags, **kw)
+    per = _solve(method, b, flags | C.FLAG_NO_SHARED_GRAM, **kw)
+    st = out.status.cpu().numpy()
+    assert not (st & C.ST_NAN).any()
+    assert all(int(out.n_selected[c]) == b.k for c in range(200))
+    ident = total = 0
+    for c in range(0, 200, 7):
+        y = b.Y[c].astype(np.float64)
+        if method == "iht":
+            from types import SimpleNamespace
+            ref = iht_fp64(b.A, y, b.k, max_iters=R)
+            ok, _ = well_separated(b.A, y, b.k, method="iht", params=SimpleNamespace(max_iters=R),
+                                   delta=FP32_DELTA, u=FP32_U, base=ref)
+            total += 1
+            if not ok:
+                continue
+            supp = out.support[c][:int(out.n_selected[c])].tolist()
+            assert supp == ref.support, (c, supp, ref.support)
+            assert rel_err(out.x[c].cpu().numpy().astype(np.float64), ref.x) <= 1e-5, c
+            kind = "identical"
+        else:
+            res = oracle_final_x(method, b.A, b.Y[c], b.k)
+            kind = compare(out, c, res, b.A, b.Y[c], delta=FP32_DELTA, u=FP32_U, method=method,
+                           A_sel=b.A, k=b.k, tol_x=1e-5)
+            total += 1
+        if kind == "identical":
+            ident += 1
+            assert out.support[c].tolist() == per.support[c].tolist(), c
+    print(f"{method} ragged shared tiles: identical {ident}/{total}")
+    assert ident >= total // 3
