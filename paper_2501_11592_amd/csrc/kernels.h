@@ -46,8 +46,9 @@ hipError_t launch_iht_grad(int bf16, int lpa, const Inst* d, const ScanTile* til
                            int nslice, int r_lds, int first, hipStream_t s);
 hipError_t launch_iht_combine(const Inst* d, const ScanTile* tiles, int ntiles, int first,
                               hipStream_t s);
+// wide: 16 waves per row tile instead of 4 (classes with fewer row tiles than CUs).
 hipError_t launch_iht_rows(int bf16, int mode, const Inst* d, const RowTile* tiles, int ntiles,
-                           int kmax, hipStream_t s);
+                           int kmax, int wide, hipStream_t s);
 // nmax: the largest n among the signals (picks threads and chunk size).
 hipError_t launch_iht_select(const Inst* dc, int nact, int mode, int nmax, hipStream_t s);
 

@@ -816,7 +816,8 @@ clomp_status_t launch_iht(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st)
         if (srows)
           HIP_TRY(launch_shared_rows(bf16, 0, d_insts + c.i0, nall, 0, st), "iht resid");
         else
-          HIP_TRY(launch_iht_rows(bf16, 0, d_insts, d_rows + c.row_off, nrows, c.kmax, st),
+          HIP_TRY(launch_iht_rows(bf16, 0, d_insts, d_rows + c.row_off, nrows, c.kmax,
+                                  nrows < h->num_cu, st),
                   "iht resid");
       }
       {
@@ -847,7 +848,8 @@ clomp_status_t launch_iht(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st)
         if (srows)
           HIP_TRY(launch_shared_rows(bf16, 1, d_insts + c.i0, nall, 0, st), "iht step");
         else
-          HIP_TRY(launch_iht_rows(bf16, 1, d_insts, d_rows + c.row_off, nrows, c.kmax, st),
+          HIP_TRY(launch_iht_rows(bf16, 1, d_insts, d_rows + c.row_off, nrows, c.kmax,
+                                  nrows < h->num_cu, st),
                   "iht step");
       }
       {
@@ -884,7 +886,8 @@ clomp_status_t launch_paper(clomp_ctx* h, const Plan& P, int bf16, hipStream_t s
         if (P.ishared && c.kmax <= 256)
           HIP_TRY(launch_shared_rows(bf16, 0, d_insts + c.i0, nall, 0, st), "paper resid");
         else
-          HIP_TRY(launch_iht_rows(bf16, 0, d_insts, d_rows + c.row_off, nrows, c.kmax, st),
+          HIP_TRY(launch_iht_rows(bf16, 0, d_insts, d_rows + c.row_off, nrows, c.kmax,
+                                  nrows < h->num_cu, st),
                   "paper resid");
       }
       {

@@ -876,11 +876,16 @@ enum RowMode : int {
   ROW_IHT_U = 4    // IHT: partial ||A_bulk[:, S] g_S||^2 (the normalised step)
 };
 
-template <typename TA, int MODE>
-__global__ __launch_bounds__(kBlock) void rows_kernel(const Inst* __restrict__ insts,
-                                                      const RowTile* __restrict__ tiles,
-                                                      int t, int it, float tol2) {
-  extern __shared__ __align__(16) float rsh[];  // coef[t1] | (int) sup[t1] | part[4*64]
+// NW waves split the columns (4; the IHT modes also 16, for classes with
+// fewer row tiles than CUs: fewer dependent load rounds per lane).
+template <typename TA, int MODE, int NW = kWaves>
+__global__ __launch_bounds__(64 * NW) void rows_kernel(const Inst* __restrict__ insts,
+                                                       const RowTile* __restrict__ tiles,
+                                                       int t, int it, float tol2) {
+  static_assert(NW == kWaves || MODE == ROW_IHT_R || MODE == ROW_IHT_U,
+                "the CGLS modes reduce over kWaves waves");
+  constexpr int NTH = 64 * NW;
+  extern __shared__ __align__(16) float rsh[];  // coef[t1] | (int) sup[t1] | part[NW*64]
   __shared__ float red[kWaves];
   const RowTile rt = tiles[blockIdx.x];
   const Inst& I = insts[rt.inst];
@@ -921,11 +926,11 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const Inst* __restrict__ i
     }
     if (rt.tile == 0 && threadIdx.x == 0) I.st->gamma[it & 1] = gamma;
   } else if (MODE == ROW_IHT_U) {
-    for (int l = threadIdx.x; l < t1; l += kBlock) coef[l] = I.gbuf[I.support[l]];
+    for (int l = threadIdx.x; l < t1; l += NTH) coef[l] = I.gbuf[I.support[l]];
   } else {
-    for (int l = threadIdx.x; l < t1; l += kBlock) coef[l] = src[l];
+    for (int l = threadIdx.x; l < t1; l += NTH) coef[l] = src[l];
   }
-  for (int l = threadIdx.x; l < t1; l += kBlock) sup[l] = I.support[l];
+  for (int l = threadIdx.x; l < t1; l += NTH) sup[l] = I.support[l];
   __syncthreads();
   const TA* A;
   long long lda;
@@ -941,20 +946,20 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const Inst* __restrict__ i
   const int i = rt.i0 + lane;
   float acc = 0.f;
   if (i < rt.i1) {
-    // columns l = w, w+4, ...: eight independent chains keep eight loads in
+    // columns l = w, w+NW, ...: eight independent chains keep eight loads in
     // flight per lane
     float a[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) a[u] = 0.f;
     int l = w;
-    for (; l + 7 * kWaves < t1; l += 8 * kWaves) {
+    for (; l + 7 * NW < t1; l += 8 * NW) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int ll = l + u * kWaves;
+        const int ll = l + u * NW;
         a[u] = fmaf(Vec<TA>::one(A + (long long)sup[ll] * lda + i), coef[ll], a[u]);
       }
     }
-    for (; l < t1; l += kWaves) a[0] = fmaf(Vec<TA>::one(A + (long long)sup[l] * lda + i), coef[l], a[0]);
+    for (; l < t1; l += NW) a[0] = fmaf(Vec<TA>::one(A + (long long)sup[l] * lda + i), coef[l], a[0]);
     acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   }
   part[w * 64 + lane] = acc;
@@ -962,7 +967,20 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const Inst* __restrict__ i
   if (w == 0) {
     float v = 0.f;
     if (i < rt.i1) {
-      const float sum = (part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]);
+      float sum;
+      if constexpr (NW == 4) {
+        sum = (part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]);
+      } else {
+        // the NW wave partials as a balanced tree in a fixed order
+        float pv[NW];
+#pragma unroll
+        for (int q = 0; q < NW; ++q) pv[q] = part[q * 64 + lane];
+#pragma unroll
+        for (int h = NW / 2; h > 0; h >>= 1)
+#pragma unroll
+          for (int q = 0; q < h; ++q) pv[q] = pv[q] + pv[q + h];
+        sum = pv[0];
+      }
       const float* yw = I.r + I.m_pad;
       if (MODE == ROW_RESID || MODE == ROW_IHT_R) {
         I.r[i] = yw[i] - sum;
@@ -3109,8 +3127,29 @@ hipError_t launch_iht_combine(const Inst* d, const ScanTile* tiles, int ntiles, 
 }
 
 hipError_t launch_iht_rows(int bf16, int mode, const Inst* d, const RowTile* tiles, int ntiles,
-                           int kmax, hipStream_t s) {
+                           int kmax, int wide, hipStream_t s) {
   if (ntiles <= 0) return nothing_to_launch(s);
+  if (wide) {
+    // 16 waves per row tile (few tiles: a single long signal or a small class)
+    const size_t lds = ((size_t)2 * (kmax + 1) + 16 * 64) * sizeof(float);
+    const dim3 b(16 * 64);
+    if (bf16) {
+      if (mode == 0)
+        CLOMP_LAUNCH((rows_kernel<uint16_t, ROW_IHT_R, 16>), dim3(ntiles), b, lds, s, d, tiles,
+                     kmax, 0, 0.f);
+      else
+        CLOMP_LAUNCH((rows_kernel<uint16_t, ROW_IHT_U, 16>), dim3(ntiles), b, lds, s, d, tiles,
+                     kmax, 0, 0.f);
+    } else {
+      if (mode == 0)
+        CLOMP_LAUNCH((rows_kernel<float, ROW_IHT_R, 16>), dim3(ntiles), b, lds, s, d, tiles,
+                     kmax, 0, 0.f);
+      else
+        CLOMP_LAUNCH((rows_kernel<float, ROW_IHT_U, 16>), dim3(ntiles), b, lds, s, d, tiles,
+                     kmax, 0, 0.f);
+    }
+    return hipGetLastError();
+  }
   const size_t lds = ((size_t)2 * (kmax + 1) + 4 * 64) * sizeof(float);
   if (bf16) {
     if (mode == 0)
