@@ -312,6 +312,12 @@ clomp_status_t clomp_profile_reset(clomp_handle_t h);
  *                  one contraction C = A^T R over the batch's residuals
  *                  (argmax fused); before it, c = c0 - Gf[:, S] s per signal
  *                  (default 1: always contract; a value >= k never)
+ *   shared_min_tiles  IHT and paper mode on a shared dictionary: the batch's
+ *                  gradient is one contraction A^T R only when that
+ *                  contraction has at least this many 128 x 128 output tiles
+ *                  (atoms x signals); smaller batches scan per signal, which
+ *                  keeps more of the device busy (default: half the compute
+ *                  units; 1 always contracts)
  * clomp_get_tuning returns the values in use for the last solve.
  * Errors: INVALID_ARGUMENT (NULL, negative or > 65536 values).
  */
@@ -320,7 +326,8 @@ typedef struct {
   int32_t pass_tile_kb;
   int32_t team_min_rows;
   int32_t rscan_min_t;
-  int32_t reserved[4];
+  int32_t shared_min_tiles;
+  int32_t reserved[3];
 } clomp_tuning_t;
 
 clomp_status_t clomp_set_tuning(clomp_handle_t h, const clomp_tuning_t* t /*host*/);

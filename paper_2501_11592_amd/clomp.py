@@ -69,7 +69,7 @@ class Profile(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("scan_tile_kb", ctypes.c_int32), ("pass_tile_kb", ctypes.c_int32),
                 ("team_min_rows", ctypes.c_int32), ("rscan_min_t", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("shared_min_tiles", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 @dataclass
@@ -215,10 +215,12 @@ class Solver:
         _check(self._h, load_library().clomp_set_params(self._h, ctypes.byref(self.params)),
                "clomp_set_params")
 
-    def set_tuning(self, scan_tile_kb=0, pass_tile_kb=0, team_min_rows=0, rscan_min_t=0):
+    def set_tuning(self, scan_tile_kb=0, pass_tile_kb=0, team_min_rows=0, rscan_min_t=0,
+                   shared_min_tiles=0):
         t = Tuning()
         t.scan_tile_kb, t.pass_tile_kb = scan_tile_kb, pass_tile_kb
         t.team_min_rows, t.rscan_min_t = team_min_rows, rscan_min_t
+        t.shared_min_tiles = shared_min_tiles
         _check(self._h, load_library().clomp_set_tuning(self._h, ctypes.byref(t)),
                "clomp_set_tuning")
 
@@ -227,7 +229,8 @@ class Solver:
         _check(self._h, load_library().clomp_get_tuning(self._h, ctypes.byref(t)),
                "clomp_get_tuning")
         return {"scan_tile_kb": t.scan_tile_kb, "pass_tile_kb": t.pass_tile_kb,
-                "team_min_rows": t.team_min_rows, "rscan_min_t": t.rscan_min_t}
+                "team_min_rows": t.team_min_rows, "rscan_min_t": t.rscan_min_t,
+                "shared_min_tiles": t.shared_min_tiles}
 
     def profile_reset(self):
         _check(self._h, load_library().clomp_profile_reset(self._h), "clomp_profile_reset")

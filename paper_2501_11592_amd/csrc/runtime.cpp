@@ -147,6 +147,8 @@ struct clomp_ctx {
   int pass_tile_kb = kPassTargetKB;
   int team_min_rows = 256;            // larger supports use coefficient teams
   int rscan_min_t = 1;                // shared dictionary: A^T R scan from this support size
+  int shared_min_tiles = 0;           // IHT / paper mode: contraction tiles needed for the
+                                      // shared gradient (0: half the compute units)
   int last_scan_kb = kScanTargetKB, last_pass_kb = kPassTargetKB;   // of the last solve
   std::map<std::string, int> tuned;   // autotuned tile size per size class
   PlanCache pcache;
@@ -319,7 +321,15 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
       sameA = a.A == b.A && a.lda == b.lda && a.n == b.n && a.m == b.m &&
               a.A_master == b.A_master && a.lda_master == b.lda_master;
     }
-    P.ishared = iht && sameA;
+    // IHT / paper mode: the batch's gradient as one contraction pays only when
+    // it has enough 128 x 128 output tiles to fill the device; a small batch
+    // (a 256 x 256 image: four tiles) scans per signal instead
+    if (iht && sameA) {
+      const long long tiles =
+          (long long)((inst[order[0]].n + 127) / 128) * ((P.nbig + 127) / 128);
+      const int need = h->shared_min_tiles > 0 ? h->shared_min_tiles : std::max(1, h->num_cu / 2);
+      P.ishared = tiles >= need;
+    }
     bool shared = sameA && !iht && !(fl & CLOMP_FLAG_RESIDUAL_FLOW);
     if (shared) {
       const size_t l = (size_t)round_up_int(inst[order[0]].n, 256);
@@ -1455,14 +1465,17 @@ clomp_status_t clomp_grad(clomp_handle_t h, int32_t n, int32_t m, int64_t lda, i
 clomp_status_t clomp_set_tuning(clomp_handle_t h, const clomp_tuning_t* t) {
   if (!h || !t) return CLOMP_INVALID_ARGUMENT;
   if (t->scan_tile_kb < 0 || t->scan_tile_kb > 65536 || t->pass_tile_kb < 0 ||
-      t->pass_tile_kb > 65536 || t->team_min_rows < 0 || t->rscan_min_t < 0)
+      t->pass_tile_kb > 65536 || t->team_min_rows < 0 || t->rscan_min_t < 0 ||
+      t->shared_min_tiles < 0)
     return fail(h, CLOMP_INVALID_ARGUMENT,
-                "tile sizes must lie in [0, 65536] KB; team_min_rows and rscan_min_t >= 0");
+                "tile sizes must lie in [0, 65536] KB; team_min_rows, rscan_min_t and "
+                "shared_min_tiles >= 0");
   if (t->scan_tile_kb) h->scan_tile_kb = h->last_scan_kb = t->scan_tile_kb;
   if (t->pass_tile_kb) h->pass_tile_kb = h->last_pass_kb = t->pass_tile_kb;
   h->tuned.clear();
   if (t->team_min_rows) h->team_min_rows = t->team_min_rows;
   if (t->rscan_min_t) h->rscan_min_t = t->rscan_min_t;
+  if (t->shared_min_tiles) h->shared_min_tiles = t->shared_min_tiles;
   h->pcache.valid = false;
   drop_graphs(h);
   return CLOMP_OK;
@@ -1475,6 +1488,8 @@ clomp_status_t clomp_get_tuning(clomp_handle_t h, clomp_tuning_t* t) {
   t->pass_tile_kb = h->last_pass_kb;
   t->team_min_rows = h->team_min_rows;
   t->rscan_min_t = h->rscan_min_t;
+  t->shared_min_tiles = h->shared_min_tiles > 0 ? h->shared_min_tiles
+                                                : std::max(1, h->num_cu / 2);
   return CLOMP_OK;
 }
 

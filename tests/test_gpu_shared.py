@@ -22,10 +22,12 @@ f32 = lambda v: float(np.float32(v))
 ITER = C.FLAG_NO_FUSED_SMALL   # keep the image columns out of the fused loop
 
 
-def _solve(method, b, flags, rscan_min_t=0, **kw):
+def _solve(method, b, flags, rscan_min_t=0, shared_min_tiles=0, **kw):
     sol = C.Solver(0, method=method, flags=flags, **kw)
-    if rscan_min_t:
-        sol.set_tuning(rscan_min_t=rscan_min_t)
+    if rscan_min_t or shared_min_tiles:
+        # shared_min_tiles = 1: IHT and paper mode take the shared schedule even
+        # for batches whose contraction has few output tiles
+        sol.set_tuning(rscan_min_t=rscan_min_t, shared_min_tiles=shared_min_tiles)
     out = sol.solve_shared(dev(b.At), b.m, dev(b.Y), b.k)
     torch.cuda.synchronize()
     sol.close()
@@ -189,7 +191,7 @@ def test_shared_gradient_iht_and_paper_mode(method):
     from tests.gpu_helpers import rel_err
     R = 20
     b = W.image_batch(0.3)
-    out = _solve(method, b, 0, inner_steps=R)
+    out = _solve(method, b, 0, inner_steps=R, shared_min_tiles=1)
     per = _solve(method, b, C.FLAG_NO_SHARED_GRAM, inner_steps=R)
     prm = PaperParams(threshold=f32(0.7), max_iters=R, lr_rel=f32(0.05), beta1=f32(0.9),
                       beta2=f32(0.999), eps_rel=f32(1e-8))
@@ -270,7 +272,7 @@ def test_shared_ragged_tiles_nan_padding(method):
     R = 20
     flags = ITER if method != "iht" else 0
     kw = {} if method != "iht" else dict(inner_steps=R)
-    out = _solve(method, b, flags, **kw)
+    out = _solve(method, b, flags, shared_min_tiles=1, **kw)
     per = _solve(method, b, flags | C.FLAG_NO_SHARED_GRAM, **kw)
     st = out.status.cpu().numpy()
     assert not (st & C.ST_NAN).any()
