@@ -52,6 +52,25 @@ def test_status_strings_and_defaults(lib):
     assert abs(p.select_threshold - 0.7) < 1e-7 and p.prior_tv == 0.0
 
 
+def header_struct_fields(name):
+    """(field, element count) of `typedef struct { ... } name;` in the header."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct\s*\{([^}]*)\}\s*" + name + r"\s*;", text).group(1)
+    out = []
+    for decl in body.split(";"):
+        mt = re.search(r"(\w+)\s*(?:\[(\d+)\])?\s*$", decl.strip())
+        if mt:
+            out.append((mt.group(1), int(mt.group(2) or 1)))
+    return out
+
+
+def test_tuning_struct_matches_header():
+    fields = header_struct_fields("clomp_tuning_t")
+    py = [(f, getattr(t, "_length_", 1)) for f, t in C.Tuning._fields_]
+    assert py == fields
+    assert ctypes.sizeof(C.Tuning) == 4 * sum(c for _, c in fields) == 8 * 4
+
+
 def test_struct_layout_matches_header():
     assert ctypes.sizeof(C.Instance) == 4 * 4 + 2 * 8 + 8 * 8
     assert ctypes.sizeof(C.Params) == 12 * 4
