@@ -58,17 +58,24 @@ def header_struct_fields(name):
     body = re.search(r"typedef struct\s*\{([^}]*)\}\s*" + name + r"\s*;", text).group(1)
     out = []
     for decl in body.split(";"):
-        mt = re.search(r"(\w+)\s*(?:\[(\d+)\])?\s*$", decl.strip())
-        if mt:
-            out.append((mt.group(1), int(mt.group(2) or 1)))
+        for piece in decl.split(","):   # `int32_t n, m;` declares two fields
+            mt = re.search(r"(\w+)\s*(?:\[(\d+)\])?\s*$", piece.strip())
+            if mt:
+                out.append((mt.group(1), int(mt.group(2) or 1)))
     return out
 
 
-def test_tuning_struct_matches_header():
-    fields = header_struct_fields("clomp_tuning_t")
-    py = [(f, getattr(t, "_length_", 1)) for f, t in C.Tuning._fields_]
-    assert py == fields
-    assert ctypes.sizeof(C.Tuning) == 4 * sum(c for _, c in fields) == 8 * 4
+@pytest.mark.parametrize("name, cls", [("clomp_tuning_t", C.Tuning),
+                                       ("clomp_params_t", C.Params),
+                                       ("clomp_instance_t", C.Instance)])
+def test_binding_structs_match_header(name, cls):
+    """Field names, order and array lengths of the ctypes mirrors."""
+    py = [(f[0], getattr(f[1], "_length_", 1)) for f in cls._fields_]
+    assert py == header_struct_fields(name)
+
+
+def test_tuning_struct_size():
+    assert ctypes.sizeof(C.Tuning) == 8 * 4
 
 
 def test_struct_layout_matches_header():
