@@ -96,6 +96,16 @@ typedef enum {
                                         A; this flag keeps the per-signal
                                         passes                                 */
 
+#define CLOMP_FLAG_NO_REFINE 128u    /* CLOMP and OMP: x receives the
+                                        coefficients the greedy loop reached
+                                        (CLOMP: the Adam iterate on the bulk
+                                        matrix; OMP: its least squares on the
+                                        bulk matrix) instead of the least-
+                                        squares refinement on A_master;
+                                        resid_norm is that x's residual on
+                                        A_master.  Exposes the learned
+                                        coefficients before refinement       */
+
 /*
  * Solver parameters.  The paper states the optimiser only as automatic
  * differentiation and back-propagation on learnable s (Methods, "Coefficients
@@ -293,9 +303,11 @@ clomp_status_t clomp_profile_read(clomp_handle_t h, clomp_profile_t* out /*host*
 clomp_status_t clomp_profile_reset(clomp_handle_t h);
 
 /*
- * Launch-shape tuning of a handle (host struct).  Each field is the number of
- * bulk-matrix kilobytes one workgroup streams in the corresponding kernel;
- * 0 keeps the current value.  Autotuning (CLOMP_FLAG_AUTOTUNE) writes the same
+ * Launch-shape tuning of a handle (host struct).  In every field 0 keeps the
+ * current value and -1 restores the default; other values must lie in
+ * [1, 65536] (spin_limit: >= 1).  The tile fields are the number of
+ * bulk-matrix kilobytes one workgroup streams in the corresponding kernel.
+ * Autotuning (CLOMP_FLAG_AUTOTUNE) writes the same
  * table: on the first solve of a batch whose size class it has not seen, it
  * times candidate values on the batch's own first pass over A and keeps the
  * fastest per (bulk dtype, schedule, size class).
@@ -305,8 +317,11 @@ clomp_status_t clomp_profile_reset(clomp_handle_t h);
  *                  this many atoms update the coefficients with a team of
  *                  ceil((t+1)/16) workgroups per signal (at most 128, and
  *                  only while the teams of all active signals fit on the
- *                  device at once); smaller supports use one workgroup
- *                  (default 256; a value >= k disables teams)
+ *                  device at once and the occupancy query for the launch's
+ *                  shape and LDS admits a member on every CU); smaller
+ *                  supports use one workgroup (default 256; a value >= k
+ *                  disables teams).  Members wait for one another's
+ *                  published coefficients; each wait is bounded (spin_limit)
  *   rscan_min_t    shared-dictionary batches: from the iteration whose
  *                  support has this many atoms on, the correlation scan is
  *                  one contraction C = A^T R over the batch's residuals
@@ -318,8 +333,12 @@ clomp_status_t clomp_profile_reset(clomp_handle_t h);
  *                  (atoms x signals); smaller batches scan per signal, which
  *                  keeps more of the device busy (default: half the compute
  *                  units; 1 always contracts)
+ *   spin_limit     polls of a coefficient-team wait before it gives up: the
+ *                  signal then carries CLOMP_ST_WATCHDOG, its coefficients
+ *                  are unspecified, and every kernel still finishes (default
+ *                  2^20; a small value forces that path, for testing it)
  * clomp_get_tuning returns the values in use for the last solve.
- * Errors: INVALID_ARGUMENT (NULL, negative or > 65536 values).
+ * Errors: INVALID_ARGUMENT (NULL, or a value outside the ranges above).
  */
 typedef struct {
   int32_t scan_tile_kb;
@@ -327,7 +346,8 @@ typedef struct {
   int32_t team_min_rows;
   int32_t rscan_min_t;
   int32_t shared_min_tiles;
-  int32_t reserved[3];
+  int32_t spin_limit;
+  int32_t reserved[2];
 } clomp_tuning_t;
 
 clomp_status_t clomp_set_tuning(clomp_handle_t h, const clomp_tuning_t* t /*host*/);

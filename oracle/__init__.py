@@ -30,7 +30,11 @@ Modules
   brute      O3  exhaustive support search for tiny instances
   grad       O4  loss/gradient of 1/2||A(mask*s) - y||^2;  O5 one Adam step
   lstsq      O6  least squares on a support;  FP64 residual norm
-  separation     "well-separated instance" test used to gate support identity
+  incremental    O1 with an updated QR (classical Gram-Schmidt twice) and O2
+                 with the gradient in Gram form G_S s_S - b_S: the same
+                 quantities at sizes the plain renderings cannot reach
+  separation     "well-separated instance" test used to gate support identity,
+                 and the separated prefix of a long support
 
 Parity status
   O2's pre-refinement Adam iterate s_adam has no closed form: parity unpinned
@@ -46,12 +50,15 @@ from .clomp_paper import clomp_paper_fp64, PaperParams
 from .iht import iht_fp64
 from .prior import dct_synthesis, forward_difference, tv_1d, tv_grad_coeffs, lstsq_support_tv
 from .brute import bruteforce_support
-from .separation import well_separated
+from .separation import (well_separated, separation_report, separated_prefix, common_prefix,
+                         perturbed_atoms, perturbed_vector)
+from .incremental import omp_cgs2_fp64, clomp_gram_fp64
 
 __all__ = [
     "lstsq_support", "resid_norm_fp64", "grad_fp64", "adam_step_fp64",
     "omp_fp64", "clomp_fp64", "ClompParams", "clomp_paper_fp64", "PaperParams", "iht_fp64",
     "dct_synthesis", "forward_difference", "tv_1d", "tv_grad_coeffs", "lstsq_support_tv",
     "bruteforce_support",
-    "well_separated",
+    "well_separated", "separation_report", "separated_prefix", "common_prefix",
+    "perturbed_atoms", "perturbed_vector", "omp_cgs2_fp64", "clomp_gram_fp64",
 ]

@@ -54,3 +54,66 @@ def well_separated(A, y, k, method="clomp", params=ClompParams(), delta=1e-4,
         if pert.support != base.support:
             return False, base
     return True, base
+
+
+def common_prefix(a, b):
+    """Number of leading positions where two ordered supports agree."""
+    n = 0
+    for p, q in zip(a, b):
+        if p != q:
+            break
+        n += 1
+    return n
+
+
+def separated_prefix(base, perturbed, delta):
+    """Length of the leading part of base.support that is well separated: the
+    selections before the first iteration whose gap is below delta, cut further
+    to where every perturbed run still agrees with the base run.  The greedy
+    loop is causal, so selections before that point are decided with margin."""
+    L = len(base.support)
+    for t, g in enumerate(base.gaps):
+        if g < delta:
+            L = min(L, t)
+            break
+    for p in perturbed:
+        L = min(L, common_prefix(base.support, p.support))
+    return L
+
+
+def perturbed_atoms(At, u, seed, out=None, chunk=4096):
+    """At * (1 + u e) with e independent random signs, for an atom-major (n, m)
+    array, filled by chunks of atoms (no full-size temporaries).  Returns out."""
+    At = np.asarray(At)
+    if out is None:
+        out = np.empty(At.shape, dtype=np.float64)
+    for c, j0 in enumerate(range(0, At.shape[0], chunk)):
+        j1 = min(At.shape[0], j0 + chunk)
+        e = np.random.default_rng([7, 7, seed, c]).choice([-1.0, 1.0], size=(j1 - j0, At.shape[1]))
+        np.multiply(At[j0:j1], 1.0 + u * e, out=out[j0:j1])
+    return out
+
+
+def perturbed_vector(y, u, seed):
+    """y * (1 + u e) with e random signs (companion of perturbed_atoms)."""
+    y = np.asarray(y, dtype=np.float64)
+    return y * (1.0 + u * np.random.default_rng([7, 8, seed]).choice([-1.0, 1.0], size=y.shape))
+
+
+def separation_report(A, y, k, method="clomp", params=ClompParams(), delta=1e-4, u=2.0 ** -24,
+                      seeds=(1, 2), A_refine=None, base=None):
+    """(ok, prefix, base): well_separated's verdict and the separated prefix of
+    the base support, from the same perturbed runs."""
+    A = np.asarray(A, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    if base is None:
+        base = _run(method, A, y, k, params, A_refine)
+    pert = []
+    for sd in seeds:
+        rng = np.random.default_rng([7, 7, sd])
+        Ap = A * (1.0 + u * rng.choice([-1.0, 1.0], size=A.shape))
+        yp = y * (1.0 + u * rng.choice([-1.0, 1.0], size=y.shape))
+        pert.append(_run(method, Ap, yp, k, params, A_refine))
+    ok = (not len(base.gaps) or min(base.gaps) >= delta) and all(
+        p.support == base.support for p in pert)
+    return ok, separated_prefix(base, pert, delta), base

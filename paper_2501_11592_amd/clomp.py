@@ -26,7 +26,7 @@ METHODS = {"clomp": METHOD_CLOMP, "omp": METHOD_OMP, "iht": METHOD_IHT,
            "clomp_paper": METHOD_PAPER}
 ST_NAN, ST_K_CAPPED, ST_ZERO_Y, ST_REFINE_INACCURATE, ST_WATCHDOG = 1, 2, 4, 8, 32
 FLAG_GRAPH, FLAG_NO_FUSED_SMALL, FLAG_AUTOTUNE, FLAG_PROFILE = 1, 2, 4, 8
-FLAG_RESIDUAL_FLOW, FLAG_CORR_FLOW, FLAG_NO_SHARED_GRAM = 16, 32, 64
+FLAG_RESIDUAL_FLOW, FLAG_CORR_FLOW, FLAG_NO_SHARED_GRAM, FLAG_NO_REFINE = 16, 32, 64, 128
 PHASES = ("scan", "gram", "coef", "resid", "refine", "norm", "init", "pass", "fused")
 
 STATUS_NAMES = {0: "CLOMP_OK", 1: "CLOMP_INVALID_ARGUMENT", 2: "CLOMP_OUT_OF_MEMORY",
@@ -69,7 +69,8 @@ class Profile(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("scan_tile_kb", ctypes.c_int32), ("pass_tile_kb", ctypes.c_int32),
                 ("team_min_rows", ctypes.c_int32), ("rscan_min_t", ctypes.c_int32),
-                ("shared_min_tiles", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("shared_min_tiles", ctypes.c_int32), ("spin_limit", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 @dataclass
@@ -161,6 +162,38 @@ def dtype_code(t):
     raise ClompError(f"unsupported dtype {t.dtype}")
 
 
+def _need(cond, msg):
+    if not cond:
+        raise ClompError(msg)
+
+
+def _check_vec(name, t, device, dtypes, length):
+    """A device vector of at least `length` contiguous elements."""
+    _need(isinstance(t, torch.Tensor), f"{name} must be a tensor")
+    _need(t.device == device, f"{name} is on {t.device}; the solver runs on {device}")
+    _need(t.dtype in dtypes, f"{name} has dtype {t.dtype}; expected one of {dtypes}")
+    _need(t.is_contiguous(), f"{name} must be contiguous")
+    _need(t.numel() >= length, f"{name} has {t.numel()} elements; {length} are read")
+
+
+def _check_atoms(name, t, device, dtypes, m, n=None):
+    """An atom-major matrix (n, lda): unit stride along each atom, lda >= m,
+    and storage for n * lda elements from its first element (the kernels read
+    whole padded atoms)."""
+    _need(isinstance(t, torch.Tensor), f"{name} must be a tensor")
+    _need(t.device == device, f"{name} is on {t.device}; the solver runs on {device}")
+    _need(t.dtype in dtypes, f"{name} has dtype {t.dtype}; expected one of {dtypes}")
+    _need(t.dim() == 2 and (t.shape[1] <= 1 or t.stride(1) == 1),
+          f"{name} must be 2-D (n, lda) with unit stride along each atom")
+    _need(n is None or t.shape[0] == n, f"{name} has {t.shape[0]} atoms; expected {n}")
+    lda = t.stride(0)
+    _need(t.shape[1] >= m and lda >= m, f"{name}: lda = {lda} and width {t.shape[1]} must be "
+                                        f">= m = {m}")
+    extent = (t.storage_offset() + t.shape[0] * lda) * t.element_size()
+    _need(t.untyped_storage().nbytes() >= extent,
+          f"{name}: storage holds fewer than n * lda elements")
+
+
 @dataclass
 class BatchResult:
     x: list            # per instance: float32 tensor (n,)
@@ -180,6 +213,8 @@ class Solver:
         if not torch.cuda.is_available():
             raise ClompError("no GPU available: the CLOMP library runs only on the device")
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
         p = default_params()
         if method not in METHODS:
             raise ClompError(f"unknown method {method!r}")
@@ -216,11 +251,12 @@ class Solver:
                "clomp_set_params")
 
     def set_tuning(self, scan_tile_kb=0, pass_tile_kb=0, team_min_rows=0, rscan_min_t=0,
-                   shared_min_tiles=0):
+                   shared_min_tiles=0, spin_limit=0):
+        """0 keeps a value, -1 restores its default."""
         t = Tuning()
         t.scan_tile_kb, t.pass_tile_kb = scan_tile_kb, pass_tile_kb
         t.team_min_rows, t.rscan_min_t = team_min_rows, rscan_min_t
-        t.shared_min_tiles = shared_min_tiles
+        t.shared_min_tiles, t.spin_limit = shared_min_tiles, spin_limit
         _check(self._h, load_library().clomp_set_tuning(self._h, ctypes.byref(t)),
                "clomp_set_tuning")
 
@@ -230,7 +266,7 @@ class Solver:
                "clomp_get_tuning")
         return {"scan_tile_kb": t.scan_tile_kb, "pass_tile_kb": t.pass_tile_kb,
                 "team_min_rows": t.team_min_rows, "rscan_min_t": t.rscan_min_t,
-                "shared_min_tiles": t.shared_min_tiles}
+                "shared_min_tiles": t.shared_min_tiles, "spin_limit": t.spin_limit}
 
     def profile_reset(self):
         _check(self._h, load_library().clomp_profile_reset(self._h), "clomp_profile_reset")
@@ -257,6 +293,24 @@ class Solver:
         if any(dtype_code(it["At"]) != dt for it in items):
             raise ClompError("all instances of a batch must share the bulk dtype")
         dev = self.device
+        # the library cannot see buffer sizes: every tensor is checked here,
+        # before any launch
+        seen = set()
+        for q, it in enumerate(items):
+            m = int(it["m"])
+            _need(m > 0 and int(it["k"]) > 0, f"instance {q}: m and k must be positive")
+            A = it["At"]
+            if id(A) not in seen:
+                _check_atoms(f"instance {q}: At", A, dev, (torch.float32, torch.bfloat16), m)
+            Am = it.get("At_master")
+            if Am is not None and id(Am) not in seen:
+                _check_atoms(f"instance {q}: At_master", Am, dev, (torch.float32,), m,
+                             n=A.shape[0])
+                seen.add(id(Am))
+            seen.add(id(A))
+            _need(Am is not None or A.dtype == torch.float32,
+                  f"instance {q}: a bfloat16 At needs a float32 At_master")
+            _check_vec(f"instance {q}: y", it["y"], dev, (torch.float32,), m)
         st = stream if stream is not None else torch.cuda.current_stream(dev)
         ns = np.fromiter((it["At"].shape[0] for it in items), np.int64, count)
         ks = np.fromiter((it["k"] for it in items), np.int64, count)
@@ -336,9 +390,18 @@ class Solver:
     # ------------------------------------------------------------------ grad
     def grad(self, At, m, x, mask, y, grad_out=None, want_resid=True, stream=None):
         """Returns (loss, grad_x, u) with u = A(mask*x) - y."""
+        dev = self.device
+        kinds = (torch.float32, torch.float64)
+        _check_atoms("At", At, dev, kinds, int(m))
         dt = dtype_code(At)
         n = int(At.shape[0])
-        dev = At.device
+        _check_vec("x", x, dev, (At.dtype,), n)
+        _check_vec("y", y, dev, (At.dtype,), int(m))
+        _check_vec("mask", mask, dev, (torch.uint8, torch.bool), n)
+        if mask.dtype == torch.bool:
+            mask = mask.view(torch.uint8)
+        if grad_out is not None:
+            _check_vec("grad_out", grad_out, dev, (At.dtype,), 1)
         gx = torch.empty(n, dtype=At.dtype, device=dev)
         loss = torch.empty((), dtype=At.dtype, device=dev)
         u = torch.empty(m, dtype=At.dtype, device=dev) if want_resid else None
@@ -369,7 +432,9 @@ class ClompLoss(torch.autograd.Function):
     """loss = 1/2 ||A(mask*x) - y||^2 with the hand-written HIP backward.
 
     forward(x, mask, At, m, y): At is (n, lda) atom-major, fixed (no gradient);
-    mask is uint8 (n,).  Gradients: grad_x = mask * A^T u * g, grad_y = -u * g.
+    mask is uint8 or bool (n,).  Gradients: grad_x = mask * A^T u * g,
+    grad_y = -u * g.  The backward is not itself differentiable (a second
+    derivative raises instead of returning zero).
     """
 
     @staticmethod
@@ -380,6 +445,7 @@ class ClompLoss(torch.autograd.Function):
         return loss
 
     @staticmethod
+    @torch.autograd.function.once_differentiable
     def backward(ctx, g):
         gx, u = ctx.saved_tensors
         return gx * g, None, None, None, -u * g

@@ -30,6 +30,9 @@ constexpr int kTeamMax = 128;   // team members per signal (2048 rows)
 // are summed afterwards in slice order.
 constexpr int kIhtSliceFloats = 6144;
 constexpr int kSmallMaxK = 64;  // fused small-signal loop: k_eff bound (one wave)
+// Polls of a coefficient-team wait before it gives up and sets the watchdog
+// bit (default; clomp_set_tuning can lower it).
+constexpr unsigned kSpinLimitDefault = 1u << 20;
 
 // Fused small-signal loop: row stride of the LDS Gram / inverse-Gram matrix
 // and the dynamic LDS of one signal (G | A as FP32, odd leading dimension |
@@ -84,6 +87,8 @@ struct Inst {
   long long ldh;
   int nslice;          // IHT: slices of m in the gradient scan (>= 1)
   float tvw;           // 2w/n for the total-variation prior of weight w (0: none)
+  unsigned spin;       // bounded device waits: polls before the watchdog bit is set
+  int spare;
   unsigned long long* team;   // [2*k_eff + 2*kTeamMax] tagged words exchanged by a team
                               // (correlation-update schedule; zeroed at solve start)
   float* gbuf;         // IHT: [nslice * ldh] per-slice partial dots; g = A^T r of the

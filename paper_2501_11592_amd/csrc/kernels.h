@@ -76,6 +76,10 @@ hipError_t launch_coef_pass(int bf16, int lpa, int omp, const Inst* dc, int nact
                             const Inst* d, const ScanTile* tiles, int ntiles, int t, int T,
                             float beta1, float beta2, float lr_rel, float eps_rel, size_t lds,
                             hipStream_t s);
+// Workgroups of a coefficient-team launch (1024 threads, `lds` bytes of
+// dynamic LDS) that one compute unit can hold at once (0: none, or the query
+// failed).
+int coef_team_blocks_per_cu(int bf16, int lpa, int omp, size_t lds);
 // shared dictionary: Gf = A^T A (ld ldh of the first signal), c0 = A^T y of
 // every signal, dg = diag(Gf) (+ the prior); d[0..nsig) share A, n, m.
 hipError_t launch_shared_gram(int bf16, const Inst* d, int nsig, int n, float* Gf, float* dg,

@@ -38,6 +38,7 @@ constexpr size_t kAlign = 256;
 constexpr int kScanTargetKB = 128;   // default bulk KB streamed per scan WG
 constexpr int kPassTargetKB = 256;   // default bulk KB per pass WG (1024 threads)
 constexpr int kPassThreadsHost = 1024;
+constexpr int kTeamMinRowsDefault = 256;   // larger supports use coefficient teams
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 int round_up_int(int v, int a) { return (v + a - 1) / a * a; }
@@ -110,6 +111,7 @@ struct PlanCache {
   bool valid = false;
   int bf16 = -1;
   std::vector<ShapeRec> shapes;
+  bool sameA = false;                 // the iterated signals share one A (and master)
   Plan P;
   int scan_kb = 0, pass_kb = 0;
 };
@@ -131,6 +133,8 @@ struct clomp_ctx {
   hipEvent_t staging_free = nullptr;  // last upload from `pinned` finished
   hipEvent_t work_done = nullptr;     // last launch sequence finished
   bool have_work = false;
+  hipEvent_t grad_done = nullptr;     // last clomp_grad finished with gwork
+  bool have_grad = false;
   int lds_limit = 65536;
   int num_cu = 256;
   DevBuf gwork;
@@ -145,7 +149,9 @@ struct clomp_ctx {
   bool pass_lds_ok = false;           // dynamic-LDS ceiling raised for pass kernels
   int scan_tile_kb = kScanTargetKB;
   int pass_tile_kb = kPassTargetKB;
-  int team_min_rows = 256;            // larger supports use coefficient teams
+  int team_min_rows = kTeamMinRowsDefault;
+  int spin_limit = (int)kSpinLimitDefault;   // polls of a team wait before the watchdog
+  std::map<long long, int> team_occ;  // team workgroups per CU by (dtype, lpa, method, LDS)
   int rscan_min_t = 1;                // shared dictionary: A^T R scan from this support size
   int shared_min_tiles = 0;           // IHT / paper mode: contraction tiles needed for the
                                       // shared gradient (0: half the compute units)
@@ -208,6 +214,11 @@ clomp_status_t check_params(clomp_ctx* h, const clomp_params_t* p) {
     return fail(h, CLOMP_INVALID_ARGUMENT, "refine_iters/refine_tol must be >= 0");
   if (p->resid_tol != 0.f)
     return fail(h, CLOMP_NOT_SUPPORTED, "resid_tol != 0 (early stopping) is not served");
+  if ((p->flags & CLOMP_FLAG_NO_REFINE) &&
+      !(p->method == CLOMP_METHOD_CLOMP || p->method == CLOMP_METHOD_OMP))
+    return fail(h, CLOMP_NOT_SUPPORTED, "CLOMP_FLAG_NO_REFINE is served for CLOMP and OMP");
+  if ((p->flags & CLOMP_FLAG_NO_REFINE) && p->prior_tv > 0.f)
+    return fail(h, CLOMP_NOT_SUPPORTED, "CLOMP_FLAG_NO_REFINE is not served with the prior");
   return CLOMP_OK;
 }
 
@@ -258,6 +269,21 @@ int pick_lpa(int m, int vw) {
   int lpa = 64;
   while (lpa > 4 && lpa * 16 > nvec) lpa >>= 1;
   return lpa;
+}
+
+// Whether the iterated signals [0, nbig) of a sorted batch all name the same
+// dictionary (pointer, layout and master): the condition of the shared-
+// dictionary schedules, which read A from the first signal only.
+bool same_dictionary(const clomp_instance_t* inst, const std::vector<int>& order, int nbig) {
+  if (nbig < 2) return false;
+  const clomp_instance_t& a = inst[order[0]];
+  for (int s = 1; s < nbig; ++s) {
+    const clomp_instance_t& b = inst[order[s]];
+    if (!(a.A == b.A && a.lda == b.lda && a.n == b.n && a.m == b.m &&
+          a.A_master == b.A_master && a.lda_master == b.lda_master))
+      return false;
+  }
+  return true;
 }
 
 // Build the plan (host tables + workspace layout) for one batch.
@@ -314,13 +340,7 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     // shared dictionary: every iterated signal has the same A (pointer, layout,
     // master) and the full Gram matrix fits in 4 GB; an iteration then reads
     // columns of A^T A instead of streaming A
-    bool sameA = P.nbig >= 2 && !(fl & CLOMP_FLAG_NO_SHARED_GRAM);
-    for (int s = 1; s < P.nbig && sameA; ++s) {
-      const clomp_instance_t& a = inst[order[0]];
-      const clomp_instance_t& b = inst[order[s]];
-      sameA = a.A == b.A && a.lda == b.lda && a.n == b.n && a.m == b.m &&
-              a.A_master == b.A_master && a.lda_master == b.lda_master;
-    }
+    const bool sameA = !(fl & CLOMP_FLAG_NO_SHARED_GRAM) && same_dictionary(inst, order, P.nbig);
     // IHT / paper mode: the batch's gradient as one contraction pays only when
     // it has enough 128 x 128 output tiles to fill the device; a small batch
     // (a 256 x 256 image: four tiles) scans per signal instead
@@ -354,8 +374,8 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     P.off_gdg = ws;
     ws = align_up(ws + sizeof(float) * l, kAlign);
   }
-  snprintf(sigbuf, sizeof sigbuf, "d%d;m%d;T%d;s%d;p%d;w%d;", bf16, prm.method,
-           prm.inner_steps, scan_kb, pass_kb, h->team_min_rows * 65536 + h->rscan_min_t);
+  snprintf(sigbuf, sizeof sigbuf, "d%d;m%d;T%d;s%d;p%d;w%d;r%d;", bf16, prm.method,
+           prm.inner_steps, scan_kb, pass_kb, h->team_min_rows, h->rscan_min_t);
   P.sig += sigbuf;
   for (int s = 0; s < count; ++s) {
     const int i = order[s];
@@ -382,7 +402,8 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     // with the prior the refinement's QR holds k_eff stacked rows more
     d.tvw = (prm.prior_tv > 0.f) ? 2.f * prm.prior_tv / (float)d.n : 0.f;
     const size_t qr_rows = (size_t)d.m + (d.tvw != 0.f ? d.k_eff : 0);
-    const bool use_qr = qr_rows * d.k_eff + qr_rows + 2 * d.k_eff <= (size_t)qr_limit_floats;
+    // (LDS: the columns, the right-hand side and four vectors of k_eff)
+    const bool use_qr = qr_rows * d.k_eff + qr_rows + 4 * d.k_eff <= (size_t)qr_limit_floats;
     d.cg_slot = use_qr ? -1 : 0;
     // workspace offsets (relative; rebased after allocation)
     auto take = [&](size_t bytes) {
@@ -558,7 +579,7 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     if (d.cg_slot < 0) {
       P.qr_list.push_back(q);
       const size_t qr_rows = (size_t)d.m + (d.tvw != 0.f ? d.k_eff : 0);
-      P.qr_lds = std::max(P.qr_lds, sizeof(float) * (qr_rows * d.k_eff + qr_rows + 2 * d.k_eff));
+      P.qr_lds = std::max(P.qr_lds, sizeof(float) * (qr_rows * d.k_eff + qr_rows + 4 * d.k_eff));
     } else {
       P.insts[q].cg_slot = (int)P.cg_list.size();
       P.cg_list.push_back(q);
@@ -664,6 +685,16 @@ struct PhaseScope {
   }
 };
 
+// Coefficient-team workgroups one CU can hold (cached per launch shape).
+int team_occupancy(clomp_ctx* h, int bf16, int lpa, int omp, size_t lds) {
+  const long long key = ((long long)lds << 16) | (bf16 << 12) | (omp << 8) | lpa;
+  auto it = h->team_occ.find(key);
+  if (it != h->team_occ.end()) return it->second;
+  const int nb = coef_team_blocks_per_cu(bf16, lpa, omp, lds);
+  h->team_occ[key] = nb;
+  return nb;
+}
+
 // Greedy loop of the correlation-update schedule.
 clomp_status_t launch_hflow(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st) {
   const clomp_params_t& prm = h->params;
@@ -726,16 +757,24 @@ clomp_status_t launch_hflow(clomp_ctx* h, const Plan& P, int bf16, hipStream_t s
         const size_t t1 = (size_t)t + 1;
         // a team of W blocks per signal for supports beyond the register tile,
         // while the teams stay far below the CU count (all resident at once)
-        int W = 1;
-        if (t1 > (size_t)h->team_min_rows) {
-          const int want = (int)((t1 + 15) / 16);
-          if (want <= kTeamMax && (long long)want * nact <= h->num_cu - 8) W = want;
-        }
         size_t lds = (size_t)c.m_pad_max * sizeof(float);
         lds = std::max(lds, (omp ? 6 : 1) * t1 * sizeof(float));
         // split-row Adam (256 < t+1 <= 1024): s[R] and partials [1024/R][R]
         if (!omp && t1 > 256 && t1 <= 1024) lds = std::max(lds, (size_t)2048 * sizeof(float));
-        if (W > 1) lds = std::max(lds, (t1 + 4 + 32) * sizeof(float));
+        int W = 1;
+        if (t1 > (size_t)h->team_min_rows) {
+          const int want = (int)((t1 + 15) / 16);
+          const size_t tlds = std::max(lds, (t1 + 4 + 32) * sizeof(float));
+          // members wait for one another, so all of them must be resident at
+          // once: the occupancy query must admit a member per CU (launch shape
+          // and LDS), and the teams of all active signals stay below the CU
+          // count; otherwise the single-workgroup update runs
+          if (want <= kTeamMax && (long long)want * nact <= h->num_cu - 8 &&
+              team_occupancy(h, bf16, c.lpa, omp, tlds) >= 1) {
+            W = want;
+            lds = tlds;
+          }
+        }
         PhaseScope ps(h, PH_PASS, st);
         // Split launch: with a shared dictionary no pass shares the launch, and
         // with more active signals than CUs the 16-wave coefficient workgroups
@@ -1026,11 +1065,15 @@ clomp_status_t launch_all(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st)
       }
     }
   }
-  // refinement
-  const int ncg = (int)P.cg_list.size();
+  // refinement (or, with CLOMP_FLAG_NO_REFINE, the greedy loop's coefficients)
+  const bool refine = !(prm.flags & CLOMP_FLAG_NO_REFINE);
+  const int ncg = refine ? (int)P.cg_list.size() : 0;
   {
   PhaseScope ref_scope(h, PH_REFINE, st, false);
-  HIP_TRY(launch_qr(d_insts, d_qr, (int)P.qr_list.size(), P.qr_lds, st), "qr");
+  if (refine)
+    HIP_TRY(launch_qr(d_insts, d_qr, (int)P.qr_list.size(), P.qr_lds, st), "qr");
+  else
+    HIP_TRY(launch_copy_s(d_insts, nullptr, count, st), "copy_s");
   if (ncg > 0) {
     const float tol = prm.refine_tol > 0.f ? prm.refine_tol : 1e-6f;
     const int iters = prm.refine_iters > 0 ? prm.refine_iters : 48;
@@ -1094,6 +1137,7 @@ clomp_status_t stage_plan(clomp_ctx* h, const Plan& P, hipStream_t st) {
   for (size_t q = 0; q < P.insts.size(); ++q) {
     Inst& d = dst[q];
     d = P.insts[q];
+    d.spin = (unsigned)h->spin_limit;
     auto rb = [&](auto*& ptr) {
       if (ptr) ptr = reinterpret_cast<std::remove_reference_t<decltype(ptr)>>(
                    wsb + (reinterpret_cast<uintptr_t>(ptr) - 1));
@@ -1300,7 +1344,8 @@ clomp_status_t clomp_create(clomp_handle_t* out, int device, const clomp_params_
   h->pass_lds_ok = set_max_lds_pass((size_t)h->lds_limit) == hipSuccess;
   if (!h->pass_lds_ok) (void)hipGetLastError();
   if (hipEventCreateWithFlags(&h->staging_free, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&h->work_done, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&h->work_done, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->grad_done, hipEventDisableTiming) != hipSuccess) {
     delete h;
     (void)hipSetDevice(prev);
     return CLOMP_DEVICE_ERROR;
@@ -1341,7 +1386,12 @@ clomp_status_t clomp_solve_batch(clomp_handle_t h, const clomp_instance_t* inst,
                  (long long)inst[i].lda, (long long)inst[i].lda_master};
   Plan fresh;
   int scan_kb = h->scan_tile_kb, pass_kb = h->pass_tile_kb;
-  const bool cached = h->pcache.valid && h->pcache.bf16 == bf16 && h->pcache.shapes == shapes;
+  // a cached plan also fixes whether the batch shares one dictionary: the
+  // shared schedules read A from the first signal, so a batch with the same
+  // shapes but other sharing needs a new plan
+  const bool cached = h->pcache.valid && h->pcache.bf16 == bf16 && h->pcache.shapes == shapes &&
+                      same_dictionary(inst, h->pcache.P.order, h->pcache.P.nbig) ==
+                          h->pcache.sameA;
   Plan& P = cached ? h->pcache.P : fresh;
   if (cached) {
     scan_kb = h->pcache.scan_kb;
@@ -1383,6 +1433,7 @@ clomp_status_t clomp_solve_batch(clomp_handle_t h, const clomp_instance_t* inst,
     h->pcache.P = std::move(fresh);
     h->pcache.bf16 = bf16;
     h->pcache.shapes = std::move(shapes);
+    h->pcache.sameA = same_dictionary(inst, h->pcache.P.order, h->pcache.P.nbig);
     h->pcache.scan_kb = scan_kb;
     h->pcache.pass_kb = pass_kb;
     h->pcache.valid = true;
@@ -1456,26 +1507,41 @@ clomp_status_t clomp_grad(clomp_handle_t h, int32_t n, int32_t m, int64_t lda, i
     clomp_status_t s = ensure(h, h->gwork, need, nullptr);
     if (s != CLOMP_OK) return s;
   }
+  // the partial sums live in one per-handle buffer: a call on another stream
+  // waits until the previous call has finished with it
+  if (h->have_grad) HIP_TRY(hipStreamWaitEvent(st, h->grad_done, 0), "hipStreamWaitEvent");
   HIP_TRY(launch_grad(dtype == CLOMP_F64, n, m, lda, A, x, mask, y, grad_out, grad_x, resid_out,
                       loss, h->gwork.p, ncolchunk, colchunk, st),
           "grad");
+  HIP_TRY(hipEventRecord(h->grad_done, st), "hipEventRecord");
+  h->have_grad = true;
   return CLOMP_OK;
 }
 
 clomp_status_t clomp_set_tuning(clomp_handle_t h, const clomp_tuning_t* t) {
   if (!h || !t) return CLOMP_INVALID_ARGUMENT;
-  if (t->scan_tile_kb < 0 || t->scan_tile_kb > 65536 || t->pass_tile_kb < 0 ||
-      t->pass_tile_kb > 65536 || t->team_min_rows < 0 || t->rscan_min_t < 0 ||
-      t->shared_min_tiles < 0)
-    return fail(h, CLOMP_INVALID_ARGUMENT,
-                "tile sizes must lie in [0, 65536] KB; team_min_rows, rscan_min_t and "
-                "shared_min_tiles >= 0");
-  if (t->scan_tile_kb) h->scan_tile_kb = h->last_scan_kb = t->scan_tile_kb;
-  if (t->pass_tile_kb) h->pass_tile_kb = h->last_pass_kb = t->pass_tile_kb;
+  const int32_t v[5] = {t->scan_tile_kb, t->pass_tile_kb, t->team_min_rows, t->rscan_min_t,
+                        t->shared_min_tiles};
+  for (int32_t x : v)
+    if (x < -1 || x > 65536)
+      return fail(h, CLOMP_INVALID_ARGUMENT,
+                  "tuning values must lie in [-1, 65536] (-1: default, 0: keep)");
+  if (t->spin_limit < -1)
+    return fail(h, CLOMP_INVALID_ARGUMENT, "spin_limit must be >= -1 (-1: default, 0: keep)");
+  // -1 restores the default, 0 keeps the current value
+  auto put = [](int32_t x, int& field, int dflt) {
+    if (x == -1) field = dflt;
+    else if (x > 0) field = x;
+  };
+  put(t->scan_tile_kb, h->scan_tile_kb, kScanTargetKB);
+  put(t->pass_tile_kb, h->pass_tile_kb, kPassTargetKB);
+  h->last_scan_kb = h->scan_tile_kb;
+  h->last_pass_kb = h->pass_tile_kb;
   h->tuned.clear();
-  if (t->team_min_rows) h->team_min_rows = t->team_min_rows;
-  if (t->rscan_min_t) h->rscan_min_t = t->rscan_min_t;
-  if (t->shared_min_tiles) h->shared_min_tiles = t->shared_min_tiles;
+  put(t->team_min_rows, h->team_min_rows, kTeamMinRowsDefault);
+  put(t->rscan_min_t, h->rscan_min_t, 1);
+  put(t->shared_min_tiles, h->shared_min_tiles, 0);
+  put(t->spin_limit, h->spin_limit, (int)kSpinLimitDefault);
   h->pcache.valid = false;
   drop_graphs(h);
   return CLOMP_OK;
@@ -1490,6 +1556,7 @@ clomp_status_t clomp_get_tuning(clomp_handle_t h, clomp_tuning_t* t) {
   t->rscan_min_t = h->rscan_min_t;
   t->shared_min_tiles = h->shared_min_tiles > 0 ? h->shared_min_tiles
                                                 : std::max(1, h->num_cu / 2);
+  t->spin_limit = h->spin_limit;
   return CLOMP_OK;
 }
 
@@ -1533,6 +1600,7 @@ clomp_status_t clomp_destroy(clomp_handle_t h) {
   if (h->pinned) (void)hipHostFree(h->pinned);
   if (h->staging_free) (void)hipEventDestroy(h->staging_free);
   if (h->work_done) (void)hipEventDestroy(h->work_done);
+  if (h->grad_done) (void)hipEventDestroy(h->grad_done);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   (void)hipSetDevice(prev);
   delete h;

@@ -1057,7 +1057,45 @@ __global__ __launch_bounds__(kBlock) void cg_dots_kernel(const Inst* __restrict_
 
 // ============================================================ small QR refine
 // Householder QR of the FP32 master columns A_S (m x t1, in LDS) and the
-// triangular solve R x = Q^T y, one workgroup per instance in the list.
+// triangular solve R x = Q^T y, one workgroup per instance in the list,
+// followed by kQrSteps steps of iterative refinement: the residual
+// r = y - A_S x accumulated in FP64 from the master columns, the correction
+// d = argmin ||r - A_S d|| from the same factors, x += d.  With the residual
+// in higher precision the error of x falls to about kappa(A_S) * 2^-24.
+constexpr int kQrSteps = 2;
+
+// Apply the stored reflectors H_0 .. H_{t1-1} to v (length mr) and solve
+// R d = (Q^T v)[0 .. t1), d into out.  Reflector c is column c of M from
+// row c on, with squared norm vn[c] (0: skipped).
+__device__ void qr_apply_solve(const float* M, const float* Rd, const float* vn, float* v,
+                               float* out, int mr, int t1, float* red) {
+  for (int c = 0; c < t1; ++c) {
+    const float* Mc = M + (long long)c * mr;
+    float p = 0.f;
+    for (int i = c + threadIdx.x; i < mr; i += kBlock) p = fmaf(Mc[i], v[i], p);
+    const float d = block_sum(p, red);
+    if (vn[c] > 0.f) {
+      const float f = 2.f * d / vn[c];
+      for (int i = c + threadIdx.x; i < mr; i += kBlock) v[i] = fmaf(-f, Mc[i], v[i]);
+    }
+    __syncthreads();
+  }
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  for (int c = t1 - 1; c >= 0; --c) {
+    if (wv == 0) {
+      float sacc = 0.f;
+      for (int cc = c + 1 + lane; cc < t1; cc += 64) sacc = fmaf(M[c + (long long)cc * mr], out[cc], sacc);
+      sacc = wave_sum(sacc);
+      if (lane == 0) {
+        const float dd = Rd[c];
+        out[c] = (dd != 0.f) ? (v[c] - sacc) / dd : 0.f;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void qr_refine_kernel(const Inst* __restrict__ insts,
                                                            const int* __restrict__ list) {
   extern __shared__ __align__(16) float qsh[];
@@ -1074,6 +1112,8 @@ __global__ __launch_bounds__(kBlock) void qr_refine_kernel(const Inst* __restric
   float* yv = qsh + (long long)mr * t1;   // mr
   float* Rd = yv + mr;             // t1 diagonal of R
   float* xs = Rd + t1;             // t1 solution
+  float* vn = xs + t1;             // t1 squared reflector norms
+  float* dx = vn + t1;             // t1 refinement correction
   for (int idx = threadIdx.x; idx < mr * t1; idx += kBlock) {
     const int c = idx / mr, i = idx - c * mr;
     M[idx] = (i < m) ? I.Am[(long long)I.support[c] * I.ldam + i]
@@ -1101,7 +1141,10 @@ __global__ __launch_bounds__(kBlock) void qr_refine_kernel(const Inst* __restric
       diag[0] = alpha;
     }
     __syncthreads();
-    if (threadIdx.x == 0) Rd[c] = alpha;
+    if (threadIdx.x == 0) {
+      Rd[c] = alpha;
+      vn[c] = (nrm > 0.f && vn2 > 0.f) ? vn2 : 0.f;
+    }
     if (!(nrm > 0.f) || !(vn2 > 0.f)) {
       rank_def = true;
       __syncthreads();
@@ -1131,6 +1174,26 @@ __global__ __launch_bounds__(kBlock) void qr_refine_kernel(const Inst* __restric
         xs[c] = (d != 0.f) ? (yv[c] - sacc) / d : 0.f;
       }
     }
+    __syncthreads();
+  }
+  // iterative refinement: r = y - A_S x in FP64 from the master columns
+  // (stacked prior rows: r = -sqrt(lambda_c) x_c), correction from the factors
+  for (int step = 0; step < kQrSteps && !rank_def; ++step) {
+    for (int i = threadIdx.x; i < mr; i += kBlock) {
+      double acc;
+      if (i < m) {
+        acc = (double)yw[i];
+        for (int c = 0; c < t1; ++c)
+          acc -= (double)I.Am[(long long)I.support[c] * I.ldam + i] * (double)xs[c];
+      } else {
+        const int c = i - m;
+        acc = -(double)sqrtf(tv_diag(I, I.support[c])) * (double)xs[c];
+      }
+      yv[i] = (float)acc;
+    }
+    __syncthreads();
+    qr_apply_solve(M, Rd, vn, yv, dx, mr, t1, red);
+    for (int c = threadIdx.x; c < t1; c += kBlock) xs[c] += dx[c];
     __syncthreads();
   }
   for (int c = threadIdx.x; c < t1; c += kBlock) I.xf[c] = xs[c];
@@ -1198,9 +1261,10 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(const Inst* __restrict
 }
 
 // Copy the coefficients reached by the greedy loop into xf (the CGLS start).
+// list == nullptr: every instance of the launch (one workgroup each).
 __global__ __launch_bounds__(kBlock) void copy_s_kernel(const Inst* __restrict__ insts,
                                                         const int* __restrict__ list) {
-  const Inst& I = insts[list[blockIdx.x]];
+  const Inst& I = insts[list ? list[blockIdx.x] : blockIdx.x];
   const int t1 = *I.nsel;
   for (int l = threadIdx.x; l < t1; l += kBlock) I.xf[l] = I.s[l];
   if (threadIdx.x == 0) I.st->cg_done = 0;
@@ -2368,12 +2432,11 @@ __global__ __launch_bounds__(kPassThreads) void ypass_kernel(const Inst* __restr
 // reader waits until the word carries the tag it expects, so the value and
 // its readiness travel together and no read-modify-write barrier is needed.
 // Tags grow strictly within a solve (Adam step number, or t+1 for OMP) and
-// the words are zeroed at solve start.  A wait is bounded: on expiry it sets
+// the words are zeroed at solve start.  A wait is bounded (I.spin polls): on
+// expiry it sets
 // the watchdog bit, which ends every other wait of the signal at once; the
 // launch then finishes with unspecified coefficients and member 0 retires
 // the signal.
-constexpr unsigned kSpinLimit = 1u << 20;
-
 __device__ inline void team_put(unsigned long long* p, unsigned tag, float v) {
   __hip_atomic_store(p, ((unsigned long long)tag << 32) | __float_as_uint(v), __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_AGENT);
@@ -2386,7 +2449,7 @@ __device__ inline float team_get(const Inst& I, const unsigned long long* p, uns
     __builtin_amdgcn_s_sleep(1);
     if (__hip_atomic_load(I.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ST_WATCHDOG)
       break;
-    if (++spins > kSpinLimit) {
+    if (++spins > I.spin) {
       atomicOr(I.status, ST_WATCHDOG);
       break;
     }
@@ -3281,6 +3344,31 @@ static hipError_t coef_pass_dispatch(int lpa, int coef, const Inst* dc, int nact
     case 16: return coef_pass_lpa<TA, 16>(coef, dc, nact, W, d, tiles, ntiles, t, T, b1, b2, lr, ep, lds, s);
     case 32: return coef_pass_lpa<TA, 32>(coef, dc, nact, W, d, tiles, ntiles, t, T, b1, b2, lr, ep, lds, s);
     default: return coef_pass_lpa<TA, 64>(coef, dc, nact, W, d, tiles, ntiles, t, T, b1, b2, lr, ep, lds, s);
+  }
+}
+
+template <typename TA, int LPA>
+static int team_blocks_per_cu(int omp, size_t lds) {
+  int nb = 0;
+  const hipError_t e =
+      omp ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, coef_pass_kernel<TA, LPA, COEF_OMP_TEAM>, kPassThreads, lds)
+          : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, coef_pass_kernel<TA, LPA, COEF_ADAM_TEAM>, kPassThreads, lds);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return nb;
+}
+
+int coef_team_blocks_per_cu(int bf16, int lpa, int omp, size_t lds) {
+  switch (lpa) {
+    case 4: return bf16 ? team_blocks_per_cu<uint16_t, 4>(omp, lds) : team_blocks_per_cu<float, 4>(omp, lds);
+    case 8: return bf16 ? team_blocks_per_cu<uint16_t, 8>(omp, lds) : team_blocks_per_cu<float, 8>(omp, lds);
+    case 16: return bf16 ? team_blocks_per_cu<uint16_t, 16>(omp, lds) : team_blocks_per_cu<float, 16>(omp, lds);
+    case 32: return bf16 ? team_blocks_per_cu<uint16_t, 32>(omp, lds) : team_blocks_per_cu<float, 32>(omp, lds);
+    default: return bf16 ? team_blocks_per_cu<uint16_t, 64>(omp, lds) : team_blocks_per_cu<float, 64>(omp, lds);
   }
 }
 

@@ -242,14 +242,95 @@ def device_gaussian_atoms(n, m, lda, seed, device, chunk_atoms=4096):
     return At
 
 
+# --------------------------------------------------- host draws with goldens
+def measurements(At, m, supp, s_supp):
+    """y = A_S s_S for a noiseless instance: the float64 products of the stored
+    columns summed by numpy's fixed-order reduction (no BLAS, so the value does
+    not depend on the host's thread count), rounded to float32."""
+    AS = np.asarray(At[np.asarray(supp), :m], dtype=np.float64)
+    return (AS * np.asarray(s_supp, dtype=np.float64)[:, None]).sum(axis=0).astype(np.float32)
+
+
+def bf16_values(At32):
+    """The bfloat16 storage of a float32 array (round to nearest even), returned
+    as the float32 array of the stored values."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(At32)).to(torch.bfloat16).to(
+        torch.float32).numpy()
+
+
+def uneven_golden_indices(specs, count=16):
+    """Stratified sample of the uneven batch: the instances at the centres of
+    `count` equal strata of the batch sorted by n, the last stratum replaced by
+    the largest n.  These are drawn on the host so the oracle can regenerate
+    them."""
+    order = np.argsort([sp.n for sp in specs], kind="stable")
+    N = len(order)
+    pos = [int((q + 0.5) * N / count) for q in range(count - 1)] + [N - 1]
+    return [int(order[p]) for p in pos]
+
+
+def uneven_instance_golden(i, spec):
+    """Instance i of the uneven batch as the host draws it (the stratified
+    sample): A iid N(0, 1/m) float32 master (lda a multiple of 32), N(0, 1)
+    non-zeros on a uniform support, noiseless y = A s (fixed-order sum)."""
+    g = rng_for(4, i, 3)
+    n, m, k = spec.n, spec.m, spec.k
+    blk = g.standard_normal((n, m), dtype=np.float32)
+    blk *= np.float32(1.0 / math.sqrt(m))
+    At = _pack(blk, pad_lda(m, 4), np.float32)
+    supp = np.sort(g.choice(n, size=k, replace=False))
+    s = np.zeros(n)
+    s[supp] = g.standard_normal(k)
+    return Signal(At, m, measurements(At, m, supp, s[supp]), k, supp, s)
+
+
+FLAT_CHUNK = 4096
+
+
+def flat_image_host(n=FLAT_N, m=FLAT_M, k=FLAT_K, workers=None):
+    """The flattened 256 x 256 image drawn on the host: A iid N(0, 1/m) as an
+    (n, lda) float32 array, atoms j0 .. j0+4095 drawn from their own PCG64
+    stream (so several threads can fill it and the values do not depend on
+    their number); power-law coefficients truncated to k; noiseless y = A s
+    (fixed-order sum).  Returns (At, y, supp, s)."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    lda = pad_lda(m, 4)
+    At = np.zeros((n, lda), dtype=np.float32)
+    scale = np.float32(1.0 / math.sqrt(m))
+
+    def fill(c):
+        j0 = c * FLAT_CHUNK
+        j1 = min(n, j0 + FLAT_CHUNK)
+        blk = rng_for(5, 0, 100 + c).standard_normal((j1 - j0, m), dtype=np.float32)
+        blk *= scale
+        At[j0:j1, :m] = blk
+
+    nchunk = (n + FLAT_CHUNK - 1) // FLAT_CHUNK
+    with ThreadPoolExecutor(max_workers=workers or min(16, os.cpu_count() or 1)) as ex:
+        list(ex.map(fill, range(nchunk)))
+    supp, s = flat_image_coeffs(n, k)
+    return At, measurements(At, m, supp, s[supp]), supp, s
+
+
+def fingerprint(a):
+    """sha256 of an array's bytes (inputs of a stored oracle result)."""
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
 # ------------------------------------------------------------ device batches
-def uneven_batch_device(count=4096, device="cuda"):
+def uneven_batch_device(count=4096, device="cuda", golden=True):
     """The uneven batch drawn on the device: per instance an FP32 master
     (lda rounded to 32) and its bfloat16 copy (lda rounded to 64), packed in two
     flat buffers; y = A s computed from the master in float64 on the device.
-    Returns (specs, items, supports, coefficient dicts)."""
+    With golden=True the stratified sample (uneven_golden_indices) is drawn on
+    the host instead (uneven_instance_golden, bfloat16 rounding on the host)
+    and uploaded.  Returns (specs, items, supports, coefficient dicts)."""
     import torch
     specs = uneven_specs(count)
+    gold = set(uneven_golden_indices(specs)) if golden and count == 4096 else set()
     lda32 = [pad_lda(sp.m, 4) for sp in specs]
     lda16 = [pad_lda(sp.m, 2) for sp in specs]
     tot32 = sum(sp.n * l for sp, l in zip(specs, lda32))
@@ -264,6 +345,16 @@ def uneven_batch_device(count=4096, device="cuda"):
         Ab = buf16[o16:o16 + n * lda16[i]].view(n, lda16[i])
         o32 += n * lda32[i]
         o16 += n * lda16[i]
+        if i in gold:
+            sig = uneven_instance_golden(i, sp)
+            Am.copy_(torch.from_numpy(sig.At))
+            Ab.zero_()
+            Ab[:, :m] = torch.from_numpy(bf16_values(sig.At[:, :m])).to(device).to(torch.bfloat16)
+            items.append(dict(At=Ab, m=m, y=torch.from_numpy(sig.y).to(device), k=k,
+                              At_master=Am))
+            supports.append(sig.support)
+            coefs.append(sig.s[sig.support])
+            continue
         gen = torch.Generator(device=device)
         gen.manual_seed(torch_seed_for(4, i))
         Am.zero_()
@@ -282,15 +373,16 @@ def uneven_batch_device(count=4096, device="cuda"):
     return specs, items, supports, coefs
 
 
-def flat_image_device(device="cuda", n=FLAT_N, m=FLAT_M, k=FLAT_K):
-    """The flattened 256 x 256 image: A iid N(0, 1/m) drawn on the device as an
-    FP32 master and a bfloat16 copy; power-law coefficients truncated to k;
-    noiseless y = A s from the master in float64."""
+def flat_image_device(device="cuda", host=None, m=FLAT_M):
+    """The flattened 256 x 256 image on the device: the host draw of
+    flat_image_host (or `host`, its result) uploaded as the FP32 master, and
+    its bfloat16 copy rounded on the host.  Returns (Am, Ab, y, supp, s)."""
     import torch
-    supp, s = flat_image_coeffs(n, k)
-    Am = device_gaussian_atoms(n, m, pad_lda(m, 4), torch_seed_for(5, 0), device)
+    At, y, supp, s = host if host is not None else flat_image_host(m=m)
+    n = At.shape[0]
+    Am = torch.from_numpy(At).to(device)
     Ab = torch.zeros((n, pad_lda(m, 2)), dtype=torch.bfloat16, device=device)
-    Ab[:, :m] = Am[:, :m].to(torch.bfloat16)
-    idx = torch.as_tensor(supp, device=device)
-    y = (Am[idx, :m].double().T @ torch.as_tensor(s[supp], device=device)).float().contiguous()
-    return Am, Ab, y, supp, s
+    for j0 in range(0, n, FLAT_CHUNK):
+        j1 = min(n, j0 + FLAT_CHUNK)
+        Ab[j0:j1, :m] = torch.from_numpy(At[j0:j1, :m]).to(torch.bfloat16).to(device)
+    return Am, Ab, torch.from_numpy(y).to(device), supp, s

@@ -136,3 +136,52 @@ def test_product_path_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(C, "_lib", None)
     with pytest.raises(C.ClompError):
         C.load_library(str(tmp_path / "missing.so"))
+
+
+# ---- binding checks (no GPU needed: they run before any library call) ----
+import torch  # noqa: E402
+
+CPU = torch.device("cpu")
+
+
+def _raises(fn, text):
+    with pytest.raises(C.ClompError, match=text):
+        fn()
+
+
+def test_binding_rejects_matrices_the_kernels_would_overrun():
+    ok = torch.zeros(10, 16)
+    C._check_atoms("At", ok, CPU, (torch.float32,), 12)
+    _raises(lambda: C._check_atoms("At", ok, CPU, (torch.float32,), 17), "must be >= m")
+    _raises(lambda: C._check_atoms("At", ok.double(), CPU, (torch.float32,), 12), "dtype")
+    _raises(lambda: C._check_atoms("At", ok.t(), CPU, (torch.float32,), 8), "unit stride")
+    _raises(lambda: C._check_atoms("At", ok, CPU, (torch.float32,), 12, n=11), "atoms")
+    # a (n, m) view of a padded buffer whose last atom's padding is missing
+    buf = torch.zeros(10 * 16 - 4)
+    view = buf.as_strided((10, 12), (16, 1))
+    _raises(lambda: C._check_atoms("At", view, CPU, (torch.float32,), 12), "storage")
+    full = torch.zeros(10 * 16).as_strided((10, 12), (16, 1))
+    C._check_atoms("At", full, CPU, (torch.float32,), 12)
+    _raises(lambda: C._check_atoms("At", ok, torch.device("meta"), (torch.float32,), 12),
+            "solver runs on")
+
+
+def test_binding_rejects_short_or_mistyped_vectors():
+    y = torch.zeros(12)
+    C._check_vec("y", y, CPU, (torch.float32,), 12)
+    _raises(lambda: C._check_vec("y", y, CPU, (torch.float32,), 13), "13 are read")
+    _raises(lambda: C._check_vec("y", y.double(), CPU, (torch.float32,), 12), "dtype")
+    _raises(lambda: C._check_vec("y", torch.zeros(24)[::2], CPU, (torch.float32,), 12),
+            "contiguous")
+    _raises(lambda: C._check_vec("mask", torch.zeros(12, dtype=torch.int32), CPU,
+                                 (torch.uint8, torch.bool), 12), "dtype")
+
+
+def test_loss_backward_is_once_differentiable():
+    fn = C.ClompLoss.backward
+    assert getattr(fn, "__wrapped__", None) is not None or "once_differentiable" in repr(fn)
+
+
+def test_set_tuning_ranges_documented_in_header():
+    text = open(HEADER).read()
+    assert "-1 restores the default" in text and "spin_limit" in text

@@ -14,6 +14,8 @@ import numpy as np
 import pytest
 
 from oracle import (omp_fp64, clomp_fp64, ClompParams, clomp_paper_fp64, PaperParams,
+                    omp_cgs2_fp64, clomp_gram_fp64, separation_report, separated_prefix,
+                    common_prefix, perturbed_atoms, perturbed_vector,
                     iht_fp64, lstsq_support,
                     resid_norm_fp64, grad_fp64, adam_step_fp64,
                     bruteforce_support, well_separated,
@@ -649,3 +651,158 @@ def test_clomp_prior_matches_autograd_and_torch_adam_rendering():
         assert S == ref.support
         np.testing.assert_allclose(s.detach().numpy()[S], ref.extra["s_adam"],
                                    rtol=1e-10, atol=1e-12)
+
+
+# ------------------------------------------------- large-instance renderings
+# omp_cgs2_fp64 / clomp_gram_fp64 compute O1 / O2 through exact identities
+# (updated QR; G_S s_S - b_S).  Pinned against the plain renderings, which are
+# pinned above, and the Gram form also against the autograd rendering.
+
+def _instances():
+    out = []
+    for seed in range(4):
+        A, y, _, _ = gaussian_instance(40 + seed, 64, 256, 8)
+        out.append((A, y + 0.01 * np.random.default_rng(seed).standard_normal(64), 10))
+    A, y, _, _ = gaussian_instance(50, 160, 600, 40)
+    out.append((A, y + 1e-3 * np.random.default_rng(9).standard_normal(160), 48))
+    g = np.random.default_rng(51)
+    A = g.standard_normal((120, 480)) / math.sqrt(120)
+    supp, s = W.power_law_coeffs(g, 480, 60)
+    out.append((A, A @ s, 60))
+    return out
+
+
+def test_incremental_omp_matches_plain_omp():
+    for A, y, k in _instances():
+        At = np.ascontiguousarray(A.T)            # atom-major storage, passed as a view
+        a = omp_fp64(A, y, k)
+        b = omp_cgs2_fp64(At.T, y, k)
+        assert b.support == a.support
+        np.testing.assert_allclose(b.x, a.x, rtol=0, atol=1e-10 * np.abs(a.x).max())
+        assert abs(b.resid_norm - a.resid_norm) <= 1e-10 * np.linalg.norm(y)
+        np.testing.assert_allclose(b.gaps, a.gaps, rtol=1e-6, atol=1e-12)
+
+
+def test_incremental_omp_refines_on_master():
+    A, y, _ = _instances()[4]
+    Ab = A * (1 + 2.0 ** -8 * np.random.default_rng(3).choice([-1, 1], A.shape))
+    r = omp_cgs2_fp64(Ab, y, 30, A_refine=A)
+    assert r.support == omp_fp64(Ab, y, 30).support
+    np.testing.assert_allclose(r.x[r.support], lstsq_support(A, y, r.support), rtol=0,
+                               atol=1e-13)
+
+
+def test_gram_clomp_matches_plain_clomp():
+    for A, y, k in _instances():
+        At = np.ascontiguousarray(A.T)
+        a = clomp_fp64(A, y, k)
+        b = clomp_gram_fp64(At.T, y, k, ClompParams())
+        assert b.support == a.support
+        sa = a.extra["s_adam"]
+        np.testing.assert_allclose(b.extra["s_adam"], sa, rtol=0, atol=1e-10 * np.abs(sa).max())
+        np.testing.assert_allclose(b.x, a.x, rtol=0, atol=1e-10 * np.abs(a.x).max())
+        assert b.extra["steps"] == a.extra["steps"]
+        assert abs(b.extra["sigma"] - a.extra["sigma"]) <= 1e-14 * a.extra["sigma"]
+        assert abs(b.resid_norm - a.resid_norm) <= 1e-10 * np.linalg.norm(y)
+
+
+def test_gram_clomp_bf16_style_with_master_matches_plain():
+    A, y, _ = _instances()[4]
+    Ab = A * (1 + 2.0 ** -8 * np.random.default_rng(5).choice([-1, 1], A.shape))
+    P = ClompParams(inner_steps=32, lr_rel=0.05)
+    a = clomp_fp64(Ab, y, 40, P, A_refine=A)
+    b = clomp_gram_fp64(Ab, y, 40, P, A_refine=A)
+    assert b.support == a.support
+    np.testing.assert_allclose(b.x, a.x, rtol=0, atol=1e-10 * np.abs(a.x).max())
+
+
+def test_gram_clomp_matches_autograd_and_torch_adam_rendering():
+    """The Gram-form oracle against the framework rendering (autograd through
+    A (mask * s), torch.optim.Adam with the per-iteration learning rate)."""
+    torch = pytest.importorskip("torch")
+    A, y, _, _ = gaussian_instance(60, 24, 96, 5)
+    y = y + 0.01 * np.random.default_rng(60).standard_normal(24)
+    P = ClompParams(inner_steps=16, lr_rel=0.05)
+    ref = clomp_gram_fp64(A, y, 6, P)
+    At, yt = torch.tensor(A), torch.tensor(y)
+    s = torch.zeros(96, dtype=torch.float64, requires_grad=True)
+    mask = torch.zeros(96, dtype=torch.float64)
+    opt, S = None, []
+    for t in range(6):
+        with torch.no_grad():
+            c = At.T @ (yt - At @ (mask * s))
+            score = c.abs().clone()
+            score[mask.bool()] = -float("inf")
+            j = int(torch.argmax(score))
+            if t == 0:
+                sig = float(c.abs().max())
+                opt = torch.optim.Adam([s], lr=1.0, betas=(0.9, 0.999), eps=1e-8 * sig,
+                                       foreach=False)
+            opt.param_groups[0]["lr"] = 0.05 * abs(float(c[j]))
+            mask[j] = 1.0
+            S.append(j)
+        for _ in range(16):
+            opt.zero_grad()
+            loss = 0.5 * ((At @ (mask * s) - yt) ** 2).sum()
+            loss.backward()
+            opt.step()
+    assert S == ref.support
+    np.testing.assert_allclose(s.detach().numpy()[S], ref.extra["s_adam"], rtol=1e-11, atol=1e-13)
+
+
+def test_incremental_renderings_zero_y_and_capped_k():
+    A, _, _, _ = gaussian_instance(61, 6, 20, 2)
+    for f in (lambda yy, kk: omp_cgs2_fp64(A, yy, kk),
+              lambda yy, kk: clomp_gram_fp64(A, yy, kk, ClompParams())):
+        r = f(np.zeros(6), 3)
+        assert r.status & ST_ZERO_Y and r.support == []
+        r = f(np.ones(6), 9)
+        assert r.status & ST_K_CAPPED and len(r.support) == 6
+        assert r.resid_norm < 1e-12      # |S| = m: y is reproduced exactly
+
+
+def test_separated_prefix_stops_at_first_small_gap_and_disagreement():
+    from oracle.omp import SolveResult
+    base = SolveResult([5, 1, 9, 3], np.zeros(10), 0.0, [0.5, 0.2, 1e-6, 0.3], [])
+    assert separated_prefix(base, [], 1e-4) == 2
+    assert separated_prefix(base, [], 1e-7) == 4
+    p = SolveResult([5, 2, 9, 3], np.zeros(10), 0.0, [], [])
+    assert separated_prefix(base, [p], 1e-7) == 1
+    assert common_prefix([1, 2, 3], [1, 2, 3]) == 3 and common_prefix([], [1]) == 0
+
+
+def test_separation_report_agrees_with_well_separated():
+    for seed in range(6):
+        A, y, _, _ = gaussian_instance(70 + seed, 48, 160, 6)
+        ok1, base = well_separated(A, y, 6, delta=1e-3, u=2.0 ** -8)
+        ok2, pre, _ = separation_report(A, y, 6, delta=1e-3, u=2.0 ** -8, base=base)
+        assert ok1 == ok2 and (pre == 6) == ok1
+
+
+def test_perturbed_atoms_relative_size_and_determinism():
+    At = np.random.default_rng(1).standard_normal((9000, 7))
+    P = perturbed_atoms(At, 2.0 ** -8, 3, chunk=4096)
+    np.testing.assert_allclose(np.abs(P / At - 1.0), 2.0 ** -8, rtol=1e-12)
+    np.testing.assert_array_equal(P, perturbed_atoms(At, 2.0 ** -8, 3, chunk=4096))
+    assert not np.array_equal(P, perturbed_atoms(At, 2.0 ** -8, 4, chunk=4096))
+    y = np.arange(1.0, 6.0)
+    np.testing.assert_allclose(np.abs(perturbed_vector(y, 2.0 ** -24, 1) / y - 1), 2.0 ** -24,
+                               rtol=1e-9)
+
+
+def test_golden_input_generators_are_deterministic_and_fixed_order():
+    specs = W.uneven_specs(4096)
+    idx = W.uneven_golden_indices(specs)
+    ns = [specs[i].n for i in idx]
+    assert len(idx) == 16 == len(set(idx)) and ns == sorted(ns)
+    assert max(ns) == max(sp.n for sp in specs)           # includes the largest n
+    a = W.uneven_instance_golden(idx[0], specs[idx[0]])
+    b = W.uneven_instance_golden(idx[0], specs[idx[0]])
+    np.testing.assert_array_equal(a.At, b.At)
+    np.testing.assert_array_equal(a.y, b.y)
+    assert a.At.shape[1] % 32 == 0 and not a.At[:, a.m:].any()
+    y64 = a.A[:, a.support] @ a.s[a.support]
+    np.testing.assert_allclose(a.y, y64, rtol=1e-6, atol=1e-6 * np.abs(y64).max())
+    v = W.bf16_values(np.array([1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -2.5e-3], np.float32))
+    np.testing.assert_array_equal(v[:3], [1.0, 1.0, 1.0 + 4 * 2.0 ** -8])   # ties to even
+    assert v.dtype == np.float32 and abs(v[3] / -2.5e-3 - 1) <= 2.0 ** -9
