@@ -36,7 +36,7 @@ def _solve(method, b, flags, rscan_min_t=0, shared_min_tiles=0, **kw):
 
 # the correlation scan: always C = A^T R over the batch's residuals, or
 # always c0 - Gf[:, S] s per signal
-SCANS = {"atr": 1, "gram": 1 << 20}
+SCANS = {"atr": 1, "gram": 65536}
 
 
 @pytest.mark.parametrize("scan", sorted(SCANS))
