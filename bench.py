@@ -2,23 +2,27 @@
 instances, with the roofline of the dominant kernel and the FP64 CPU oracle
 timed on the host.
 
-Default workload (the headline): one large 1-D signal, n=16384 atoms, m=4096
-measurements (sampling rate 0.25), k=256, A iid N(0, 1/m) stored float32,
-non-zeros +-(1+|N(0,1)|), y = A s + N(0, 1e-4); batch of one, so every greedy
-iteration streams the whole 268 MB dictionary (HBM-bound).
+Default workload (the largest that fits one GPU): the uneven batch, 4096
+signals with n log-uniform in [512, 8192], m/n uniform in [0.1, 0.5], k
+uniform in [n/64, n/16], A iid N(0, 1/m) stored as a BF16 bulk copy (greedy
+loop) and an FP32 master (refinement and FP64 residual norm), N(0, 1)
+non-zeros, noiseless; all 4096 in one call.  Accuracy is stated against the
+FP64 oracle's stored results on the batch's sixteen stratified signals
+(tests/golden/uneven_oracle.json).
 
-Other workloads (--workload): small1d (1000 signals n=256 m=64 k=8), image
-(256 columns sharing A, sampling rate 0.1/0.3/0.5), image4k (3840 columns of
-n=2160 sharing A, k=108: the shared-dictionary schedule), uneven (4096 signals of
-uneven size, BF16 bulk + FP32 master), flat (n=65536, m=19661, k=2048, BF16
-CLOMP vs FP32 OMP).
+Other workloads (--workload): large1d (one signal n=16384, m=4096, k=256,
+float32: every iteration streams the whole 268 MB dictionary), small1d (1000
+signals n=256 m=64 k=8), image (256 columns sharing A, sampling rate
+0.1/0.3/0.5), image4k (3840 columns of n=2160 sharing A, k=108: the
+shared-dictionary schedule), flat (n=65536, m=19661, k=2048, BF16 CLOMP vs
+FP32 OMP).
 
 A step is one full solve of the workload's batch (k greedy iterations,
 refinement, FP64 residual norm) through the C ABI, inputs resident in HBM.
 W untimed warm-up steps, then K timed steps between device synchronisations.
 Prints one JSON line.
 
-    python bench.py [--workload large1d] [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--workload uneven] [--steps K] [--warmup W] [--gpus 1]
                     [--no-cpu-baseline] [--no-graph]
 """
 
@@ -41,14 +45,20 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="large1d",
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 5 for the uneven and flat workloads, else 30)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps (default: 1 for the uneven and flat workloads, else 3)")
+    ap.add_argument("--workload", default="uneven",
                     choices=["large1d", "small1d", "image", "image4k", "uneven", "flat"])
     ap.add_argument("--sr", type=float, default=0.3, help="image workload sampling rate")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-iht", action="store_true", help="skip the IHT comparison leg")
+    ap.add_argument("--iht", action="store_true",
+                    help="uneven workload: also run the IHT leg (off by default there)")
+    ap.add_argument("--paper", action="store_true",
+                    help="uneven workload: also run the paper-mode leg (off by default there)")
     ap.add_argument("--no-paper", action="store_true",
                     help="skip the paper-mode CLOMP leg (T_h = 0.7, 200 iterations)")
     ap.add_argument("--flow", default="auto", choices=["auto", "resid", "corr"],
@@ -58,7 +68,13 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 5 device copies of 1 GiB (reference for HBM counters)")
-    return ap.parse_args()
+    args = ap.parse_args()
+    big = args.workload in ("uneven", "flat")
+    if args.steps is None:
+        args.steps = 5 if big else 30
+    if args.warmup is None:
+        args.warmup = 1 if big else 3
+    return args
 
 
 def copy_calibration(torch):
@@ -276,7 +292,16 @@ def main():
     log(f"workload {args.workload}")
     wl = build_workload(args, torch, W)
     torch.cuda.synchronize()
-    stream = torch.cuda.Stream(torch.device("cuda", 0))
+    # the uneven batch launches eagerly on the current stream (no graph
+    # capture) and runs only the CLOMP and OMP legs unless --iht / --paper ask
+    # for more; the other workloads replay captured graphs on a created stream
+    uneven = wl["name"] == "uneven"
+    if uneven:
+        args.no_graph = True
+        args.no_iht = not args.iht
+        args.no_paper = not args.paper
+    stream = (torch.cuda.current_stream(torch.device("cuda", 0)) if args.no_graph
+              else torch.cuda.Stream(torch.device("cuda", 0)))
     flow_flag = {"auto": 0, "resid": C.FLAG_RESIDUAL_FLOW, "corr": C.FLAG_CORR_FLOW}[args.flow]
     flow_flag |= C.FLAG_NO_SHARED_GRAM if args.no_shared_gram else 0
     flags = (0 if args.no_graph else C.FLAG_GRAPH) | flow_flag
@@ -327,7 +352,9 @@ def main():
         ps.close()
 
     acc, cpu = {}, None
-    if wl["name"] == "large1d":
+    if wl["name"] == "uneven":
+        acc, cpu = accuracy_uneven(args, wl, outs)
+    elif wl["name"] == "large1d":
         acc, cpu = accuracy_large1d(args, wl, outs)
     elif wl["name"] == "small1d" and not args.no_cpu_baseline:
         acc, cpu = accuracy_batch_sample(wl, outs, n_sample=200)
@@ -380,6 +407,87 @@ def main():
 def _threads():
     from threadpoolctl import threadpool_info
     return int(max([p.get("num_threads", 1) for p in threadpool_info()] or [1]))
+
+
+UNEVEN_CPU_STRATA = (2, 6, 10)   # golden-sample positions timed for the CPU baseline
+
+
+def accuracy_uneven(args, wl, outs):
+    """The batch's sixteen stratified signals (drawn on the host, one per
+    sixteenth of the batch sorted by n) against the FP64 oracle's stored
+    results, and the oracle timed on a bounded stratified sample of them as
+    the CPU baseline (all host threads, then one)."""
+    from paper_2501_11592_amd import workloads as W
+    specs = wl["host"][0]
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "uneven_oracle.json")))
+    acc = {}
+    for method in ("clomp", "omp"):
+        o = outs[method]
+        rows = []
+        for rec in gold["instances"]:
+            i, g = rec["index"], rec[method]
+            S = o.support[i][: int(o.n_selected[i])].cpu().tolist()
+            xr = np.zeros(rec["n"])
+            xr[g["support"]] = g["x_support"]
+            x = o.x[i].cpu().numpy().astype(np.float64)
+            rows.append((S == g["support"], bool(g["separated_fp32"]),
+                         float(np.linalg.norm(x - xr) / np.linalg.norm(xr))))
+        same = [e for ok, _, e in rows if ok]
+        acc[method] = {
+            "rel_err": float(max(same)) if same else None,
+            "rel_err_median": float(np.median(same)) if same else None,
+            "rel_err_all_max": float(max(e for _, _, e in rows)),
+            "support_identical_fraction": len(same) / len(rows),
+            "separated_fraction": sum(sep for _, sep, _ in rows) / len(rows),
+            "sample": f"{len(rows)} stratified signals of the batch (one per sixteenth by n, "
+                      "n = 564 .. 8189) against the stored FP64 oracle results; rel_err over "
+                      "the signals whose ordered support equals the oracle's"}
+    cpu = None if args.no_cpu_baseline else cpu_baseline_uneven(specs, gold, W)
+    return acc, cpu
+
+
+def cpu_baseline_uneven(specs, gold, W):
+    """The FP64 CLOMP oracle (selection and Adam on the stored bfloat16
+    values, least squares on the float32 master) timed on a stratified sample
+    of the golden signals, with every host thread and with one, and scaled to
+    the whole batch by sum(k m n) (an extrapolation: the sample's time times
+    the batch's sum of k m n over the sample's)."""
+    from oracle import clomp_fp64, ClompParams
+    from threadpoolctl import threadpool_limits
+    params = ClompParams(inner_steps=32, lr_rel=f32(0.05), beta1=f32(0.9), beta2=f32(0.999),
+                         eps_rel=f32(1e-8))
+    recs = [gold["instances"][q] for q in UNEVEN_CPU_STRATA]
+    cases = []
+    for rec in recs:
+        i = rec["index"]
+        sig = W.uneven_instance_golden(i, specs[i])
+        m = specs[i].m
+        cases.append((W.bf16_values(sig.At[:, :m]).astype(np.float64).T,
+                      sig.At[:, :m].astype(np.float64).T, sig.y.astype(np.float64), sig.k))
+
+    def timed():
+        t0 = time.perf_counter()
+        for Ab, Am, y, k in cases:
+            clomp_fp64(Ab, y, k, params, A_refine=Am)
+        return time.perf_counter() - t0
+
+    kmn = lambda sp: float(sp.k) * sp.m * sp.n
+    scale = sum(kmn(sp) for sp in specs) / sum(kmn(specs[r["index"]]) for r in recs)
+    log(f"timing the FP64 oracle on {len(cases)} stratified signals (all threads, then one)")
+    threads = _threads()
+    t_all = timed()
+    with threadpool_limits(limits=1):
+        t_one = timed()
+    desc = ", ".join(f"n={specs[r['index']].n} m={specs[r['index']].m} k={specs[r['index']].k}"
+                     for r in recs)
+    return {"value": len(specs) / (t_all * scale), "unit": "signals/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{len(cases)} stratified signals of the batch ({desc}) solved by the FP64 "
+                      f"CLOMP oracle in {t_all:.1f} s, extrapolated to the 4096 signals by "
+                      f"sum(k*m*n) (factor {scale:.0f})",
+            "seconds": t_all, "host_cpus": os.cpu_count(),
+            "one_core": {"value": len(specs) / (t_one * scale), "unit": "signals/s", "cores": 1,
+                         "seconds": t_one}}
 
 
 def accuracy_large1d(args, wl, outs):

@@ -63,6 +63,8 @@ struct Class {
   int nslice = 1;                     // IHT: most m-slices of any signal of the class
   int slice_floats = 0;               // IHT: largest slice of r (floats, LDS)
   size_t htile_off = 0, ctile_off = 0;
+  int team_occ = 0;                   // coefficient-team workgroups per CU at the class's
+                                      // largest team LDS (0: no teams)
 };
 
 struct Plan {
@@ -284,6 +286,16 @@ bool same_dictionary(const clomp_instance_t* inst, const std::vector<int>& order
       return false;
   }
   return true;
+}
+
+// Coefficient-team workgroups one CU can hold (cached per launch shape).
+int team_occupancy(clomp_ctx* h, int bf16, int lpa, int omp, size_t lds) {
+  const long long key = ((long long)lds << 16) | (bf16 << 12) | (omp << 8) | lpa;
+  auto it = h->team_occ.find(key);
+  if (it != h->team_occ.end()) return it->second;
+  const int nb = coef_team_blocks_per_cu(bf16, lpa, omp, lds);
+  h->team_occ[key] = nb;
+  return nb;
 }
 
 // Build the plan (host tables + workspace layout) for one batch.
@@ -555,6 +567,17 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
       while (nch < per_lane) nch <<= 1;
       c.nch = (nch * vw <= 64) ? nch : 0;   // at most 64 floats of r per lane
     }
+    // coefficient teams (correlation-update schedule): the occupancy query
+    // runs here, before any launch or capture, at the largest LDS a team
+    // launch of the class can ask for (occupancy does not grow with LDS)
+    if (P.hflow && c.kmax > h->team_min_rows) {
+      const bool omp = prm.method == CLOMP_METHOD_OMP;
+      const size_t t1 = (size_t)c.kmax;
+      size_t tl = std::max((size_t)c.m_pad_max, (omp ? 6 : 1) * t1);
+      if (!omp && t1 > 256) tl = std::max(tl, (size_t)2048);
+      tl = std::max(tl, t1 + 4 + 32);
+      c.team_occ = team_occupancy(h, bf16, c.lpa, omp ? 1 : 0, tl * sizeof(float));
+    }
     P.classes.push_back(std::move(c));
   }
   // fused signals: row tiles (for the norm) and the launch list
@@ -685,16 +708,6 @@ struct PhaseScope {
   }
 };
 
-// Coefficient-team workgroups one CU can hold (cached per launch shape).
-int team_occupancy(clomp_ctx* h, int bf16, int lpa, int omp, size_t lds) {
-  const long long key = ((long long)lds << 16) | (bf16 << 12) | (omp << 8) | lpa;
-  auto it = h->team_occ.find(key);
-  if (it != h->team_occ.end()) return it->second;
-  const int nb = coef_team_blocks_per_cu(bf16, lpa, omp, lds);
-  h->team_occ[key] = nb;
-  return nb;
-}
-
 // Greedy loop of the correlation-update schedule.
 clomp_status_t launch_hflow(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st) {
   const clomp_params_t& prm = h->params;
@@ -766,11 +779,11 @@ clomp_status_t launch_hflow(clomp_ctx* h, const Plan& P, int bf16, hipStream_t s
           const int want = (int)((t1 + 15) / 16);
           const size_t tlds = std::max(lds, (t1 + 4 + 32) * sizeof(float));
           // members wait for one another, so all of them must be resident at
-          // once: the occupancy query must admit a member per CU (launch shape
-          // and LDS), and the teams of all active signals stay below the CU
+          // once: the occupancy query (taken when the plan was built, never
+          // inside a launch sequence that may be captured) must admit a member
+          // per CU, and the teams of all active signals stay below the CU
           // count; otherwise the single-workgroup update runs
-          if (want <= kTeamMax && (long long)want * nact <= h->num_cu - 8 &&
-              team_occupancy(h, bf16, c.lpa, omp, tlds) >= 1) {
+          if (want <= kTeamMax && (long long)want * nact <= h->num_cu - 8 && c.team_occ >= 1) {
             W = want;
             lds = tlds;
           }

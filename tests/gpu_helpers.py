@@ -49,6 +49,22 @@ def rel_err(x, ref):
     return np.linalg.norm(x - ref) / (nr if nr > 0 else 1.0)
 
 
+def coef_err(x, ref, floor=1e-2):
+    """Per-coefficient companion of rel_err: the largest relative error over
+    the significant coefficients of ref (|ref_j| >= floor * max |ref|), and
+    the largest absolute error of any coefficient relative to ||ref||_2.  A
+    normwise gate alone lets a small coefficient be wrong by 100%."""
+    ref = np.asarray(ref, np.float64)
+    x = np.asarray(x, np.float64)
+    top = np.abs(ref).max() if ref.size else 0.0
+    if top == 0.0:
+        return 0.0, float(np.abs(x).max() if x.size else 0.0)
+    sig = np.abs(ref) >= floor * top
+    rel = float(np.max(np.abs(x[sig] - ref[sig]) / np.abs(ref[sig])))
+    absn = float(np.max(np.abs(x - ref)) / np.linalg.norm(ref))
+    return rel, absn
+
+
 def fp64_resid(A, y, supp, x):
     S = list(supp)
     return float(np.linalg.norm(np.asarray(y, np.float64) - A[:, S] @ np.asarray(x, np.float64)[S]))

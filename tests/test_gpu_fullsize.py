@@ -20,7 +20,7 @@ import torch
 from oracle import clomp_fp64, omp_fp64, lstsq_support, resid_norm_fp64, well_separated
 from paper_2501_11592_amd import clomp as C
 from paper_2501_11592_amd import workloads as W
-from tests.gpu_helpers import PARAMS, BF16_DELTA, BF16_U, rel_err
+from tests.gpu_helpers import PARAMS, BF16_DELTA, BF16_U, coef_err, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -59,47 +59,99 @@ def test_large1d_against_committed_oracle(method, flow):
     solver.close()
 
 
-def test_uneven_batch_full_size_sampled():
-    """All 4096 signals of the uneven batch (BF16 bulk, FP32 master) in one
-    call; twelve sampled signals solved whole by the oracle (selection on the
-    BF16 values, refinement on the master) and every signal checked for the
-    refinement and norm properties on a sample of 64."""
-    specs, items, supps, coefs = W.uneven_batch_device(4096, "cuda")
-    solver = C.Solver(0, method="clomp")
-    out = solver.solve_batch(items)
+UNEVEN_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "uneven_oracle.json")
+
+
+def _solve_like_bench(method, items, flags=0):
+    """The benchmark's launch configuration of the uneven batch: prepared
+    once, launched eagerly on the current stream, checked on the second
+    launch (which reuses the cached plan)."""
+    print(f"uneven batch: {method} flags {flags}", flush=True)
+    solver = C.Solver(0, method=method, flags=flags)
+    prep = solver.prepare(items)
+    solver.run(prep)
+    out = solver.run(prep)
     torch.cuda.synchronize()
+    return solver, out
+
+
+def test_uneven_batch_against_committed_oracle():
+    """All 4096 signals of the uneven batch (BF16 bulk, FP32 master) in one
+    call, launched as the benchmark launches them.  The sixteen stratified signals drawn on
+    the host (one per sixteenth of the batch sorted by n, up to n = 8189) are
+    compared with the oracle's stored results: the ordered support over each
+    signal's separated prefix (the whole support when separated), the final
+    x normwise and per coefficient, and the learned coefficients before the
+    refinement.  Every signal is checked for the refinement and norm
+    properties on a sample of 64."""
+    gold = json.load(open(UNEVEN_GOLDEN))
+    specs, items, supps, coefs = W.uneven_batch_device(4096, "cuda")
+    # the stored results were computed on exactly these host draws
+    for rec in gold["instances"]:
+        i = rec["index"]
+        sig = W.uneven_instance_golden(i, specs[i])
+        assert W.fingerprint(sig.At) == rec["A_sha256"] and W.fingerprint(sig.y) == rec["y_sha256"]
     keff = np.array([min(s.k, s.m, s.n) for s in specs])
-    assert (out.n_selected.cpu().numpy() == keff).all()
-    assert (out.status.cpu().numpy() & ~C.ST_K_CAPPED == 0).all()
+    outs = {}
+    for method in ("clomp", "omp"):
+        solver, out = _solve_like_bench(method, items)
+        outs[method] = out
+        assert (out.n_selected.cpu().numpy() == keff).all()
+        assert (out.status.cpu().numpy() & ~C.ST_K_CAPPED == 0).all()
+        solver.close()
+    # the Adam iterate itself (x before the refinement)
+    solver, raw = _solve_like_bench("clomp", items, C.FLAG_NO_REFINE)
+    solver.close()
     order = np.argsort([s.n * s.k for s in specs])
-    # refinement / norm properties on 64 signals spread over the size range
     for i in order[:: len(order) // 64]:
         it, sp = items[i], specs[i]
         Am = _vec(it["At_master"][:, : sp.m]).T
         yv = _vec(it["y"])
+        out = outs["clomp"]
         S = out.support[i][: int(out.n_selected[i])].cpu().tolist()
         x = _vec(out.x[i])
         xs = lstsq_support(Am, yv, S)
         assert rel_err(x[S], xs) <= 1e-5, (i, rel_err(x[S], xs))
         assert abs(float(out.resid_norm[i]) - resid_norm_fp64(Am, yv, S, x[S])) <= 1e-9 * (
             1 + np.linalg.norm(yv))
-    # whole solves by the oracle on twelve of the smaller signals
-    ident = 0
-    for i in order[: 600: 50]:
-        it, sp = items[i], specs[i]
-        Am = _vec(it["At_master"][:, : sp.m]).T
-        Ab = _vec(it["At"][:, : sp.m].float()).T
-        yv = _vec(it["y"])
-        ref = clomp_fp64(Ab, yv, sp.k, PARAMS, A_refine=Am)
-        ok, _ = well_separated(Ab, yv, sp.k, params=PARAMS, delta=BF16_DELTA, u=BF16_U,
-                               A_refine=Am, base=ref)
-        S = out.support[i][: int(out.n_selected[i])].cpu().tolist()
-        if ok:
-            assert S == ref.support, i
-            assert rel_err(_vec(out.x[i]), ref.x) <= 1e-3
-            ident += 1
-    print(f"uneven: {ident} of 12 sampled signals well separated and identical")
-    solver.close()
+    report = {"clomp": [], "omp": []}
+    for rec in gold["instances"]:
+        i, k = rec["index"], rec["k"]
+        for method in ("clomp", "omp"):
+            g, out = rec[method], outs[method]
+            S = out.support[i][: int(out.n_selected[i])].cpu().tolist()
+            pre = g["separated_prefix_fp32"]
+            # the library and the oracle see the same stored bfloat16 values:
+            # the float32 gates decide where the selections must agree
+            assert S[:pre] == g["support"][:pre], (method, i, pre)
+            same = S == g["support"]
+            xr = np.zeros(rec["n"])
+            xr[g["support"]] = g["x_support"]
+            x = _vec(out.x[i])
+            e = rel_err(x, xr)
+            ce, ca = coef_err(x, xr)
+            row = dict(index=i, n=rec["n"], separated=g["separated_fp32"], identical=same,
+                       rel_err=e, coef_rel_err=ce, coef_abs_err=ca)
+            if g["separated_fp32"]:
+                assert same, (method, i)
+                assert e <= 1e-3 and ce <= 1e-2 and ca <= 1e-3, (method, i, e, ce, ca)
+            if method == "clomp" and same:
+                xa = _vec(raw.x[i])[g["support"]]
+                row["s_adam_rel_err"] = rel_err(xa, np.asarray(g["s_adam"]))
+            report[method].append(row)
+    for method, rows in report.items():
+        sep = sum(r["separated"] for r in rows)
+        ident = sum(r["identical"] for r in rows)
+        errs = [r["rel_err"] for r in rows if r["identical"]]
+        print(f"uneven {method}: ordered support identical {ident}/{len(rows)} "
+              f"(separated {sep}); rel.err max {max(errs):.2e} median {np.median(errs):.2e}")
+        # the agreement floor: every separated signal (12 of the 16 for each
+        # method in the stored results)
+        assert sep >= 12 and ident >= sep
+    adam = [r["s_adam_rel_err"] for r in report["clomp"] if "s_adam_rel_err" in r]
+    print(f"uneven clomp: Adam iterate rel.err max {max(adam):.2e} median {np.median(adam):.2e} "
+          f"over {len(adam)} signals")
+    assert max(adam) <= 1e-3
 
 
 def test_flat_image_full_size():

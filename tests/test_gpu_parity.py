@@ -163,6 +163,38 @@ def test_coefficient_teams(method):
     single.close()
 
 
+@pytest.mark.parametrize("method", ["clomp", "omp"])
+def test_team_watchdog_forced_from_host(method):
+    """The bounded team wait, forced to give up from the host: a spin limit of
+    one poll per wait.  Some signal must carry CLOMP_ST_WATCHDOG, every kernel
+    must still finish (the device synchronises without error), and with the
+    default limit restored the same handle solves exactly as a fresh one."""
+    sigs = [W.single_small(200 + i, n=2048, m=384, k=80) for i in range(4)]
+    items = _items(sigs)
+    team = C.Solver(0, method=method, flags=C.FLAG_CORR_FLOW)
+    team.set_tuning(team_min_rows=16, spin_limit=1)
+    assert team.get_tuning()["spin_limit"] == 1
+    out = team.solve_batch(items)
+    torch.cuda.synchronize()
+    st = out.status.cpu().numpy()
+    print(f"{method}: status bits with spin_limit 1: {st.tolist()}")
+    assert (st & C.ST_WATCHDOG).any()
+    assert ((st & ~(C.ST_WATCHDOG | C.ST_REFINE_INACCURATE)) == 0).all()
+    team.set_tuning(spin_limit=-1)
+    assert team.get_tuning()["spin_limit"] == 1 << 20
+    again = team.solve_batch(items)
+    fresh = C.Solver(0, method=method, flags=C.FLAG_CORR_FLOW)
+    fresh.set_tuning(team_min_rows=16)
+    ref = fresh.solve_batch(items)
+    torch.cuda.synchronize()
+    assert (again.status.cpu().numpy() == 0).all()
+    for i in range(len(sigs)):
+        assert torch.equal(again.support[i], ref.support[i])
+        assert torch.equal(again.x[i], ref.x[i])
+    team.close()
+    fresh.close()
+
+
 @pytest.mark.parametrize("flow", ["resid", "corr"])
 def test_autotune_matches_default(flow):
     """CLOMP_FLAG_AUTOTUNE times the candidate tile sizes on the first call of a
@@ -347,6 +379,42 @@ def test_grad_fp64_gradcheck_and_autograd(solvers):
     loss.backward()
     np.testing.assert_allclose(x.grad.cpu().numpy(), g64, rtol=1e-12, atol=1e-12)
     assert abs(loss.item() - l64) <= 1e-12 * max(1, l64)
+
+
+def test_grad_fp64_gradcheck_uneven_instances():
+    """FP64 gradcheck of the hand-written backward on the eight smallest
+    instances of the uneven batch's size distribution (n log-uniform in
+    [512, 8192], m/n in [0.1, 0.5], k in [n/64, n/16]): A iid N(0, 1/m), mask
+    on k random atoms, random x and y; and the gradient against the oracle's
+    to 1e-12."""
+    from oracle import grad_fp64
+    specs = W.uneven_specs(4096)
+    order = np.argsort([sp.n for sp in specs], kind="stable")[:8]
+    for i in order:
+        sp = specs[i]
+        g = np.random.default_rng([2501, 11592, 4, int(i), 9])
+        A = g.standard_normal((sp.m, sp.n)) / math.sqrt(sp.m)
+        lda = W.pad_lda(sp.m, 8)
+        At_h = np.zeros((sp.n, lda))
+        At_h[:, :sp.m] = A.T
+        mask_h = np.zeros(sp.n, np.uint8)
+        mask_h[g.choice(sp.n, sp.k, replace=False)] = 1
+        x_h, y_h = g.standard_normal(sp.n), g.standard_normal(sp.m)
+        At = dev(At_h)
+        mask = dev(mask_h)
+        x = dev(x_h).requires_grad_(True)
+        y = dev(y_h).requires_grad_(True)
+        print(f"gradcheck: uneven instance {i} n={sp.n} m={sp.m} k={sp.k}", flush=True)
+        f = lambda xx, yy: C.ClompLoss.apply(xx, mask, At, sp.m, yy)
+        assert torch.autograd.gradcheck(f, (x, y), eps=1e-6, atol=1e-8, rtol=1e-6)
+        l64, g64, u64 = grad_fp64(x_h, mask_h, A, y_h)
+        loss = f(x, y)
+        loss.backward()
+        np.testing.assert_allclose(x.grad.cpu().numpy(), g64, rtol=1e-12,
+                                   atol=1e-12 * np.abs(g64).max())
+        np.testing.assert_allclose(y.grad.cpu().numpy(), -u64, rtol=1e-12,
+                                   atol=1e-12 * np.abs(u64).max())
+        assert abs(loss.item() - l64) <= 1e-12 * l64
 
 
 def test_abi_errors_on_device(solvers):
