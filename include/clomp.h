@@ -259,6 +259,31 @@ clomp_status_t clomp_grad(clomp_handle_t h, int32_t n, int32_t m, int64_t lda,
                           void* loss, void* hip_stream);
 
 /*
+ * Allocation-free variant of clomp_grad, for callers that cannot allocate
+ * device memory during the call: code under HIP graph capture, tight serving
+ * loops, hosts that forbid allocation after start-up.  Same arguments, same
+ * kernels and the same results, bit for bit, as clomp_grad; its scratch (the
+ * forward partial sums and, when resid_out is NULL, the residual) is a
+ * device-resident array of 16 MiB per device, resolved once by clomp_create
+ * on the handle's device and held until the process ends.  The call allocates
+ * nothing and records no event.
+ *   Limit: es * (ceil(n / 256) * m + m + ceil(m / 256)) <= 16 MiB, es = 4
+ *   (F32) or 8 (F64); e.g. n = 65536 with m <= 16320 (F32).
+ *   Races: every call on one device shares that device's scratch; calls whose
+ *   work can overlap on one device (two streams, two host threads, two
+ *   handles) must be ordered by the caller.  Nothing in the scratch needs to
+ *   start at zero, and the previous call's contents are overwritten.
+ * Errors: as clomp_grad, plus INVALID_ARGUMENT when the call needs more
+ * scratch than the limit (nothing is launched), DEVICE_ERROR when the scratch
+ * address of the handle's device is unknown.
+ */
+clomp_status_t clomp_grad_noalloc(clomp_handle_t h, int32_t n, int32_t m, int64_t lda,
+                                  int32_t dtype, const void* A, const void* x,
+                                  const uint8_t* mask, const void* y,
+                                  const void* grad_out, void* grad_x, void* resid_out,
+                                  void* loss, void* hip_stream);
+
+/*
  * Schedules.  Signals with k_eff <= 64 whose dictionary fits in LDS run the
  * fused small-signal loop (one launch for the whole greedy loop of all of
  * them).  The others are iterated, one launch sequence per iteration: the

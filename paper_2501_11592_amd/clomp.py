@@ -117,6 +117,8 @@ def load_library(path=LIB_PATH):
     lib.clomp_grad.argtypes = [H, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
                                ctypes.c_int32] + [ctypes.c_void_p] * 9
     lib.clomp_grad.restype = ctypes.c_int
+    lib.clomp_grad_noalloc.argtypes = lib.clomp_grad.argtypes
+    lib.clomp_grad_noalloc.restype = ctypes.c_int
     lib.clomp_profile_read.argtypes = [H, ctypes.POINTER(Profile)]
     lib.clomp_profile_read.restype = ctypes.c_int
     lib.clomp_profile_reset.argtypes = [H]
@@ -388,8 +390,12 @@ class Solver:
         return self.solve_batch(items, stream)
 
     # ------------------------------------------------------------------ grad
-    def grad(self, At, m, x, mask, y, grad_out=None, want_resid=True, stream=None):
-        """Returns (loss, grad_x, u) with u = A(mask*x) - y."""
+    def grad(self, At, m, x, mask, y, grad_out=None, want_resid=True, stream=None,
+             out=None, noalloc=False):
+        """Returns (loss, grad_x, u) with u = A(mask*x) - y.  out: optional
+        (loss, grad_x, u) tensors to write (u may be None).  noalloc: call
+        clomp_grad_noalloc, whose scratch is the library's device-resident
+        array (no allocation inside the call)."""
         dev = self.device
         kinds = (torch.float32, torch.float64)
         _check_atoms("At", At, dev, kinds, int(m))
@@ -402,14 +408,23 @@ class Solver:
             mask = mask.view(torch.uint8)
         if grad_out is not None:
             _check_vec("grad_out", grad_out, dev, (At.dtype,), 1)
-        gx = torch.empty(n, dtype=At.dtype, device=dev)
-        loss = torch.empty((), dtype=At.dtype, device=dev)
-        u = torch.empty(m, dtype=At.dtype, device=dev) if want_resid else None
+        if out is None:
+            gx = torch.empty(n, dtype=At.dtype, device=dev)
+            loss = torch.empty((), dtype=At.dtype, device=dev)
+            u = torch.empty(m, dtype=At.dtype, device=dev) if want_resid else None
+        else:
+            loss, gx, u = out
+            _check_vec("loss", loss, dev, (At.dtype,), 1)
+            _check_vec("grad_x", gx, dev, (At.dtype,), n)
+            if u is not None:
+                _check_vec("u", u, dev, (At.dtype,), int(m))
         st = stream if stream is not None else torch.cuda.current_stream(dev)
-        rc = load_library().clomp_grad(self._h, n, m, int(At.stride(0)), dt, _ptr(At), _ptr(x),
-                                       _ptr(mask), _ptr(y), _ptr(grad_out), _ptr(gx), _ptr(u),
-                                       _ptr(loss), ctypes.c_void_p(st.cuda_stream))
-        _check(self._h, rc, "clomp_grad")
+        lib = load_library()
+        fn, name = ((lib.clomp_grad_noalloc, "clomp_grad_noalloc") if noalloc
+                    else (lib.clomp_grad, "clomp_grad"))
+        rc = fn(self._h, n, m, int(At.stride(0)), dt, _ptr(At), _ptr(x), _ptr(mask), _ptr(y),
+                _ptr(grad_out), _ptr(gx), _ptr(u), _ptr(loss), ctypes.c_void_p(st.cuda_stream))
+        _check(self._h, rc, name)
         return loss, gx, u
 
 

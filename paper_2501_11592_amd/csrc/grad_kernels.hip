@@ -7,8 +7,16 @@
 //   bwd          grad_j = mask_j * (a_j^T u) * g;  loss = 1/2 sum of partials
 // Instantiated for float and double (double serves gradient checking).
 
+#include <mutex>
+
 #include "dev_common.h"
 #include "kernels.h"
+
+// Scratch of the allocation-free gradient entry point: the column-chunk
+// partials, the residual when the caller passes none, and the loss partials.
+// One copy per device, resident until the process ends; host code reaches it
+// only through the address resolved per device by grad_scratch_init.
+static __device__ __align__(256) unsigned char scratch[clomp::kGradScratchBytes];
 
 namespace clomp {
 
@@ -110,6 +118,29 @@ static hipError_t grad_impl(int n, int m, long long lda, const void* A, const vo
                      (const T*)A, mask, (const T*)u, (const T*)grad_out, (T*)grad_x,
                      (const T*)lpart, nfin, (T*)loss);
   return hipGetLastError();
+}
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+hipError_t grad_scratch_init(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = p;
+  return hipSuccess;
+}
+
+void* grad_scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
 }
 
 hipError_t launch_grad(int f64, int n, int m, long long lda, const void* A, const void* x,

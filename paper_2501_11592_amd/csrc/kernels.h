@@ -112,5 +112,13 @@ hipError_t launch_grad(int f64, int n, int m, long long lda, const void* A, cons
                        const unsigned char* mask, const void* y, const void* grad_out,
                        void* grad_x, void* resid_out, void* loss, void* work, int ncolchunk,
                        int colchunk, hipStream_t s);
+// Allocation-free gradient: a device-resident scratch array of
+// kGradScratchBytes per device.  grad_scratch_init resolves its address on
+// `device` (which must be current) once; grad_scratch_ptr returns it (NULL
+// before init).
+constexpr size_t kGradScratchBytes = (size_t)16 << 20;
+constexpr int kMaxScratchDevices = 64;
+hipError_t grad_scratch_init(int device);
+void* grad_scratch_ptr(int device);
 
 }  // namespace clomp

@@ -1354,6 +1354,13 @@ clomp_status_t clomp_create(clomp_handle_t* out, int device, const clomp_params_
     (void)hipGetLastError();
     h->lds_limit = 65536;
   }
+  // the allocation-free gradient's scratch: its address on this device, once
+  if (grad_scratch_init(device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete h;
+    (void)hipSetDevice(prev);
+    return CLOMP_DEVICE_ERROR;
+  }
   h->pass_lds_ok = set_max_lds_pass((size_t)h->lds_limit) == hipSuccess;
   if (!h->pass_lds_ok) (void)hipGetLastError();
   if (hipEventCreateWithFlags(&h->staging_free, hipEventDisableTiming) != hipSuccess ||
@@ -1494,12 +1501,16 @@ clomp_status_t clomp_solve_batch(clomp_handle_t h, const clomp_instance_t* inst,
   return CLOMP_OK;
 }
 
-clomp_status_t clomp_grad(clomp_handle_t h, int32_t n, int32_t m, int64_t lda, int32_t dtype,
-                          const void* A, const void* x, const uint8_t* mask, const void* y,
-                          const void* grad_out, void* grad_x, void* resid_out, void* loss,
-                          void* hip_stream) {
-  if (!h) return CLOMP_INVALID_ARGUMENT;
-  if (dtype == CLOMP_BF16) return fail(h, CLOMP_NOT_SUPPORTED, "clomp_grad serves F32 and F64");
+namespace {
+constexpr int kGradColChunk = 256;   // atoms per forward partial of clomp_grad
+
+// Argument checks shared by both gradient entry points; *need receives the
+// scratch bytes of the call.
+clomp_status_t check_grad_args(clomp_ctx* h, const char* fn, int32_t n, int32_t m, int64_t lda,
+                               int32_t dtype, const void* A, const void* x, const uint8_t* mask,
+                               const void* y, const void* grad_x, const void* loss,
+                               size_t* need) {
+  if (dtype == CLOMP_BF16) return fail(h, CLOMP_NOT_SUPPORTED, "%s serves F32 and F64", fn);
   if (dtype != CLOMP_F32 && dtype != CLOMP_F64)
     return fail(h, CLOMP_INVALID_ARGUMENT, "unknown dtype %d", dtype);
   if (n <= 0 || m <= 0 || lda < m) return fail(h, CLOMP_INVALID_ARGUMENT, "bad n, m or lda");
@@ -1508,10 +1519,25 @@ clomp_status_t clomp_grad(clomp_handle_t h, int32_t n, int32_t m, int64_t lda, i
   const size_t es = dtype == CLOMP_F64 ? 8 : 4;
   if (((uintptr_t)A % es) || ((uintptr_t)x % es) || ((uintptr_t)y % es))
     return fail(h, CLOMP_INVALID_ARGUMENT, "A, x and y must be aligned to their element size");
-  const int colchunk = 256;
+  const size_t ncolchunk = ((size_t)n + kGradColChunk - 1) / kGradColChunk;
+  const size_t nfin = ((size_t)m + kBlock - 1) / kBlock;
+  *need = es * (ncolchunk * (size_t)m + (size_t)m + nfin);
+  return CLOMP_OK;
+}
+}  // namespace
+
+clomp_status_t clomp_grad(clomp_handle_t h, int32_t n, int32_t m, int64_t lda, int32_t dtype,
+                          const void* A, const void* x, const uint8_t* mask, const void* y,
+                          const void* grad_out, void* grad_x, void* resid_out, void* loss,
+                          void* hip_stream) {
+  if (!h) return CLOMP_INVALID_ARGUMENT;
+  size_t need = 0;
+  const clomp_status_t cs =
+      check_grad_args(h, "clomp_grad", n, m, lda, dtype, A, x, mask, y, grad_x, loss, &need);
+  if (cs != CLOMP_OK) return cs;
+  need += 256;
+  const int colchunk = kGradColChunk;
   const int ncolchunk = (n + colchunk - 1) / colchunk;
-  const size_t nfin = (m + kBlock - 1) / kBlock;
-  const size_t need = es * ((size_t)ncolchunk * m + m + nfin) + 256;
   DeviceGuard dg;
   HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
@@ -1528,6 +1554,32 @@ clomp_status_t clomp_grad(clomp_handle_t h, int32_t n, int32_t m, int64_t lda, i
           "grad");
   HIP_TRY(hipEventRecord(h->grad_done, st), "hipEventRecord");
   h->have_grad = true;
+  return CLOMP_OK;
+}
+
+clomp_status_t clomp_grad_noalloc(clomp_handle_t h, int32_t n, int32_t m, int64_t lda,
+                                  int32_t dtype, const void* A, const void* x,
+                                  const uint8_t* mask, const void* y, const void* grad_out,
+                                  void* grad_x, void* resid_out, void* loss, void* hip_stream) {
+  if (!h) return CLOMP_INVALID_ARGUMENT;
+  size_t need = 0;
+  const clomp_status_t cs = check_grad_args(h, "clomp_grad_noalloc", n, m, lda, dtype, A, x,
+                                            mask, y, grad_x, loss, &need);
+  if (cs != CLOMP_OK) return cs;
+  if (need > kGradScratchBytes)
+    return fail(h, CLOMP_INVALID_ARGUMENT,
+                "clomp_grad_noalloc needs %zu bytes of scratch for n = %d, m = %d; its "
+                "device-resident scratch holds %zu (use clomp_grad)",
+                need, n, m, kGradScratchBytes);
+  void* work = grad_scratch_ptr(h->device);
+  if (!work) return fail(h, CLOMP_DEVICE_ERROR, "scratch address of device %d unresolved",
+                         h->device);
+  DeviceGuard dg;
+  HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  HIP_TRY(launch_grad(dtype == CLOMP_F64, n, m, lda, A, x, mask, y, grad_out, grad_x, resid_out,
+                      loss, work, (n + kGradColChunk - 1) / kGradColChunk, kGradColChunk, st),
+          "grad");
   return CLOMP_OK;
 }
 
