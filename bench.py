@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--workload", default="uneven",
                     choices=["large1d", "small1d", "image", "image4k", "uneven", "flat"])
     ap.add_argument("--sr", type=float, default=0.3, help="image workload sampling rate")
+    ap.add_argument("--bf16", action="store_true",
+                    help="image4k: BF16 bulk copy of A with the float32 values as master")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-iht", action="store_true", help="skip the IHT comparison leg")
@@ -138,12 +140,21 @@ def build_workload(args, torch, W):
         b = W.image4k_batch(args.sr)
         At = torch.from_numpy(b.At).to(dev)
         Y = torch.from_numpy(b.Y).to(dev)
-        items = [dict(At=At, m=b.m, y=Y[c], k=b.k) for c in range(Y.shape[0])]
+        if args.bf16:
+            # BF16 bulk copy (the contractions on the BF16 matrix cores) with the
+            # float32 values as the master of the refinement
+            Ab = torch.zeros((b.n, W.pad_lda(b.m, 2)), dtype=torch.bfloat16, device=dev)
+            Ab[:, :b.m] = At[:, :b.m].to(torch.bfloat16)
+            items = [dict(At=Ab, At_master=At, m=b.m, y=Y[c], k=b.k) for c in range(Y.shape[0])]
+        else:
+            items = [dict(At=At, m=b.m, y=Y[c], k=b.k) for c in range(Y.shape[0])]
+        dt = "bf16" if args.bf16 else "f32"
         return dict(name=f"image4k_sr{args.sr}",
                     desc=f"3840 columns of a synthetic 3840x2160 image sharing one Gaussian A, "
-                         f"sampling rate {args.sr} (m={b.m}), power-law k={b.k}, float32",
+                         f"sampling rate {args.sr} (m={b.m}), power-law k={b.k}, "
+                         + ("BF16 bulk + FP32 master" if args.bf16 else "float32"),
                     cfg=dict(n=b.n, m=b.m, k=b.k, batch=3840, shared_A=True),
-                    clomp_items=items, omp_items=items, dtype="f32", host=b)
+                    clomp_items=items, omp_items=items, dtype=dt, host=b)
     if args.workload == "uneven":
         log("drawing the uneven batch on the device (4096 signals, ~89 GB)")
         specs, items, supps, coefs = W.uneven_batch_device(4096, dev)
@@ -193,6 +204,7 @@ def measured_traffic(workload, kernel):
 
 VALU_PEAK_TFLOPS = 157.3   # FP32 vector, 256 CUs at 2.4 GHz
 MFMA_FP32_PEAK_TFLOPS = 157.3   # dense FP32 matrix cores (published)
+MFMA_BF16_PEAK_TFLOPS = 2500.0  # dense BF16 matrix cores (published, without sparsity)
 
 
 def fused_flops(items, method, inner_steps=32):
@@ -230,7 +242,7 @@ def roofline(p, items=None, method="clomp"):
                 "launches": nl}
     shared = (items is not None and len(items) > 1 and p["pass_bytes"] == 0 and
               len({it["At"].data_ptr() for it in items}) == 1)
-    if shared and p["ms"]["scan"] > p["ms"]["pass"]:
+    if shared and p["ms"]["scan"] > max(p["ms"]["pass"], p["ms"]["coef"]):
         # shared dictionary: the scan is the contraction C = A^T R of the whole
         # batch on the FP32 matrix cores (plus the once-per-solve A^T A, A^T Y)
         n, m = int(items[0]["At"].shape[0]), int(items[0]["m"])
@@ -240,13 +252,18 @@ def roofline(p, items=None, method="clomp"):
         ach = fl / (k_ms * 1e-3) / 1e12
         what = ("C = A^T R over the batch, argmax epilogue" if method in ("clomp", "omp")
                 else "gradient G = A^T R over the batch")
-        return {"kernel": f"shared_mfma_kernel ({what})",
-                "bound": "mfma", "achieved": ach, "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / MFMA_FP32_PEAK_TFLOPS, "traffic": None,
+        # the scan of a BF16 bulk matrix runs on the BF16 matrix cores (the
+        # IHT / paper-mode gradient stays on FP32)
+        bfs = str(items[0]["At"].dtype) == "torch.bfloat16" and method in ("clomp", "omp")
+        peak = MFMA_BF16_PEAK_TFLOPS if bfs else MFMA_FP32_PEAK_TFLOPS
+        kname = "shared_mfma_bf16_kernel" if bfs else "shared_mfma_kernel"
+        return {"kernel": f"{kname} ({what})",
+                "bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                "frac": ach / peak, "traffic": None,
                 "avg_launch_us": 1e3 * k_ms, "flops_per_launch": fl, "launches": nl}
-    if p["launches"]["pass"] > 0 and p["ms"]["pass"] >= p["ms"]["scan"] and p["pass_bytes"] == 0:
+    if shared and p["launches"]["coef"] > 0 and p["ms"]["coef"] >= p["ms"]["scan"]:
         # shared dictionary: the launches carry coefficient workgroups only
-        nl, ms = p["launches"]["pass"], p["ms"]["pass"]
+        nl, ms = p["launches"]["coef"], p["ms"]["coef"]
         fl = 0.0
         for it in items:
             ke = min(int(it["k"]), int(it["m"]), int(it["At"].shape[0]))
@@ -337,9 +354,10 @@ def main():
         outs[method] = out
         log(f"{method} {1e3 * dt / args.steps:.3f} ms/step")
 
-    # live per-phase timing with HIP events on the launch stream (no graph)
+    # live per-phase timing with HIP events on the launch stream (no graph);
+    # --profile-steps 0 skips it (runs under hardware-counter collection)
     prof = {}
-    for method in methods:
+    for method in (methods if args.profile_steps > 0 else ()):
         ps = C.Solver(0, method=method, flags=C.FLAG_PROFILE | flow_flag)
         pp = ps.prepare(items[method], stream=stream)
         ps.run(pp, stream=stream)
@@ -391,14 +409,15 @@ def main():
         "status_flags_nonzero": {m: int((st[m] != 0).sum()) for m in st},
         "phase_ms_per_step": {m: {k: v / args.profile_steps for k, v in prof[m]["ms"].items()}
                               for m in prof},
-        "roofline": roofline(prof["clomp"], items["clomp"], "clomp"),
-        "roofline_omp": roofline(prof["omp"], items["omp"], "omp"),
+        "roofline": roofline(prof["clomp"], items["clomp"], "clomp") if prof else None,
+        "roofline_omp": roofline(prof["omp"], items["omp"], "omp") if prof else None,
         "roofline_iht": roofline(prof["iht"], items["iht"], "iht") if "iht" in prof else None,
         "roofline_clomp_paper": (roofline(prof["clomp_paper"], items["clomp_paper"], "iht")
                                  if "clomp_paper" in prof else None),
         "cpu_baseline": cpu,
     }
-    line["roofline"]["traffic"] = measured_traffic(wl["name"], line["roofline"]["kernel"])
+    if line["roofline"] is not None:
+        line["roofline"]["traffic"] = measured_traffic(wl["name"], line["roofline"]["kernel"])
     print(json.dumps(line), flush=True)
     for s in solvers.values():
         s.close()

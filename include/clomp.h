@@ -299,10 +299,11 @@ clomp_status_t clomp_grad_noalloc(clomp_handle_t h, int32_t n, int32_t m, int64_
  * solve since the last clomp_profile_reset.  Phases: 0 scan (residual
  * schedule: c = A^T r and argmax; correlation schedule: c = A^T y or
  * c0 - H s and argmax), 1 gram (selection record and new Gram column),
- * 2 coef (Adam or the OMP update), 3 resid (r = y - A_S s), 4 refine (QR or
- * CGLS), 5 norm (FP64 residual norm and output scatter), 6 init, 7 pass
- * (correlation schedule: coefficient update fused with the pass over A),
- * 8 fused (the whole greedy loop of the signals served by the fused
+ * 2 coef (Adam or the OMP update; in the correlation schedule the launches
+ * that carry only coefficient workgroups), 3 resid (r = y - A_S s), 4 refine
+ * (QR or CGLS), 5 norm (FP64 residual norm and output scatter), 6 init, 7 pass
+ * (correlation schedule: the launches of the pass over A, with the coefficient
+ * update when it shares the launch), 8 fused (the whole greedy loop of the signals served by the fused
  * small-signal kernel).
  *   ms[p]        summed device time between HIP events recorded on the launch
  *                stream immediately before and after each launch of phase p

@@ -788,7 +788,6 @@ clomp_status_t launch_hflow(clomp_ctx* h, const Plan& P, int bf16, hipStream_t s
             lds = tlds;
           }
         }
-        PhaseScope ps(h, PH_PASS, st);
         // Split launch: with a shared dictionary no pass shares the launch, and
         // with more active signals than CUs the 16-wave coefficient workgroups
         // of a fused launch would hold the device before any pass tile runs.
@@ -797,14 +796,18 @@ clomp_status_t launch_hflow(clomp_ctx* h, const Plan& P, int bf16, hipStream_t s
         // (OMP's update is short enough to hide under the pass of a fused
         // launch: it splits only for a shared dictionary)
         if (W == 1 && t1 <= 256 && (P.gflow || (!omp && nact > h->num_cu))) {
-          if (omp)
-            HIP_TRY(launch_coef_omp(d_insts + c.i0, nact, t, prm.lr_rel, prm.eps_rel, st),
-                    "coef_omp");
-          else
-            HIP_TRY(launch_coef_reg(d_insts + c.i0, nact, t, prm.inner_steps, prm.beta1,
-                                    prm.beta2, prm.lr_rel, prm.eps_rel, st),
-                    "coef_reg");
+          {
+            PhaseScope ps(h, PH_COEF, st);
+            if (omp)
+              HIP_TRY(launch_coef_omp(d_insts + c.i0, nact, t, prm.lr_rel, prm.eps_rel, st),
+                      "coef_omp");
+            else
+              HIP_TRY(launch_coef_reg(d_insts + c.i0, nact, t, prm.inner_steps, prm.beta1,
+                                      prm.beta2, prm.lr_rel, prm.eps_rel, st),
+                      "coef_reg");
+          }
           if (!P.gflow && nnext > 0) {
+            PhaseScope ps(h, PH_PASS, st);
             HIP_TRY(launch_coef_pass(bf16, c.lpa, omp, d_insts + c.i0, 0, 1, d_insts,
                                      d_htiles + c.htile_off, c.htile_prefix[nnext], t,
                                      prm.inner_steps, prm.beta1, prm.beta2, prm.lr_rel,
@@ -817,6 +820,7 @@ clomp_status_t launch_hflow(clomp_ctx* h, const Plan& P, int bf16, hipStream_t s
           }
         } else {
           // (a shared dictionary has every column of H already: no pass tiles)
+          PhaseScope ps(h, P.gflow ? PH_COEF : PH_PASS, st);
           HIP_TRY(launch_coef_pass(bf16, c.lpa, omp, d_insts + c.i0, nact, W, d_insts,
                                    d_htiles + c.htile_off, P.gflow ? 0 : c.htile_prefix[nnext], t,
                                    prm.inner_steps, prm.beta1, prm.beta2, prm.lr_rel,

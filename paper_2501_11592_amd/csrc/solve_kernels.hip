@@ -1920,6 +1920,219 @@ __global__ __launch_bounds__(256) void shared_mfma_kernel(const Inst* __restrict
     }
 }
 
+// BF16 bulk matrix: the same contractions on the BF16 matrix cores
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation), for MODE 0 (Gf = A^T A, both
+// operands the stored BF16 atoms, so every product is exact and only the
+// accumulation order differs from the FP32 kernel) and MODE 2 (the scan: the
+// residuals rounded to BF16, round to nearest even, as they are staged).  The
+// tile, wave split and epilogue are those of shared_mfma_kernel; k is staged in
+// chunks of 32 as BF16 rows with k contiguous (row stride 40 elements, so the
+// 16-byte operand reads of a 16-lane group fall in distinct banks), two
+// buffers, the next chunk's loads in flight during the products.
+// Operand layout of the instruction: lane l supplies A[l % 16][8 (l / 16) + e]
+// and B[8 (l / 16) + e][l % 16] (e < 8); register v of lane l holds
+// D[4 (l / 16) + v][l % 16] (checked with an in-bounds probe on the GPU).
+constexpr int kBfK = 32, kBfLd = 40;
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8_t __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned short bf16_bits_rne(float x) {
+  const __bf16 h = (__bf16)x;               // IEEE conversion: round to nearest even
+  return __builtin_bit_cast(unsigned short, h);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void shared_mfma_bf16_kernel(const Inst* __restrict__ insts,
+                                                               int nsig, float* __restrict__ Gf,
+                                                               int t) {
+  static_assert(MODE == 0 || MODE == 2, "BF16 contraction: Gram matrix or scan");
+  __shared__ __align__(16) unsigned short As[2][kMfmaTile][kBfLd];
+  __shared__ __align__(16) unsigned short Bs[2][kMfmaTile][kBfLd];
+  __shared__ unsigned long long kbest[2][kMfmaTile];
+  const Inst& I0 = insts[0];
+  const uint16_t* A = reinterpret_cast<const uint16_t*>(I0.A);
+  const long long lda = I0.lda, ldh = I0.ldh;
+  const int n = I0.n, m = I0.m, m_pad = I0.m_pad;   // shared by every signal
+  const int ncols = (MODE == 0) ? n : nsig;
+  const int i0 = blockIdx.x * kMfmaTile, q0 = blockIdx.y * kMfmaTile;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  mfma_f4 acc[4][4];
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+  // A side: thread stages 8 consecutive k (one 16-byte load) of rows
+  // ra + 64 u, u < 2, at k offset ka of every chunk
+  const int ra = tid >> 2, ka = (tid & 3) * 8;
+  const uint16_t* arow[2];
+  bool aok[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int i = i0 + ra + 64 * u;
+    aok[u] = i < n;
+    arow[u] = A + (long long)(aok[u] ? i : i0) * lda;
+  }
+  // B side: MODE 0 as the A side (atoms); MODE 2 four consecutive FP32
+  // residual entries (one 16-byte load) of columns rc + 32 u, u < 4, at k
+  // offset kc of every chunk
+  const int rc = tid >> 3, kc = (tid & 7) * 4;
+  const uint16_t* brow[2];
+  const float* bsig[4];
+  bool bok[4];
+  if (MODE == 0) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int q = q0 + ra + 64 * u;
+      bok[u] = q < ncols;
+      brow[u] = A + (long long)(bok[u] ? q : q0) * lda;
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = q0 + rc + 32 * u;
+      bok[u] = q < ncols;
+      bsig[u] = insts[bok[u] ? q : q0].r;
+    }
+  }
+  uint4 av[2], bvh[2];
+  float4 bvf[4];
+  // raw loads from clamped addresses (k below m for A rows: lda >= m and both
+  // multiples of 8, so a 16-byte load starting below m stays in the row; r
+  // below m_pad, a multiple of 8); the masks are applied when staging
+  auto fetch = [&](int k0) {
+    const int k = k0 + ka;
+    const int ks = k < m ? k : 0;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) av[u] = gload16(arow[u] + ks);
+    if (MODE == 0) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) bvh[u] = gload16(brow[u] + ks);
+    } else {
+      const int kb = k0 + kc;
+      const int kbs = kb < m_pad ? kb : 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) bvf[u] = gload4(bsig[u] + kbs);
+    }
+  };
+  // zero the bf16 entries of a 16-byte group at or beyond m (nk valid ones)
+  auto mask8 = [](uint4 q, int nk) -> uint4 {
+    if (nk >= 8) return q;
+    unsigned wv[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const unsigned lo = (2 * e < nk) ? 0x0000ffffu : 0u;
+      const unsigned hi = (2 * e + 1 < nk) ? 0xffff0000u : 0u;
+      wv[e] &= (lo | hi);
+    }
+    return make_uint4(wv[0], wv[1], wv[2], wv[3]);
+  };
+  fetch(0);
+  int buf = 0;
+  for (int k0 = 0; k0 < m; k0 += kBfK) {
+    {
+      const int nk = m - (k0 + ka);           // valid entries of this thread's A group
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const uint4 q = (aok[u] && nk > 0) ? mask8(av[u], nk) : make_uint4(0u, 0u, 0u, 0u);
+        *reinterpret_cast<uint4*>(&As[buf][ra + 64 * u][ka]) = q;
+      }
+      if (MODE == 0) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const uint4 q = (bok[u] && nk > 0) ? mask8(bvh[u], nk) : make_uint4(0u, 0u, 0u, 0u);
+          *reinterpret_cast<uint4*>(&Bs[buf][ra + 64 * u][ka]) = q;
+        }
+      } else {
+        const int kb = k0 + kc;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float4 f = bvf[u];
+          const bool ok = bok[u];
+          const unsigned short h0 = (ok && kb < m) ? bf16_bits_rne(f.x) : 0;
+          const unsigned short h1 = (ok && kb + 1 < m) ? bf16_bits_rne(f.y) : 0;
+          const unsigned short h2 = (ok && kb + 2 < m) ? bf16_bits_rne(f.z) : 0;
+          const unsigned short h3 = (ok && kb + 3 < m) ? bf16_bits_rne(f.w) : 0;
+          *reinterpret_cast<uint2*>(&Bs[buf][rc + 32 * u][kc]) =
+              make_uint2((unsigned)h0 | ((unsigned)h1 << 16), (unsigned)h2 | ((unsigned)h3 << 16));
+        }
+      }
+    }
+    __syncthreads();
+    if (k0 + kBfK < m) fetch(k0 + kBfK);   // in flight during the products
+    const int kk = 8 * (lane >> 4);
+    bf16x8_t a[4], b[4];
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi) {
+      const uint4 q = *reinterpret_cast<const uint4*>(&As[buf][64 * wr + 16 * bi + (lane & 15)][kk]);
+      a[bi] = __builtin_bit_cast(bf16x8_t, q);
+    }
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) {
+      const uint4 q = *reinterpret_cast<const uint4*>(&Bs[buf][64 * wc + 16 * bj + (lane & 15)][kk]);
+      b[bj] = __builtin_bit_cast(bf16x8_t, q);
+    }
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj)
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+    buf ^= 1;
+  }
+  const int ib = i0 + 64 * wr + 4 * (lane >> 4);
+  const int qb = q0 + 64 * wc + (lane & 15);
+  if (MODE == 2) {
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) {
+      const int q = qb + 16 * bj;
+      unsigned long long best = 0ull;
+      if (q < ncols) {
+        const unsigned* bm = insts[q].bitmap;
+        const int wbase = i0 + 64 * wr;
+        const unsigned bw0 = wbase < n ? gmem(bm)[wbase >> 5] : ~0u;
+        const unsigned bw1 = wbase + 32 < n ? gmem(bm)[(wbase >> 5) + 1] : ~0u;
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = ib + 16 * bi + v;
+            const unsigned word = (16 * bi + 4 * (lane >> 4) + v) < 32 ? bw0 : bw1;
+            if (i < n && !((word >> (i & 31)) & 1u)) {
+              const unsigned long long kk2 = pack_key(acc[bi][bj][v], i);
+              best = kk2 > best ? kk2 : best;
+            }
+          }
+      }
+      for (int o = 16; o < 64; o <<= 1) {
+        const unsigned long long other = __shfl_xor(best, o, 64);
+        best = other > best ? other : best;
+      }
+      if (lane < 16) kbest[wr][64 * wc + 16 * bj + lane] = best;
+    }
+    __syncthreads();
+    if (tid < kMfmaTile) {
+      const int q = q0 + tid;
+      unsigned long long best = kbest[0][tid];
+      if (kbest[1][tid] > best) best = kbest[1][tid];
+      if (q < ncols && best) atomicMax(&insts[q].key[t & 1], best);
+    }
+    return;
+  }
+  // MODE 0: the lane's four atoms of a block are consecutive (one 16-byte
+  // store; columns hold ldh >= 128 ceil(n / 128) entries, rows past n are zero)
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) {
+      const int q = qb + 16 * bj;
+      if (q >= ncols) continue;
+      const int i = ib + 16 * bi;
+      *reinterpret_cast<float4*>(Gf + i + (long long)q * ldh) =
+          make_float4(acc[bi][bj][0], acc[bi][bj][1], acc[bi][bj][2], acc[bi][bj][3]);
+    }
+}
+
 // Products over one signal's support, one 256-thread workgroup per signal
 // (t1 <= 256 atoms: the given count, or the signal's own when 0), the support
 // and coefficients staged in LDS, each lane's four consecutive rows read with
@@ -3394,7 +3607,8 @@ hipError_t launch_shared_gram(int bf16, const Inst* d, int nsig, int n, float* G
   const int nt = (n + kMfmaTile - 1) / kMfmaTile;
   const dim3 g0(nt, nt), g1(nt, (nsig + kMfmaTile - 1) / kMfmaTile);
   if (bf16) {
-    CLOMP_LAUNCH((shared_mfma_kernel<uint16_t, 0>), g0, dim3(256), 0, s, d, nsig, Gf, 0);
+    CLOMP_LAUNCH((shared_mfma_bf16_kernel<0>), g0, dim3(256), 0, s, d, nsig, Gf, 0);
+    // c0 = A^T Y keeps Y in FP32 (b = A_S^T y of the coefficient fit)
     CLOMP_LAUNCH((shared_mfma_kernel<uint16_t, 1>), g1, dim3(256), 0, s, d, nsig, Gf, 0);
   } else {
     CLOMP_LAUNCH((shared_mfma_kernel<float, 0>), g0, dim3(256), 0, s, d, nsig, Gf, 0);
@@ -3461,7 +3675,7 @@ hipError_t launch_shared_rscan(int bf16, const Inst* d, int nsig, int n, int t, 
   if (nsig <= 0) return nothing_to_launch(s);
   const dim3 g((n + kMfmaTile - 1) / kMfmaTile, (nsig + kMfmaTile - 1) / kMfmaTile);
   if (bf16)
-    CLOMP_LAUNCH((shared_mfma_kernel<uint16_t, 2>), g, dim3(256), 0, s, d, nsig, nullptr, t);
+    CLOMP_LAUNCH((shared_mfma_bf16_kernel<2>), g, dim3(256), 0, s, d, nsig, nullptr, t);
   else
     CLOMP_LAUNCH((shared_mfma_kernel<float, 2>), g, dim3(256), 0, s, d, nsig, nullptr, t);
   return hipGetLastError();

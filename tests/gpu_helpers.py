@@ -85,4 +85,8 @@ def compare(gpu, i, res, A_ref, y, *, delta, u, method, A_sel, k, tol_x, sep_par
     assert supp_gpu == res.support, (i, supp_gpu, res.support)
     e = rel_err(x_gpu, res.x)
     assert e <= tol_x, (i, e)
+    # per coefficient: no coefficient of at least 1% of the largest is off by
+    # more than 100 times the normwise tolerance
+    ce, _ = coef_err(x_gpu, res.x)
+    assert ce <= 100 * tol_x, (i, ce)
     return "identical"

@@ -98,7 +98,9 @@ def test_iht_bf16_with_master():
         Abf = torch.from_numpy(s.At[:, :s.m]).to(torch.bfloat16).to(torch.float64).numpy().T
         ident += _check(out, i, Abf, s.A, s.y, s.k, 60, BF16_DELTA, BF16_U, 1e-3)
     print(f"bf16: identical {ident}/12")
-    assert ident >= 1
+    # the oracle separates 1 of the 12 under the BF16 gates (60 iterations);
+    # _check asserts it
+    assert ident == 1
     sol.close()
 
 

@@ -136,9 +136,15 @@ def test_paper_large1d():
     ok = _check(out, 0, A, A, y, sig.k, _params(200), FP32_DELTA, FP32_U, 1e-5)
     print(f"large1d: separated {ok}, selected {int(out.n_selected[0])}")
     if not ok:
-        # not separated: the selection is still a valid paper-mode support
+        # not separated: what is unique is checked - the support is a valid
+        # paper-mode support and x is the least squares on it (the norm is
+        # checked by _check)
+        from oracle import lstsq_support
         nsel = int(out.n_selected[0])
         assert 0 < nsel <= sig.k and int(out.status[0]) & C.ST_NAN == 0
+        supp = out.support[0][:nsel].cpu().numpy().tolist()
+        x = out.x[0].cpu().numpy().astype(np.float64)
+        assert rel_err(x[supp], lstsq_support(A, y, supp)) <= 1e-5
     sol.close()
 
 

@@ -178,6 +178,16 @@ def test_shared_gram_large_support_teams(method):
     kind = compare(out, 0, res, A, sigs[0].astype(np.float64), delta=FP32_DELTA, u=FP32_U,
                    method=method, A_sel=A, k=k, tol_x=1e-5)
     print(f"{method} k=300 shared: {kind}")
+    # the oracle separates the CLOMP solve of this signal, not the OMP one;
+    # OMP's x is then checked as the least squares on the GPU's own support
+    if method == "clomp":
+        assert kind == "identical"
+    else:
+        from oracle import lstsq_support
+        from tests.gpu_helpers import rel_err
+        S = out.support[0].cpu().numpy().tolist()
+        x = out.x[0].cpu().numpy().astype(np.float64)
+        assert rel_err(x[S], lstsq_support(A, sigs[0].astype(np.float64), S)) <= 1e-5
     sol.close()
 
 
@@ -302,3 +312,46 @@ def test_shared_ragged_tiles_nan_padding(method):
             assert out.support[c].tolist() == per.support[c].tolist(), c
     print(f"{method} ragged shared tiles: identical {ident}/{total}")
     assert ident >= total // 3
+
+
+@pytest.mark.parametrize("method", ["clomp", "omp"])
+def test_shared_bf16_ragged_tiles_nan_padding(method):
+    """BF16 bulk on a shared dictionary with ragged contraction tiles (n = 300
+    atoms, 200 columns), m = 77 (a partial chunk of k) and a NaN in every lda
+    padding entry of the BF16 matrix: the BF16 matrix-core Gram matrix and
+    scan (residuals rounded to BF16) must mask the padding.  No NaN status;
+    on every sampled column the ordered support equals the oracle's (on the
+    BF16 values, refinement on the FP32 master) over its separated prefix
+    under the BF16 gates, and x is the least squares on the GPU's support."""
+    from oracle import lstsq_support, separation_report
+    from tests.gpu_helpers import BF16_DELTA, BF16_U, PARAMS, rel_err
+    b = W.image_batch(0.3, n=300, a=200, k=24, lda=96)
+    A = b.A                                            # float32 values, float64
+    Abf = torch.from_numpy(b.At[:, :b.m]).to(torch.bfloat16).to(torch.float64).numpy().T
+    At32 = dev(b.At)
+    Atb = torch.zeros((b.n, 128), dtype=torch.bfloat16, device="cuda")
+    Atb[:, :b.m] = At32[:, :b.m].to(torch.bfloat16)
+    Atb[:, b.m:] = float("nan")
+    sol = C.Solver(0, method=method, flags=ITER)
+    out = sol.solve_batch([dict(At=Atb, At_master=At32, m=b.m, y=dev(b.Y[c]), k=b.k)
+                           for c in range(200)])
+    torch.cuda.synchronize()
+    st = out.status.cpu().numpy()
+    assert not (st & C.ST_NAN).any()
+    assert all(int(out.n_selected[c]) == b.k for c in range(200))
+    total = 0
+    for c in range(0, 200, 7):
+        y = b.Y[c].astype(np.float64)
+        res = oracle_final_x(method, Abf, y, b.k, A_refine=A)
+        _, pre, _ = separation_report(Abf, y, b.k, method=method, params=PARAMS,
+                                      delta=BF16_DELTA, u=BF16_U, A_refine=A, base=res)
+        S = out.support[c].cpu().numpy().tolist()
+        assert S[:pre] == res.support[:pre], (c, pre)
+        x = out.x[c].cpu().numpy().astype(np.float64)
+        assert rel_err(x[S], lstsq_support(A, y, S)) <= 1e-5, c
+        total += pre
+    print(f"{method} bf16 ragged shared tiles: {total} selections in separated prefixes")
+    # the oracle's separated prefixes of the 29 sampled columns hold 317
+    # (CLOMP) / 278 (OMP) of their 696 selections
+    assert total >= {"clomp": 317, "omp": 278}[method]
+    sol.close()
