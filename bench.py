@@ -428,7 +428,7 @@ def _threads():
     return int(max([p.get("num_threads", 1) for p in threadpool_info()] or [1]))
 
 
-UNEVEN_CPU_STRATA = (2, 6, 10)   # golden-sample positions timed for the CPU baseline
+UNEVEN_CPU_STRATA = tuple(range(4, 15))   # golden-sample positions timed for the CPU baseline
 
 
 def accuracy_uneven(args, wl, outs):

@@ -1,13 +1,16 @@
 """GPU parity at the benchmark's full sizes, in the launch configuration the
-benchmark times (default schedule, graph capture for the headline workload).
+benchmark uses.
 
-Outputs the oracle cannot compute whole are checked one by one on samples or
-through properties that hold at any size:
-  * the refined x is the least-squares solution on the GPU's own support
-    (oracle O6 on the FP32 master columns), the reported norm is ||y - A_S x_S||;
-  * the first selections equal the oracle's (the greedy loop is causal, so the
-    first selections of a k = 2048 run are those of a k = 3 run);
-  * sampled instances of the uneven batch are solved whole by the oracle.
+  * the headline 1-D signal (n=16384, m=4096, k=256) and the uneven batch
+    (4096 signals, BF16 bulk + FP32 master; sixteen stratified signals) against
+    the oracle's stored results: ordered supports, final x normwise and per
+    coefficient, and (uneven) the Adam iterate before the refinement;
+  * the flattened 256 x 256 image (n=65536, m=19661, k=2048) against the
+    oracle's stored results over each method's separated prefix, plus the
+    overlap of the whole supports;
+  * everywhere: the refined x is the least-squares solution on the GPU's own
+    support (oracle O6 on the FP32 master columns) and the reported norm is
+    ||y - A_S x_S||.
 """
 
 import json
@@ -17,10 +20,10 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import clomp_fp64, omp_fp64, lstsq_support, resid_norm_fp64, well_separated
+from oracle import lstsq_support, resid_norm_fp64
 from paper_2501_11592_amd import clomp as C
 from paper_2501_11592_amd import workloads as W
-from tests.gpu_helpers import PARAMS, BF16_DELTA, BF16_U, coef_err, rel_err
+from tests.gpu_helpers import coef_err, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -202,4 +205,4 @@ def test_flat_image_full_size():
 
 # measured support overlap of the whole solves with the oracle's (the
 # selections after the separated prefix may go either way on near-ties)
-FLAT_OVERLAP_FLOOR = {"clomp": 0.0, "omp": 0.0}
+FLAT_OVERLAP_FLOOR = {"clomp": 0.7, "omp": 0.99}   # measured 0.763 and 1.000
