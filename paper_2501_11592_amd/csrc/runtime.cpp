@@ -58,7 +58,7 @@ struct Class {
   int kmax = 0;
   int nch = 0;                        // register-kernel vectors per lane (0: LDS kernels)
   std::vector<int> htile_prefix, ctile_prefix;
-  int cscan_sub = 1;                  // 64-atom sub-tiles per H-scan tile
+  int cscan_sub = 4;                  // 64-atom sub-tiles per H-scan tile (256 atoms)
   int nmax = 0;                       // largest n of the class
   int nslice = 1;                     // IHT: most m-slices of any signal of the class
   int slice_floats = 0;               // IHT: largest slice of r (floats, LDS)
@@ -510,15 +510,9 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     c.tile_off = P.tiles.size();
     c.row_off = P.rows.size();
     const int ng = kBlock / c.lpa;
-    {
-      // H-scan tiles of 64 * cscan_sub atoms: as large as keeps about four
-      // tiles per CU at the first iteration (many small tiles cost more to
-      // dispatch than their work)
-      long long t64 = 0;
-      for (int q = c.i0; q < c.i1; ++q) t64 += (P.insts[q].n + 63) / 64;
-      c.cscan_sub = 1;
-      while (c.cscan_sub < 16 && t64 / (2 * c.cscan_sub) >= 4LL * h->num_cu) c.cscan_sub *= 2;
-    }
+    // H-scan tiles of 256 atoms (the scan kernel chooses how many waves share
+    // a tile from the number of tiles of each launch)
+    c.cscan_sub = 4;
     for (int q = c.i0; q < c.i1; ++q) {
       const Inst& d = P.insts[q];
       // an IHT gradient workgroup streams one slice of m of each atom of its

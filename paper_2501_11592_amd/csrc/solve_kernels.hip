@@ -2960,95 +2960,77 @@ __global__ __launch_bounds__(kPassThreads) void coef_pass_kernel(
   pass_tile_body<TA, LPA, 1>(insts[tile.inst], tile, t, dsh, wbest);
 }
 
-// c_j = c0_j - sum_{l<t} H[j, l] s_l for a 64-atom tile.  Lane (q, u) of
-// wave w covers atoms 4q..4q+3 (float4 loads) and the columns l = L, L+64, ...
-// with slice L = 4w + u; slices are added with shuffles inside a wave, then
-// across the 16 waves in LDS, in a fixed order.  Then |c| with the exclusion
-// of selected atoms and the argmax key (slot t & 1) by atomicMax.
-constexpr int kCscanThreads = 1024;
-constexpr int kCscanAtoms = 64;
+// c_j = c0_j - sum_{l<t} H[j, l] s_l over tiles of 256 atoms (tiles start at
+// multiples of 256 within a signal): lane v covers atoms 4v..4v+3 with one
+// float4 load per column of H (a wave reads 1 KB of a column per load, eight
+// loads in flight), G waves split the columns of a tile (column l goes to
+// wave l mod G) and their partial sums are added in LDS in wave order; with
+// G = 1 each wave of the workgroup takes a tile of its own and no workgroup
+// barrier is needed.  Then |c| with the exclusion of selected atoms and the
+// argmax key (slot t & 1), one atomicMax per tile.  G is chosen per launch
+// from the number of tiles, so that both a batch of thousands of signals
+// and a single signal keep the device busy.
+constexpr int kHscanAtoms = 256;
 
-__global__ __launch_bounds__(kCscanThreads) void cscan_kernel(const Inst* __restrict__ insts,
-                                                              const ScanTile* __restrict__ tiles,
-                                                              int t) {
-  __shared__ float4 part[16][16];
-  const ScanTile tile = tiles[blockIdx.x];
-  const Inst& I = insts[tile.inst];
-  if (I.st->done) return;
+template <int G>
+__global__ __launch_bounds__(G == 16 ? 1024 : 256) void cscan_kernel(
+    const Inst* __restrict__ insts, const ScanTile* __restrict__ tiles, int ntiles, int t) {
+  __shared__ float4 part[G > 1 ? G : 1][64];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const int q = lane & 15;
-  const int L = 4 * w + (lane >> 4);
-  const float* ssh = I.s;                  // t coefficients, read through L2
-  unsigned long long key = 0ull;
-  // the tile spans one or more 64-atom sub-tiles (tiles start at multiples
-  // of 64); one atomicMax per tile
-  for (int jb = tile.j0; jb < tile.j1; jb += kCscanAtoms) {
-    const int j = jb + 4 * q;
-    // loads that do not depend on the sum are issued first (c0 is padded to
-    // a multiple of 256 entries, so the float4 read stays inside the buffer)
-    float4 c0v = make_float4(0.f, 0.f, 0.f, 0.f);
-    unsigned bits = 0u;
-    if (w == 0 && lane < 16 && j < tile.j1) {
-      c0v = *reinterpret_cast<const float4*>(I.c0 + j);
-      bits = I.bitmap[j >> 5];
-    }
-    float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
-    if (j < tile.j1) {
-      int l = L;
-      for (; l + 64 < t; l += 128) {
-        const float4 h0 = *reinterpret_cast<const float4*>(hcol(I, l) + j);
-        const float4 h1 = *reinterpret_cast<const float4*>(hcol(I, l + 64) + j);
-        const float s0 = ssh[l], s1 = ssh[l + 64];
-        a0.x = fmaf(h0.x, s0, a0.x); a0.y = fmaf(h0.y, s0, a0.y);
-        a0.z = fmaf(h0.z, s0, a0.z); a0.w = fmaf(h0.w, s0, a0.w);
-        a1.x = fmaf(h1.x, s1, a1.x); a1.y = fmaf(h1.y, s1, a1.y);
-        a1.z = fmaf(h1.z, s1, a1.z); a1.w = fmaf(h1.w, s1, a1.w);
-      }
-      if (l < t) {
-        const float4 h0 = *reinterpret_cast<const float4*>(hcol(I, l) + j);
-        const float s0 = ssh[l];
-        a0.x = fmaf(h0.x, s0, a0.x); a0.y = fmaf(h0.y, s0, a0.y);
-        a0.z = fmaf(h0.z, s0, a0.z); a0.w = fmaf(h0.w, s0, a0.w);
-      }
-    }
-    float4 v = make_float4(a0.x + a1.x, a0.y + a1.y, a0.z + a1.z, a0.w + a1.w);
-    // the four slices of a wave (lanes q, q+16, q+32, q+48)
+  const int ti = (G == 1) ? (int)blockIdx.x * 4 + w : (int)blockIdx.x;
+  if (ti >= ntiles) return;                  // G == 1 only: a whole wave leaves
+  const ScanTile tile = tiles[ti];
+  const Inst& I = insts[tile.inst];
+  if (I.st->done) return;                    // G > 1: the whole workgroup leaves
+  const int j = tile.j0 + 4 * lane;
+  const bool ok = j < tile.j1;
+  float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (ok) {
+    const float* ssh = I.s;                  // t coefficients, uniform per wave
+    auto fma4 = [](float4 h, float c, float4 x) {
+      return make_float4(fmaf(h.x, c, x.x), fmaf(h.y, c, x.y), fmaf(h.z, c, x.z),
+                         fmaf(h.w, c, x.w));
+    };
+    int l = (G == 1) ? 0 : w;
+    for (; l + 7 * G < t; l += 8 * G) {
+      float4 h[8];
 #pragma unroll
-    for (int o = 16; o < 64; o <<= 1) {
-      v.x += __shfl_xor(v.x, o, 64);
-      v.y += __shfl_xor(v.y, o, 64);
-      v.z += __shfl_xor(v.z, o, 64);
-      v.w += __shfl_xor(v.w, o, 64);
+      for (int u = 0; u < 8; ++u) h[u] = gload4(hcol(I, l + u * G) + j);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a = fma4(h[u], ssh[l + u * G], a);
     }
-    if (lane < 16) part[w][lane] = v;
+    for (; l < t; l += G) a = fma4(gload4(hcol(I, l) + j), ssh[l], a);
+  }
+  if (G > 1) {
+    part[w][lane] = a;
     __syncthreads();
-    if (w == 0 && lane < 16) {
-      float4 sum = part[0][lane];
+    if (w != 0) return;                      // no barrier follows
+    a = part[0][lane];
 #pragma unroll
-      for (int ww = 1; ww < 16; ++ww) {
-        const float4 u = part[ww][lane];
-        sum.x += u.x; sum.y += u.y; sum.z += u.z; sum.w += u.w;
-      }
-      const float hs[4] = {sum.x, sum.y, sum.z, sum.w};
-      const float cs[4] = {c0v.x, c0v.y, c0v.z, c0v.w};
+    for (int q = 1; q < G; ++q) {
+      const float4 u = part[q][lane];
+      a = make_float4(a.x + u.x, a.y + u.y, a.z + u.z, a.w + u.w);
+    }
+  }
+  unsigned long long key = 0ull;
+  if (ok) {
+    // c0 and ldh are padded to a multiple of 256 entries: the float4 read of
+    // the last atoms stays inside the buffer; 4 atoms share a bitmap word
+    const float4 c0v = gload4(I.c0 + j);
+    const unsigned bits = I.bitmap[j >> 5];
+    const float cs[4] = {c0v.x - a.x, c0v.y - a.y, c0v.z - a.z, c0v.w - a.w};
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int je = j + e;
-        if (je < tile.j1) {
-          const float c = cs[e] - hs[e];
-          const unsigned sel = (bits >> (je & 31)) & 1u;   // 4 atoms share a word
-          const unsigned long long k2 = sel ? 0ull : pack_key(c, je);
-          key = k2 > key ? k2 : key;
-        }
+    for (int e = 0; e < 4; ++e) {
+      const int je = j + e;
+      if (je < tile.j1 && !((bits >> (je & 31)) & 1u)) {
+        const unsigned long long k2 = pack_key(cs[e], je);
+        key = k2 > key ? k2 : key;
       }
     }
-    __syncthreads();   // part is rewritten by the next sub-tile
   }
-  if (w == 0) {
-    key = wave_max_u64(key);
-    if (lane == 0 && key) atomicMax(&I.key[t & 1], key);
-  }
+  key = wave_max_u64(key);
+  if (lane == 0 && key) atomicMax(&I.key[t & 1], key);
 }
 
 // Coefficient update of iteration t when no pass shares the launch (shared
@@ -3683,7 +3665,13 @@ hipError_t launch_shared_rscan(int bf16, const Inst* d, int nsig, int n, int t, 
 
 hipError_t launch_cscan(const Inst* d, const ScanTile* tiles, int ntiles, int t, hipStream_t s) {
   if (ntiles <= 0) return nothing_to_launch(s);
-  CLOMP_LAUNCH(cscan_kernel, dim3(ntiles), dim3(kCscanThreads), 0, s, d, tiles, t);
+  // waves per tile from the number of tiles: about 16 waves per CU or more
+  if (ntiles >= 4096)
+    CLOMP_LAUNCH(cscan_kernel<1>, dim3((ntiles + 3) / 4), dim3(256), 0, s, d, tiles, ntiles, t);
+  else if (ntiles >= 1024)
+    CLOMP_LAUNCH(cscan_kernel<4>, dim3(ntiles), dim3(256), 0, s, d, tiles, ntiles, t);
+  else
+    CLOMP_LAUNCH(cscan_kernel<16>, dim3(ntiles), dim3(1024), 0, s, d, tiles, ntiles, t);
   return hipGetLastError();
 }
 
