@@ -27,6 +27,9 @@ Modules
                    Adam step per iteration, R iterations
   iht        F4  normalised iterative hard thresholding (comparison method)
   prior      F2  total-variation prior of Eq. (5) on x = D s (explicit DCT-II D)
+  image_prior  F2  image priors of Eq. (6) (2-D total variation) and Eq. (7)
+                   (local variation, 3 x 3 windows) and CLOMP on the columns of
+                   one image with both
   brute      O3  exhaustive support search for tiny instances
   grad       O4  loss/gradient of 1/2||A(mask*s) - y||^2;  O5 one Adam step
   lstsq      O6  least squares on a support;  FP64 residual norm
@@ -53,6 +56,8 @@ from .brute import bruteforce_support
 from .separation import (well_separated, separation_report, separated_prefix, common_prefix,
                          perturbed_atoms, perturbed_vector)
 from .incremental import omp_cgs2_fp64, clomp_gram_fp64
+from .image_prior import (tv_2d, tv_2d_grad, lv, lv_grad, image_prior_loss, image_prior_grad,
+                          clomp_image_fp64)
 
 __all__ = [
     "lstsq_support", "resid_norm_fp64", "grad_fp64", "adam_step_fp64",
@@ -61,4 +66,6 @@ __all__ = [
     "bruteforce_support",
     "well_separated", "separation_report", "separated_prefix", "common_prefix",
     "perturbed_atoms", "perturbed_vector", "omp_cgs2_fp64", "clomp_gram_fp64",
+    "tv_2d", "tv_2d_grad", "lv", "lv_grad", "image_prior_loss", "image_prior_grad",
+    "clomp_image_fp64",
 ]
