@@ -106,6 +106,35 @@ typedef enum {
                                         A_master.  Exposes the learned
                                         coefficients before refinement       */
 
+#define CLOMP_FLAG_IMAGE 256u       /* CLOMP on the columns of one image: the
+                                        call's instances, in call order, are
+                                        the columns 0 .. count-1 of an n x
+                                        count image (x_c = D s_c, D the
+                                        orthonormal DCT-II synthesis basis),
+                                        all measured with the same A (same
+                                        pointer, n, m, lda, master) and with
+                                        the same k.  prior_tv then weighs the
+                                        2-D total variation of Eq. (6) (the
+                                        within-column term of the 1-D prior
+                                        plus the term between neighbouring
+                                        columns) and prior_lv the local
+                                        variation of Eq. (7) (sample standard
+                                        deviation over every 3 x 3 window of
+                                        the image, step 1).  Every iteration
+                                        each column selects its atom, then the
+                                        inner_steps Adam steps are taken on
+                                        all columns together (the priors
+                                        couple them).  x receives the learned
+                                        coefficients (no least-squares
+                                        refinement: the local variation is not
+                                        quadratic) and resid_norm their FP64
+                                        residual on A_master.  Requires the
+                                        CLOMP method, n <= 4096, k_eff <= 1024
+                                        and the shared-dictionary schedule
+                                        (not CLOMP_FLAG_NO_SHARED_GRAM or
+                                        CLOMP_FLAG_RESIDUAL_FLOW); otherwise
+                                        NOT_SUPPORTED                          */
+
 /*
  * Solver parameters.  The paper states the optimiser only as automatic
  * differentiation and back-propagation on learnable s (Methods, "Coefficients
@@ -142,7 +171,10 @@ typedef enum {
  *                the selection does not.  Served where the refinement runs
  *                as the in-LDS QR ((m + k_eff) * k_eff within about 24K
  *                floats), else clomp_solve_batch returns NOT_SUPPORTED.
- *                0 (default): no prior.
+ *                0 (default): no prior.  With CLOMP_FLAG_IMAGE: the weight of
+ *                the 2-D total variation of Eq. (6).
+ *   prior_lv     CLOMP_FLAG_IMAGE only: weight >= 0 of the local variation of
+ *                Eq. (7) on the image (0 default: none).
  */
 typedef struct {
   int32_t method;
@@ -157,6 +189,7 @@ typedef struct {
   uint32_t flags;
   float select_threshold;
   float prior_tv;
+  float prior_lv;
 } clomp_params_t;
 
 /*

@@ -27,6 +27,7 @@ METHODS = {"clomp": METHOD_CLOMP, "omp": METHOD_OMP, "iht": METHOD_IHT,
 ST_NAN, ST_K_CAPPED, ST_ZERO_Y, ST_REFINE_INACCURATE, ST_WATCHDOG = 1, 2, 4, 8, 32
 FLAG_GRAPH, FLAG_NO_FUSED_SMALL, FLAG_AUTOTUNE, FLAG_PROFILE = 1, 2, 4, 8
 FLAG_RESIDUAL_FLOW, FLAG_CORR_FLOW, FLAG_NO_SHARED_GRAM, FLAG_NO_REFINE = 16, 32, 64, 128
+FLAG_IMAGE = 256
 PHASES = ("scan", "gram", "coef", "resid", "refine", "norm", "init", "pass", "fused")
 
 STATUS_NAMES = {0: "CLOMP_OK", 1: "CLOMP_INVALID_ARGUMENT", 2: "CLOMP_OUT_OF_MEMORY",
@@ -39,7 +40,8 @@ class Params(ctypes.Structure):
                 ("beta2", ctypes.c_float), ("eps_rel", ctypes.c_float),
                 ("resid_tol", ctypes.c_float), ("refine_iters", ctypes.c_int32),
                 ("refine_tol", ctypes.c_float), ("flags", ctypes.c_uint32),
-                ("select_threshold", ctypes.c_float), ("prior_tv", ctypes.c_float)]
+                ("select_threshold", ctypes.c_float), ("prior_tv", ctypes.c_float),
+                ("prior_lv", ctypes.c_float)]
 
 
 class Instance(ctypes.Structure):
@@ -210,7 +212,7 @@ class Solver:
 
     def __init__(self, device=0, method="clomp", inner_steps=None, lr_rel=0.05,
                  beta1=0.9, beta2=0.999, eps_rel=1e-8, refine_iters=0,
-                 refine_tol=0.0, flags=0, select_threshold=0.7, prior_tv=0.0):
+                 refine_tol=0.0, flags=0, select_threshold=0.7, prior_tv=0.0, prior_lv=0.0):
         lib = load_library()
         if not torch.cuda.is_available():
             raise ClompError("no GPU available: the CLOMP library runs only on the device")
@@ -227,6 +229,7 @@ class Solver:
         p.eps_rel, p.refine_iters, p.refine_tol, p.flags = eps_rel, refine_iters, refine_tol, flags
         p.select_threshold = select_threshold
         p.prior_tv = prior_tv
+        p.prior_lv = prior_lv
         self.params = p
         h = ctypes.c_void_p()
         _check(None, lib.clomp_create(ctypes.byref(h), self.device.index or 0, ctypes.byref(p)),

@@ -30,6 +30,11 @@ constexpr int kTeamMax = 128;   // team members per signal (2048 rows)
 // are summed afterwards in slice order.
 constexpr int kIhtSliceFloats = 6144;
 constexpr int kSmallMaxK = 64;  // fused small-signal loop: k_eff bound (one wave)
+// Image mode (the columns of one image, coupled by the priors): largest n
+// (the five pixel columns of a local-variation neighbourhood and the pixel
+// gradient in LDS) and largest k_eff (support vectors in LDS).
+constexpr int kImageMaxN = 4096;
+constexpr int kImageMaxK = 1024;
 // Polls of a coefficient-team wait before it gives up and sets the watchdog
 // bit (default; clomp_set_tuning can lower it).
 constexpr unsigned kSpinLimitDefault = 1u << 20;
@@ -88,7 +93,7 @@ struct Inst {
   int nslice;          // IHT: slices of m in the gradient scan (>= 1)
   float tvw;           // 2w/n for the total-variation prior of weight w (0: none)
   unsigned spin;       // bounded device waits: polls before the watchdog bit is set
-  int spare;
+  int col;             // image mode: the instance's position in the call (its column)
   unsigned long long* team;   // [2*k_eff + 2*kTeamMax] tagged words exchanged by a team
                               // (correlation-update schedule; zeroed at solve start)
   float* gbuf;         // IHT: [nslice * ldh] per-slice partial dots; g = A^T r of the

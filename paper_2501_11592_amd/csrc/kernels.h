@@ -107,6 +107,24 @@ hipError_t launch_shared_rscan(int bf16, const Inst* d, int nsig, int n, int t, 
 hipError_t launch_cscan(const Inst* d, const ScanTile* tiles, int ntiles, int t, hipStream_t s);
 hipError_t set_max_lds_pass(size_t bytes);
 
+// Image mode (CLOMP on the columns of one image with the priors of Eq. (6)
+// and Eq. (7)).  init: the DCT-II synthesis basis D (n x n, ld ldd) and nzero
+// floats from `zero` on cleared (the dense coefficient images and the pixel
+// image, contiguous).  record: the selection of iteration t of columns
+// d[0..W).  synth: pixel columns x_c = D_S s_c (t1 atoms) into X (ld ldd).
+// step: Adam step number `step` (1-based) of every column on the loss with
+// the priors (htv = 2 w_tv / W, wlv = w_lv), Sd_cur / Sd_next the dense
+// coefficient images before / after it.
+hipError_t launch_image_init(float* D, int n, long long ldd, float* zero, long long nzero,
+                             hipStream_t s);
+hipError_t launch_image_record(const Inst* d, int W, int t, float lr_rel, float eps_rel,
+                               hipStream_t s);
+hipError_t launch_image_synth(const Inst* d, int W, int t1, const float* D, long long ldd,
+                              float* X, hipStream_t s);
+hipError_t launch_image_step(const Inst* d, int W, int n, int t, int step, float beta1,
+                             float beta2, float htv, float wlv, const float* D, long long ldd,
+                             const float* X, const float* Sd_cur, float* Sd_next, hipStream_t s);
+
 // clomp_grad kernels
 hipError_t launch_grad(int f64, int n, int m, long long lda, const void* A, const void* x,
                        const unsigned char* mask, const void* y, const void* grad_out,

@@ -82,6 +82,8 @@ struct Plan {
   bool ishared = false;               // IHT / paper mode with a shared dictionary: one
                                       // A^T R contraction per iteration
   size_t off_gf = 0, off_gdg = 0;     // shared Gram matrix and diagonal (workspace)
+  bool image = false;                 // CLOMP_FLAG_IMAGE on the shared-dictionary schedule
+  size_t off_dct = 0, off_sd = 0, off_x = 0;   // image mode: basis, coefficient images, pixels
   int nbig = 0;                       // sorted instances [0, nbig) use the iterated kernels;
                                       // [nbig, count) run the fused small-signal loop
   std::vector<int> small_list;
@@ -219,8 +221,39 @@ clomp_status_t check_params(clomp_ctx* h, const clomp_params_t* p) {
   if ((p->flags & CLOMP_FLAG_NO_REFINE) &&
       !(p->method == CLOMP_METHOD_CLOMP || p->method == CLOMP_METHOD_OMP))
     return fail(h, CLOMP_NOT_SUPPORTED, "CLOMP_FLAG_NO_REFINE is served for CLOMP and OMP");
-  if ((p->flags & CLOMP_FLAG_NO_REFINE) && p->prior_tv > 0.f)
+  if ((p->flags & CLOMP_FLAG_NO_REFINE) && p->prior_tv > 0.f && !(p->flags & CLOMP_FLAG_IMAGE))
     return fail(h, CLOMP_NOT_SUPPORTED, "CLOMP_FLAG_NO_REFINE is not served with the prior");
+  if (!(p->prior_lv >= 0.f && p->prior_lv <= 3.402823466e38f))
+    return fail(h, CLOMP_INVALID_ARGUMENT, "prior_lv must be finite and >= 0");
+  if (p->prior_lv > 0.f && !(p->flags & CLOMP_FLAG_IMAGE))
+    return fail(h, CLOMP_NOT_SUPPORTED, "the local-variation prior needs CLOMP_FLAG_IMAGE");
+  if (p->flags & CLOMP_FLAG_IMAGE) {
+    if (p->method != CLOMP_METHOD_CLOMP)
+      return fail(h, CLOMP_NOT_SUPPORTED, "CLOMP_FLAG_IMAGE is served for CLOMP");
+    if (p->flags & (CLOMP_FLAG_NO_SHARED_GRAM | CLOMP_FLAG_RESIDUAL_FLOW))
+      return fail(h, CLOMP_NOT_SUPPORTED,
+                  "CLOMP_FLAG_IMAGE runs the shared-dictionary schedule only");
+  }
+  return CLOMP_OK;
+}
+
+// The columns of an image (CLOMP_FLAG_IMAGE): one dictionary for all, the
+// same k, sizes within the image kernels' limits.
+clomp_status_t check_image_batch(clomp_ctx* h, const clomp_instance_t* inst, int32_t count) {
+  if (count <= 0) return CLOMP_OK;
+  const clomp_instance_t& a = inst[0];
+  for (int i = 1; i < count; ++i) {
+    const clomp_instance_t& b = inst[i];
+    if (!(a.A == b.A && a.lda == b.lda && a.n == b.n && a.m == b.m && a.k == b.k &&
+          a.A_master == b.A_master && a.lda_master == b.lda_master))
+      return fail(h, CLOMP_NOT_SUPPORTED,
+                  "CLOMP_FLAG_IMAGE: instance %d differs from instance 0 in A, its layout, its "
+                  "master or k (the columns of an image share all of them)", i);
+  }
+  if (a.n > kImageMaxN)
+    return fail(h, CLOMP_NOT_SUPPORTED, "CLOMP_FLAG_IMAGE: n = %d exceeds %d", a.n, kImageMaxN);
+  if (std::min(a.k, std::min(a.m, a.n)) > kImageMaxK)
+    return fail(h, CLOMP_NOT_SUPPORTED, "CLOMP_FLAG_IMAGE: k_eff exceeds %d", kImageMaxK);
   return CLOMP_OK;
 }
 
@@ -315,7 +348,9 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
   std::vector<int> order(count);
   std::vector<int> lpa(count), keff(count);
   std::vector<char> fused(count, 0);
-  const bool allow_fused = !(prm.flags & CLOMP_FLAG_NO_FUSED_SMALL) && !iht;
+  const bool image = (prm.flags & CLOMP_FLAG_IMAGE) != 0;
+  // (the columns of an image iterate in lock-step: none runs the fused loop)
+  const bool allow_fused = !(prm.flags & CLOMP_FLAG_NO_FUSED_SMALL) && !iht && !image;
   for (int i = 0; i < count; ++i) {
     order[i] = i;
     lpa[i] = pick_lpa(inst[i].m, vw);
@@ -352,7 +387,9 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     // shared dictionary: every iterated signal has the same A (pointer, layout,
     // master) and the full Gram matrix fits in 4 GB; an iteration then reads
     // columns of A^T A instead of streaming A
-    const bool sameA = !(fl & CLOMP_FLAG_NO_SHARED_GRAM) && same_dictionary(inst, order, P.nbig);
+    // (an image of one column keeps the shared-dictionary schedule too)
+    const bool sameA = !(fl & CLOMP_FLAG_NO_SHARED_GRAM) &&
+                       (same_dictionary(inst, order, P.nbig) || (image && P.nbig == 1));
     // IHT / paper mode: the batch's gradient as one contraction pays only when
     // it has enough 128 x 128 output tiles to fill the device; a small batch
     // (a 256 x 256 image: four tiles) scans per signal instead
@@ -386,6 +423,19 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     P.off_gdg = ws;
     ws = align_up(ws + sizeof(float) * l, kAlign);
   }
+  P.image = image && P.gflow;
+  if (P.image) {
+    // the DCT-II synthesis basis (n columns of ldh), two dense coefficient
+    // images (ping-pong by Adam step) and, with the local variation, the
+    // pixel image
+    const size_t l = (size_t)round_up_int(inst[order[0]].n, 256);
+    P.off_dct = ws;
+    ws = align_up(ws + sizeof(float) * l * inst[order[0]].n, kAlign);
+    P.off_sd = ws;
+    ws = align_up(ws + sizeof(float) * 2 * l * count, kAlign);
+    P.off_x = ws;
+    ws = align_up(ws + sizeof(float) * l * count, kAlign);
+  }
   snprintf(sigbuf, sizeof sigbuf, "d%d;m%d;T%d;s%d;p%d;w%d;r%d;", bf16, prm.method,
            prm.inner_steps, scan_kb, pass_kb, h->team_min_rows, h->rscan_min_t);
   P.sig += sigbuf;
@@ -404,6 +454,7 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
     d.rnorm = src.resid_norm;
     d.status = src.status;
     d.lda = src.lda;
+    d.col = i;
     d.n = src.n;
     d.m = src.m;
     d.k = src.k;
@@ -782,6 +833,36 @@ clomp_status_t launch_hflow(clomp_ctx* h, const Plan& P, int bf16, hipStream_t s
             lds = tlds;
           }
         }
+        if (P.image) {
+          // the columns of one image: selection record, then every Adam step
+          // as one launch over all columns (the priors couple neighbours)
+          char* wsb = reinterpret_cast<char*>(h->ws.p);
+          const long long ldd = round_up_int(P.insts[0].n, 256);
+          const float* Dm = reinterpret_cast<const float*>(wsb + P.off_dct);
+          float* Sd = reinterpret_cast<float*>(wsb + P.off_sd);
+          float* X = reinterpret_cast<float*>(wsb + P.off_x);
+          const int Wc = c.i1 - c.i0;   // one class: every column
+          const float htv = 2.f * prm.prior_tv / (float)Wc;
+          {
+            PhaseScope ps(h, PH_COEF, st);
+            HIP_TRY(launch_image_record(d_insts + c.i0, Wc, t, prm.lr_rel, prm.eps_rel, st),
+                    "image record");
+          }
+          for (int tau = 0; tau < prm.inner_steps; ++tau) {
+            const int step = t * prm.inner_steps + tau + 1;
+            const float* cur = Sd + (long long)((step - 1) & 1) * ldd * Wc;
+            float* nxt = Sd + (long long)(step & 1) * ldd * Wc;
+            if (prm.prior_lv > 0.f) {
+              PhaseScope ps(h, PH_COEF, st);
+              HIP_TRY(launch_image_synth(d_insts + c.i0, Wc, t + 1, Dm, ldd, X, st),
+                      "image synth");
+            }
+            PhaseScope ps(h, PH_COEF, st);
+            HIP_TRY(launch_image_step(d_insts + c.i0, Wc, P.insts[0].n, t, step, prm.beta1,
+                                      prm.beta2, htv, prm.prior_lv, Dm, ldd, X, cur, nxt, st),
+                    "image step");
+          }
+        } else
         // Split launch: with a shared dictionary no pass shares the launch, and
         // with more active signals than CUs the 16-wave coefficient workgroups
         // of a fused launch would hold the device before any pass tile runs.
@@ -994,6 +1075,15 @@ clomp_status_t launch_all(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st)
   {
     PhaseScope ps(h, PH_INIT, st, false);
     HIP_TRY(launch_init(d_insts, count, st), "init");
+    if (P.image) {
+      // the basis, and both dense coefficient images and the pixel image at
+      // zero (contiguous in the workspace)
+      char* wsb = reinterpret_cast<char*>(h->ws.p);
+      const long long ldd = round_up_int(P.insts[0].n, 256);
+      HIP_TRY(launch_image_init(reinterpret_cast<float*>(wsb + P.off_dct), P.insts[0].n, ldd,
+                                reinterpret_cast<float*>(wsb + P.off_sd), 3LL * ldd * count, st),
+              "image init");
+    }
   }
   if (!P.small_list.empty()) {
     const int* d_small = reinterpret_cast<const int*>(tb + P.off_small);
@@ -1077,7 +1167,9 @@ clomp_status_t launch_all(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st)
     }
   }
   // refinement (or, with CLOMP_FLAG_NO_REFINE, the greedy loop's coefficients)
-  const bool refine = !(prm.flags & CLOMP_FLAG_NO_REFINE);
+  // (image mode returns the learned coefficients: the local variation is not
+  // quadratic, so no least-squares solve minimises the same loss)
+  const bool refine = !(prm.flags & CLOMP_FLAG_NO_REFINE) && !P.image;
   const int ncg = refine ? (int)P.cg_list.size() : 0;
   {
   PhaseScope ref_scope(h, PH_REFINE, st, false);
@@ -1301,6 +1393,7 @@ void clomp_default_params(clomp_params_t* p) {
   p->flags = 0u;
   p->select_threshold = 0.7f;
   p->prior_tv = 0.f;
+  p->prior_lv = 0.f;
 }
 
 const char* clomp_status_string(clomp_status_t s) {
@@ -1385,7 +1478,9 @@ clomp_status_t clomp_set_params(clomp_handle_t h, const clomp_params_t* params) 
 
 clomp_status_t clomp_check_batch(clomp_handle_t h, const clomp_instance_t* inst, int32_t count,
                                  int32_t a_dtype) {
-  return check_batch_impl(h, inst, count, a_dtype);
+  const clomp_status_t s = check_batch_impl(h, inst, count, a_dtype);
+  if (s != CLOMP_OK || !h || !(h->params.flags & CLOMP_FLAG_IMAGE)) return s;
+  return check_image_batch(h, inst, count);
 }
 
 clomp_status_t clomp_solve_batch(clomp_handle_t h, const clomp_instance_t* inst, int32_t count,
@@ -1393,6 +1488,8 @@ clomp_status_t clomp_solve_batch(clomp_handle_t h, const clomp_instance_t* inst,
   if (!h) return CLOMP_INVALID_ARGUMENT;
   clomp_status_t s = check_batch_impl(h, inst, count, a_dtype);
   if (s != CLOMP_OK || count == 0) return s;
+  if ((h->params.flags & CLOMP_FLAG_IMAGE) && (s = check_image_batch(h, inst, count)) != CLOMP_OK)
+    return s;
   const int bf16 = a_dtype == CLOMP_BF16;
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   DeviceGuard dg;
@@ -1459,7 +1556,10 @@ clomp_status_t clomp_solve_batch(clomp_handle_t h, const clomp_instance_t* inst,
   const Plan& PP = h->pcache.P;
   h->last_scan_kb = scan_kb;
   h->last_pass_kb = pass_kb;
-  if (h->params.prior_tv > 0.f && !PP.cg_list.empty())
+  if ((h->params.flags & CLOMP_FLAG_IMAGE) && !PP.image)
+    return fail(h, CLOMP_NOT_SUPPORTED,
+                "CLOMP_FLAG_IMAGE needs the shared-dictionary schedule (Gram matrix within 4 GB)");
+  if (h->params.prior_tv > 0.f && !PP.cg_list.empty() && !PP.image)
     return fail(h, CLOMP_NOT_SUPPORTED,
                 "the total-variation prior needs the in-LDS QR refinement: (m + k_eff) * k_eff "
                 "of a signal exceeds it");

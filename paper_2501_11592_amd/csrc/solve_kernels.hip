@@ -3033,6 +3033,193 @@ __global__ __launch_bounds__(G == 16 ? 1024 : 256) void cscan_kernel(
   if (lane == 0 && key) atomicMax(&I.key[t & 1], key);
 }
 
+// ============================================================ image priors
+// CLOMP on the columns of one image (CLOMP_FLAG_IMAGE): column c of the image
+// is x_c = D s_c (D the orthonormal DCT-II synthesis basis, n x n); the loss
+// adds w_tv TV(X) (Eq. (6): the within-column term of the 1-D prior, which
+// sits on the Gram diagonal, plus (w_tv / W) sum_c ||s_c - s_c+1||^2, the
+// between-column term written in the coefficients since D is orthonormal) and
+// w_lv LV(X) (Eq. (7): mean over every 3 x 3 window, step 1, of the sample
+// standard deviation).  The supports are sparse, so x_c = D_S s_S and the
+// local-variation gradient D_S^T g_x cost n |S| per column: no full transform.
+// Every Adam step is one launch over all columns (two with the local
+// variation: the pixel image first), so that each column reads its
+// neighbours' values of the same step; the dense coefficient images alternate
+// by step parity.
+
+// D[i + k ldd] = c_k cos(pi k (2i + 1) / (2n)), c_0 = sqrt(1/n), c_k = sqrt(2/n)
+// (the phase reduced modulo 4n in integers, cospi of an exact quotient); the
+// dense coefficient images and the pixel image start at zero.
+__global__ __launch_bounds__(kBlock) void image_init_kernel(float* __restrict__ D, int n,
+                                                            long long ldd,
+                                                            float* __restrict__ zero,
+                                                            long long nzero) {
+  const long long stride = (long long)gridDim.x * kBlock;
+  const long long nd = (long long)n * n;
+  for (long long q = (long long)blockIdx.x * kBlock + threadIdx.x; q < nd + nzero; q += stride) {
+    if (q < nd) {
+      const int k = (int)(q / n), i = (int)(q % n);
+      const long long p = ((long long)k * (2 * i + 1)) % (4LL * n);
+      const float ck = sqrtf((k == 0 ? 1.f : 2.f) / (float)n);
+      D[i + (long long)k * ldd] = ck * cospif((float)p / (float)(2 * n));
+    } else {
+      zero[q - nd] = 0.f;
+    }
+  }
+}
+
+// Selection record of iteration t of every live column (no coefficient update).
+__global__ __launch_bounds__(kBlock) void image_record_kernel(const Inst* __restrict__ insts,
+                                                              int t, float lr_rel,
+                                                              float eps_rel) {
+  const Inst& I = insts[blockIdx.x];
+  if (I.st->done) return;
+  const unsigned long long key = I.key[t & 1];
+  const int j = key_index(key);
+  if (key == 0ull || j < 0 || j >= I.n) {
+    if (threadIdx.x == 0) {
+      I.st->done = 1;
+      atomicOr(I.status, ST_WATCHDOG);
+    }
+    return;
+  }
+  record_selection<kBlock>(I, key, t, lr_rel, eps_rel);
+}
+
+// Pixel column x_c = sum_l D[:, S_l] s_l of every live column (t1 atoms).
+__global__ __launch_bounds__(kBlock) void image_synth_kernel(const Inst* __restrict__ insts,
+                                                             int t1, const float* __restrict__ D,
+                                                             long long ldd,
+                                                             float* __restrict__ X) {
+  __shared__ float ssh[kImageMaxK];
+  __shared__ int jsh[kImageMaxK];
+  const Inst& I = insts[blockIdx.x];
+  if (I.st->done) return;
+  for (int l = threadIdx.x; l < t1; l += kBlock) {
+    ssh[l] = I.s[l];
+    jsh[l] = I.support[l];
+  }
+  __syncthreads();
+  float* xc = X + (long long)I.col * ldd;
+  for (int i = threadIdx.x; i < I.n; i += kBlock) {
+    float acc = 0.f;
+    for (int l = 0; l < t1; ++l) acc = fmaf(D[i + (long long)jsh[l] * ldd], ssh[l], acc);
+    xc[i] = acc;
+  }
+}
+
+// One Adam step (number `step`, 1-based) of every live column on
+//   1/2 ||y_c - A s_c||^2 + w_tv TV(X) + w_lv LV(X)
+// restricted to the column's support of t1 = t + 1 atoms: the data term and
+// the within-column TV from the Gram matrix (G s - b, prior on the diagonal),
+// htv = 2 w_tv / W times the differences to the neighbours' coefficients
+// (Sd_cur, dense, ld ldd), and w_lv times D_S^T of the column's pixel gradient
+// of LV, formed from the pixel columns c-2 .. c+2 of X staged in LDS.  The
+// updated coefficients go to I.s (support order) and to Sd_next.
+__global__ __launch_bounds__(kBlock) void image_step_kernel(
+    const Inst* __restrict__ insts, int W, int t, int step, float beta1, float beta2, float htv,
+    float wlv, const float* __restrict__ D, long long ldd, const float* __restrict__ X,
+    const float* __restrict__ Sd_cur, float* __restrict__ Sd_next) {
+  extern __shared__ __align__(16) float xsh[];    // with LV: 5 pixel columns | pixel gradient
+  __shared__ float ssh[kImageMaxK];
+  __shared__ int jsh[kImageMaxK];
+  __shared__ float gsh[kImageMaxK];
+  const Inst& I = insts[blockIdx.x];
+  if (I.st->done) return;
+  const int t1 = t + 1, n = I.n, c = I.col;
+  const int tid = threadIdx.x;
+  for (int l = tid; l < t1; l += kBlock) {
+    ssh[l] = I.s[l];
+    jsh[l] = I.support[l];
+    gsh[l] = 0.f;
+  }
+  if (wlv != 0.f && n >= 3 && W >= 3) {
+    // pixel columns c-2 .. c+2 (those inside the image)
+    for (int q = 0; q < 5; ++q) {
+      const int cc = c - 2 + q;
+      for (int i = tid; i < n; i += kBlock)
+        xsh[q * n + i] = (cc >= 0 && cc < W) ? X[i + (long long)cc * ldd] : 0.f;
+    }
+    __syncthreads();
+    // d LV / d x[i, c]: every window (centre rows 1 .. n-2, centre columns
+    // 1 .. W-2) that holds the pixel adds (x - mean) / (8 std) (nothing when
+    // std = 0), divided by the number of windows
+    float* gx = xsh + 5 * n;
+    const float invB = 1.f / ((float)(n - 2) * (float)(W - 2));
+    for (int i = tid; i < n; i += kBlock) {
+      float g = 0.f;
+      const float xi = xsh[2 * n + i];
+      for (int di = -1; di <= 1; ++di) {
+        const int ip = i + di;
+        if (ip < 1 || ip > n - 2) continue;
+        for (int dc = -1; dc <= 1; ++dc) {
+          const int cp = c + dc;
+          if (cp < 1 || cp > W - 2) continue;
+          const int q0 = dc + 1;                 // staged columns q0 .. q0+2
+          float sum = 0.f;
+#pragma unroll
+          for (int u = 0; u < 3; ++u)
+#pragma unroll
+            for (int v = -1; v <= 1; ++v) sum += xsh[(q0 + u) * n + ip + v];
+          const float mean = sum * (1.f / 9.f);
+          float ss = 0.f;
+#pragma unroll
+          for (int u = 0; u < 3; ++u)
+#pragma unroll
+            for (int v = -1; v <= 1; ++v) {
+              const float dlt = xsh[(q0 + u) * n + ip + v] - mean;
+              ss = fmaf(dlt, dlt, ss);
+            }
+          const float sd = sqrtf(ss * 0.125f);
+          if (sd > 0.f) g += (xi - mean) / (8.f * sd);
+        }
+      }
+      gx[i] = g * invB;
+    }
+    __syncthreads();
+    // D_S^T g_x: one wave per support row, lanes over the pixels
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int l = wv; l < t1; l += kBlock / 64) {
+      const float* dcol = D + (long long)jsh[l] * ldd;
+      float a = 0.f;
+      for (int i = lane; i < n; i += 64) a = fmaf(dcol[i], gx[i], a);
+      a = wave_sum(a);
+      if (lane == 0) gsh[l] = a;
+    }
+  }
+  __syncthreads();
+  const float lr = I.st->lr, eps = I.st->eps;
+  const float ibc1 = __builtin_amdgcn_rcpf((float)(1.0 - pow((double)beta1, (double)step)));
+  const float ibc2 = __builtin_amdgcn_rcpf((float)(1.0 - pow((double)beta2, (double)step)));
+  const long long ldg = I.ldg;
+  for (int l = tid; l < t1; l += kBlock) {
+    // G is symmetric: row l of every column, consecutive threads consecutive rows
+    float acc = 0.f;
+    for (int l2 = 0; l2 < t1; ++l2) acc = fmaf(I.G[l + (long long)l2 * ldg], ssh[l2], acc);
+    float gr = acc - I.b[l];
+    const int j = jsh[l];
+    const float sl = ssh[l];
+    if (htv != 0.f) {
+      float hd = 0.f;
+      if (c > 0) hd += sl - Sd_cur[j + (long long)(c - 1) * ldd];
+      if (c < W - 1) hd += sl - Sd_cur[j + (long long)(c + 1) * ldd];
+      gr = fmaf(htv, hd, gr);
+    }
+    if (wlv != 0.f) gr = fmaf(wlv, gsh[l], gr);
+    float mo = I.mo[l], ve = I.ve[l];
+    mo = beta1 * mo + (1.f - beta1) * gr;
+    ve = beta2 * ve + (1.f - beta2) * (gr * gr);
+    const float mh = mo * ibc1;
+    const float vh = ve * ibc2;
+    const float sv = sl - lr * mh * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(vh) + eps);
+    I.s[l] = sv;
+    I.mo[l] = mo;
+    I.ve[l] = ve;
+    Sd_next[j + (long long)c * ldd] = sv;
+  }
+  if (tid == 0) I.st->step = step;
+}
+
 // Coefficient update of iteration t when no pass shares the launch (shared
 // dictionary, CLOMP, t+1 <= 256): one workgroup of ceil((t+1)/16) waves per
 // signal, so small supports do not hold a 16-wave workgroup each and several
@@ -3472,7 +3659,7 @@ hipError_t set_max_lds(size_t bytes) {
       (const void*)cg_dots_kernel<64, 0>, (const void*)cg_dots_kernel<4, 1>,
       (const void*)cg_dots_kernel<8, 1>, (const void*)cg_dots_kernel<16, 1>,
       (const void*)cg_dots_kernel<32, 1>, (const void*)cg_dots_kernel<64, 1>,
-      (const void*)qr_refine_kernel};
+      (const void*)qr_refine_kernel, (const void*)image_step_kernel};
   return raise_dynamic_lds(fns, sizeof(fns) / sizeof(fns[0]), bytes);
 }
 
@@ -3672,6 +3859,41 @@ hipError_t launch_cscan(const Inst* d, const ScanTile* tiles, int ntiles, int t,
     CLOMP_LAUNCH(cscan_kernel<4>, dim3(ntiles), dim3(256), 0, s, d, tiles, ntiles, t);
   else
     CLOMP_LAUNCH(cscan_kernel<16>, dim3(ntiles), dim3(1024), 0, s, d, tiles, ntiles, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_image_init(float* D, int n, long long ldd, float* zero, long long nzero,
+                             hipStream_t s) {
+  const long long tot = (long long)n * n + nzero;
+  const int grid = (int)std::min<long long>((tot + kBlock - 1) / kBlock, 4096);
+  CLOMP_LAUNCH(image_init_kernel, dim3(std::max(grid, 1)), dim3(kBlock), 0, s, D, n, ldd, zero,
+               nzero);
+  return hipGetLastError();
+}
+
+hipError_t launch_image_record(const Inst* d, int W, int t, float lr_rel, float eps_rel,
+                               hipStream_t s) {
+  if (W <= 0) return nothing_to_launch(s);
+  CLOMP_LAUNCH(image_record_kernel, dim3(W), dim3(kBlock), 0, s, d, t, lr_rel, eps_rel);
+  return hipGetLastError();
+}
+
+hipError_t launch_image_synth(const Inst* d, int W, int t1, const float* D, long long ldd,
+                              float* X, hipStream_t s) {
+  if (W <= 0) return nothing_to_launch(s);
+  if (t1 > kImageMaxK) return hipErrorInvalidValue;
+  CLOMP_LAUNCH(image_synth_kernel, dim3(W), dim3(kBlock), 0, s, d, t1, D, ldd, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_image_step(const Inst* d, int W, int n, int t, int step, float beta1,
+                             float beta2, float htv, float wlv, const float* D, long long ldd,
+                             const float* X, const float* Sd_cur, float* Sd_next, hipStream_t s) {
+  if (W <= 0) return nothing_to_launch(s);
+  if (t + 1 > kImageMaxK || n > kImageMaxN) return hipErrorInvalidValue;
+  const size_t lds = (wlv != 0.f && n >= 3 && W >= 3) ? (size_t)6 * n * sizeof(float) : 0;
+  CLOMP_LAUNCH(image_step_kernel, dim3(W), dim3(kBlock), lds, s, d, W, t, step, beta1, beta2,
+               htv, wlv, D, ldd, X, Sd_cur, Sd_next);
   return hipGetLastError();
 }
 

@@ -49,7 +49,7 @@ def test_status_strings_and_defaults(lib):
     assert p.method == 0 and p.inner_steps == 32
     assert abs(p.lr_rel - 0.05) < 1e-7 and abs(p.beta1 - 0.9) < 1e-7
     assert abs(p.beta2 - 0.999) < 1e-7 and p.resid_tol == 0.0
-    assert abs(p.select_threshold - 0.7) < 1e-7 and p.prior_tv == 0.0
+    assert abs(p.select_threshold - 0.7) < 1e-7 and p.prior_tv == 0.0 and p.prior_lv == 0.0
 
 
 def header_struct_fields(name):
@@ -80,7 +80,7 @@ def test_tuning_struct_size():
 
 def test_struct_layout_matches_header():
     assert ctypes.sizeof(C.Instance) == 4 * 4 + 2 * 8 + 8 * 8
-    assert ctypes.sizeof(C.Params) == 12 * 4
+    assert ctypes.sizeof(C.Params) == 13 * 4
 
 
 def _inst(n=100, m=20, k=5, lda=20, A=4096, Am=0, ldm=0, y=8192):
