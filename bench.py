@@ -68,6 +68,10 @@ def parse():
     ap.add_argument("--no-shared-gram", action="store_true",
                     help="keep per-signal passes over a shared A (no full Gram matrix)")
     ap.add_argument("--profile-steps", type=int, default=2)
+    ap.add_argument("--pass-tile-kb", type=int, default=0,
+                    help="bulk-matrix KB per pass workgroup (0: the library default)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="let the library time its tile candidates on the first call")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 5 device copies of 1 GiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -321,10 +325,14 @@ def main():
               else torch.cuda.Stream(torch.device("cuda", 0)))
     flow_flag = {"auto": 0, "resid": C.FLAG_RESIDUAL_FLOW, "corr": C.FLAG_CORR_FLOW}[args.flow]
     flow_flag |= C.FLAG_NO_SHARED_GRAM if args.no_shared_gram else 0
+    flow_flag |= C.FLAG_AUTOTUNE if args.autotune else 0
     flags = (0 if args.no_graph else C.FLAG_GRAPH) | flow_flag
     methods = ("clomp", "omp") + (() if args.no_iht else ("iht",)) + (
         () if args.no_paper else ("clomp_paper",))
     solvers = {m: C.Solver(0, method=m, flags=flags) for m in methods}
+    if args.pass_tile_kb:
+        for sv in solvers.values():
+            sv.set_tuning(pass_tile_kb=args.pass_tile_kb)
     # IHT (200 iterations, the experiments' comparison method) runs on the
     # same storage as CLOMP
     items = {"clomp": wl["clomp_items"], "omp": wl["omp_items"], "iht": wl["clomp_items"],
@@ -359,6 +367,8 @@ def main():
     prof = {}
     for method in (methods if args.profile_steps > 0 else ()):
         ps = C.Solver(0, method=method, flags=C.FLAG_PROFILE | flow_flag)
+        if args.pass_tile_kb:
+            ps.set_tuning(pass_tile_kb=args.pass_tile_kb)
         pp = ps.prepare(items[method], stream=stream)
         ps.run(pp, stream=stream)
         torch.cuda.synchronize()
