@@ -72,6 +72,9 @@ def parse():
                     help="bulk-matrix KB per pass workgroup (0: the library default)")
     ap.add_argument("--autotune", action="store_true",
                     help="let the library time its tile candidates on the first call")
+    ap.add_argument("--image-priors", type=float, nargs=2, default=None, metavar=("W_TV", "W_LV"),
+                    help="image workload: also run CLOMP on the columns as one image with "
+                         "the 2-D total variation and local variation weights given")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 5 device copies of 1 GiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -192,7 +195,7 @@ def kernel_digest():
     def region(a, b):
         return src[src.index(mark + a):src.index(mark + b)]
     text = region("Adam (CLOMP)", "rows kernels") + \
-        region("correlation-update schedule", "launchers") + hdr
+        region("correlation-update schedule", "image priors") + hdr
     return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
@@ -329,14 +332,26 @@ def main():
     flags = (0 if args.no_graph else C.FLAG_GRAPH) | flow_flag
     methods = ("clomp", "omp") + (() if args.no_iht else ("iht",)) + (
         () if args.no_paper else ("clomp_paper",))
-    solvers = {m: C.Solver(0, method=m, flags=flags) for m in methods}
+    # the image leg: the columns coupled by the priors of Eq. (6) and (7)
+    image_leg = args.image_priors is not None and wl["name"].startswith("image_sr")
+    if args.image_priors is not None and not image_leg:
+        raise SystemExit("--image-priors needs --workload image")
+    methods += ("clomp_image",) if image_leg else ()
+
+    def make_solver(m, fl):
+        if m == "clomp_image":
+            return C.Solver(0, method="clomp", flags=fl | C.FLAG_IMAGE,
+                            prior_tv=args.image_priors[0], prior_lv=args.image_priors[1])
+        return C.Solver(0, method=m, flags=fl)
+
+    solvers = {m: make_solver(m, flags) for m in methods}
     if args.pass_tile_kb:
         for sv in solvers.values():
             sv.set_tuning(pass_tile_kb=args.pass_tile_kb)
     # IHT (200 iterations, the experiments' comparison method) runs on the
     # same storage as CLOMP
     items = {"clomp": wl["clomp_items"], "omp": wl["omp_items"], "iht": wl["clomp_items"],
-             "clomp_paper": wl["clomp_items"]}
+             "clomp_paper": wl["clomp_items"], "clomp_image": wl["clomp_items"]}
     count = len(items["clomp"])
 
     # descriptors and outputs packed once (inputs stay resident); every step
@@ -366,7 +381,7 @@ def main():
     # --profile-steps 0 skips it (runs under hardware-counter collection)
     prof = {}
     for method in (methods if args.profile_steps > 0 else ()):
-        ps = C.Solver(0, method=method, flags=C.FLAG_PROFILE | flow_flag)
+        ps = make_solver(method, C.FLAG_PROFILE | flow_flag)
         if args.pass_tile_kb:
             ps.set_tuning(pass_tile_kb=args.pass_tile_kb)
         pp = ps.prepare(items[method], stream=stream)
@@ -414,6 +429,10 @@ def main():
                          "ms_per_step": 1e3 * timings["clomp_paper"], "iterations": 200,
                          "threshold": 0.7, "dtype": wl["dtype"]}
                         if "clomp_paper" in timings else None),
+        "clomp_image": ({"value": count / timings["clomp_image"], "unit": "signals/s",
+                         "ms_per_step": 1e3 * timings["clomp_image"],
+                         "prior_tv": args.image_priors[0], "prior_lv": args.image_priors[1],
+                         "dtype": wl["dtype"]} if "clomp_image" in timings else None),
         "accuracy": acc,
         "accuracy_gate_1e-3": (all(a["rel_err"] <= 1e-3 for a in acc.values()) if acc else None),
         "status_flags_nonzero": {m: int((st[m] != 0).sum()) for m in st},

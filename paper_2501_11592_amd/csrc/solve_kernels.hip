@@ -3033,6 +3033,56 @@ __global__ __launch_bounds__(G == 16 ? 1024 : 256) void cscan_kernel(
   if (lane == 0 && key) atomicMax(&I.key[t & 1], key);
 }
 
+// Coefficient update of iteration t when no pass shares the launch (shared
+// dictionary, CLOMP, t+1 <= 256): one workgroup of ceil((t+1)/16) waves per
+// signal, so small supports do not hold a 16-wave workgroup each and several
+// signals share a CU; RPL rows of G per lane for supports up to 64*RPL.  The
+// selection record, then the register-tile Adam.
+template <int RPL>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(RPL == 2 ? 6 : 1)))
+void coef_reg_kernel(const Inst* __restrict__ insts_c, int t,
+                                                        int T, float beta1, float beta2,
+                                                        float lr_rel, float eps_rel) {
+  __shared__ __align__(16) float part[adam_part_floats<RPL>()];
+  const Inst& I = insts_c[blockIdx.x];
+  if (I.st->done) return;
+  const unsigned long long key = I.key[t & 1];
+  const int j = key_index(key);
+  if (key == 0ull || j < 0 || j >= I.n) {
+    if (threadIdx.x == 0) {
+      I.st->done = 1;
+      atomicOr(I.status, ST_WATCHDOG);
+    }
+    return;
+  }
+  record_selection<0>(I, key, t, lr_rel, eps_rel);
+  __syncthreads();
+  adam_reg_body<RPL>(I, t, T, beta1, beta2, part, blockDim.x >> 6, false);
+}
+
+// OMP counterpart of coef_reg_kernel: the selection record and the
+// bordered-inverse update of iteration t in one 256-thread workgroup per
+// signal (no pass in the launch).
+__global__ __launch_bounds__(256) void coef_omp_kernel(const Inst* __restrict__ insts_c, int t,
+                                                       float lr_rel, float eps_rel) {
+  extern __shared__ __align__(16) float osh[];   // g[t+1] | v[t+1] | vpart[t+1]
+  __shared__ float red[4], red2[4];
+  const Inst& I = insts_c[blockIdx.x];
+  if (I.st->done) return;
+  const unsigned long long key = I.key[t & 1];
+  const int j = key_index(key);
+  if (key == 0ull || j < 0 || j >= I.n) {
+    if (threadIdx.x == 0) {
+      I.st->done = 1;
+      atomicOr(I.status, ST_WATCHDOG);
+    }
+    return;
+  }
+  record_selection<256>(I, key, t, lr_rel, eps_rel);
+  __syncthreads();
+  omp_ginv_body<256>(I, t, osh, red, red2, false);
+}
+
 // ============================================================ image priors
 // CLOMP on the columns of one image (CLOMP_FLAG_IMAGE): column c of the image
 // is x_c = D s_c (D the orthonormal DCT-II synthesis basis, n x n); the loss
@@ -3218,56 +3268,6 @@ __global__ __launch_bounds__(kBlock) void image_step_kernel(
     Sd_next[j + (long long)c * ldd] = sv;
   }
   if (tid == 0) I.st->step = step;
-}
-
-// Coefficient update of iteration t when no pass shares the launch (shared
-// dictionary, CLOMP, t+1 <= 256): one workgroup of ceil((t+1)/16) waves per
-// signal, so small supports do not hold a 16-wave workgroup each and several
-// signals share a CU; RPL rows of G per lane for supports up to 64*RPL.  The
-// selection record, then the register-tile Adam.
-template <int RPL>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(RPL == 2 ? 6 : 1)))
-void coef_reg_kernel(const Inst* __restrict__ insts_c, int t,
-                                                        int T, float beta1, float beta2,
-                                                        float lr_rel, float eps_rel) {
-  __shared__ __align__(16) float part[adam_part_floats<RPL>()];
-  const Inst& I = insts_c[blockIdx.x];
-  if (I.st->done) return;
-  const unsigned long long key = I.key[t & 1];
-  const int j = key_index(key);
-  if (key == 0ull || j < 0 || j >= I.n) {
-    if (threadIdx.x == 0) {
-      I.st->done = 1;
-      atomicOr(I.status, ST_WATCHDOG);
-    }
-    return;
-  }
-  record_selection<0>(I, key, t, lr_rel, eps_rel);
-  __syncthreads();
-  adam_reg_body<RPL>(I, t, T, beta1, beta2, part, blockDim.x >> 6, false);
-}
-
-// OMP counterpart of coef_reg_kernel: the selection record and the
-// bordered-inverse update of iteration t in one 256-thread workgroup per
-// signal (no pass in the launch).
-__global__ __launch_bounds__(256) void coef_omp_kernel(const Inst* __restrict__ insts_c, int t,
-                                                       float lr_rel, float eps_rel) {
-  extern __shared__ __align__(16) float osh[];   // g[t+1] | v[t+1] | vpart[t+1]
-  __shared__ float red[4], red2[4];
-  const Inst& I = insts_c[blockIdx.x];
-  if (I.st->done) return;
-  const unsigned long long key = I.key[t & 1];
-  const int j = key_index(key);
-  if (key == 0ull || j < 0 || j >= I.n) {
-    if (threadIdx.x == 0) {
-      I.st->done = 1;
-      atomicOr(I.status, ST_WATCHDOG);
-    }
-    return;
-  }
-  record_selection<256>(I, key, t, lr_rel, eps_rel);
-  __syncthreads();
-  omp_ginv_body<256>(I, t, osh, red, red2, false);
 }
 
 // ============================================================ launchers
