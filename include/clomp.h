@@ -412,13 +412,55 @@ typedef struct {
 clomp_status_t clomp_set_tuning(clomp_handle_t h, const clomp_tuning_t* t /*host*/);
 clomp_status_t clomp_get_tuning(clomp_handle_t h, clomp_tuning_t* t /*host*/);
 
+/*
+ * The process-wide autotune table (host only; no handle, no device call).
+ * Under CLOMP_FLAG_AUTOTUNE a solve looks up its size class first in its
+ * handle's own table, then here, and times the candidates only when neither
+ * has it; every timed choice is written to both.  The table outlives handles,
+ * and these three calls move it across processes as text:
+ *
+ *   clomp-tuning 1
+ *   <key> <tile KB>
+ *   ...
+ *
+ * One entry per line ('\n', optionally '\r\n'); blank lines and lines that
+ * start with '#' are ignored.  A key names a size class as
+ * arch/dtype/method/schedule/m<o>/n<o>/c<o> (for example
+ * gfx950/bf16/clomp/corr/m12/n13/c12: device architecture, bulk dtype,
+ * method, correlation-update or residual schedule, and the octaves
+ * floor(log2 v) of the largest m, the largest n and the number of iterated
+ * signals); at most 127 characters from [A-Za-z0-9_./:+-].  The value is the
+ * tile size in KB that the schedule's tile field takes (pass_tile_kb for
+ * "corr", scan_tile_kb for "resid"), 1 .. 65536.
+ *
+ * clomp_tuning_table_import merges `text` (NUL-terminated) into the table: an
+ * imported entry replaces one with the same key.  All or nothing: a missing
+ * header, a malformed line, a value out of range or a key given twice leaves
+ * the table unchanged and returns INVALID_ARGUMENT.  *n_entries (may be NULL)
+ * receives the number of entries imported.
+ * clomp_tuning_table_export writes the whole table, NUL-terminated, keys in
+ * byte order.  *len receives its length without the NUL; with buf NULL only
+ * the length is returned; a `cap` below len + 1 returns INVALID_ARGUMENT and
+ * writes nothing to buf.
+ * clomp_tuning_table_clear empties the table (handles keep their own).
+ * Failures of these calls are reported by clomp_last_error(NULL) on the
+ * calling thread.  The table is guarded by a lock: any thread may call them.
+ * (A tuning aid, not an operation of the method: a saved table lets later
+ * runs of the same size classes skip the candidate timing.)
+ */
+clomp_status_t clomp_tuning_table_import(const char* text /*host*/, int32_t* n_entries /*host*/);
+clomp_status_t clomp_tuning_table_export(char* buf /*host*/, size_t cap, size_t* len /*host*/);
+clomp_status_t clomp_tuning_table_clear(void);
+
 /* Free the handle, its workspace and graphs (synchronises its device). */
 clomp_status_t clomp_destroy(clomp_handle_t h);
 
 /* Static string naming a status code. */
 const char* clomp_status_string(clomp_status_t s);
 
-/* Message of the last failure on `h` ("" if none; static text if h is NULL). */
+/* Message of the last failure on `h` ("" if none).  With h NULL: the message
+ * of the calling thread's last failed handle-free call (the tuning table),
+ * else a static text. */
 const char* clomp_last_error(clomp_handle_t h);
 
 #ifdef __cplusplus

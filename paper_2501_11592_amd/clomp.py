@@ -135,6 +135,13 @@ def load_library(path=LIB_PATH):
     lib.clomp_status_string.restype = ctypes.c_char_p
     lib.clomp_last_error.argtypes = [H]
     lib.clomp_last_error.restype = ctypes.c_char_p
+    lib.clomp_tuning_table_import.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]
+    lib.clomp_tuning_table_import.restype = ctypes.c_int
+    lib.clomp_tuning_table_export.argtypes = [ctypes.c_char_p, ctypes.c_size_t,
+                                              ctypes.POINTER(ctypes.c_size_t)]
+    lib.clomp_tuning_table_export.restype = ctypes.c_int
+    lib.clomp_tuning_table_clear.argtypes = []
+    lib.clomp_tuning_table_clear.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -429,6 +436,47 @@ class Solver:
                 _ptr(grad_out), _ptr(gx), _ptr(u), _ptr(loss), ctypes.c_void_p(st.cuda_stream))
         _check(self._h, rc, name)
         return loss, gx, u
+
+
+def _check_table(rc, what):
+    if rc != 0:
+        msg = load_library().clomp_last_error(None).decode()
+        raise ClompError(f"{what}: {STATUS_NAMES.get(rc, rc)}: {msg}")
+
+
+def tuning_table_import(text):
+    """Merge a saved autotune table (the text of tuning_table_export) into the
+    process-wide table; returns the number of entries."""
+    n = ctypes.c_int32(0)
+    _check_table(load_library().clomp_tuning_table_import(text.encode(), ctypes.byref(n)),
+                 "clomp_tuning_table_import")
+    return n.value
+
+
+def tuning_table_export():
+    """The process-wide autotune table as text."""
+    lib = load_library()
+    ln = ctypes.c_size_t(0)
+    _check_table(lib.clomp_tuning_table_export(None, 0, ctypes.byref(ln)),
+                 "clomp_tuning_table_export")
+    buf = ctypes.create_string_buffer(ln.value + 1)
+    _check_table(lib.clomp_tuning_table_export(buf, ln.value + 1, ctypes.byref(ln)),
+                 "clomp_tuning_table_export")
+    return buf.value.decode()
+
+
+def tuning_table_clear():
+    _check_table(load_library().clomp_tuning_table_clear(), "clomp_tuning_table_clear")
+
+
+def save_tuning_table(path):
+    with open(path, "w") as f:
+        f.write(tuning_table_export())
+
+
+def load_tuning_table(path):
+    with open(path) as f:
+        return tuning_table_import(f.read())
 
 
 def check_batch(items_ctypes, count, dtype, handle=None):

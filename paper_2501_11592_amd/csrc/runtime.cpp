@@ -21,6 +21,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -161,6 +162,7 @@ struct clomp_ctx {
                                       // shared gradient (0: half the compute units)
   int last_scan_kb = kScanTargetKB, last_pass_kb = kPassTargetKB;   // of the last solve
   std::map<std::string, int> tuned;   // autotuned tile size per size class
+  std::string arch = "unknown";       // device architecture (first field of its name)
   PlanCache pcache;
 };
 
@@ -1279,12 +1281,50 @@ clomp_status_t stage_plan(clomp_ctx* h, const Plan& P, hipStream_t st) {
 // the fused pass of iteration 0 (correlation schedule, after the first pass
 // has chosen the atom) or the scan of iteration 0 (residual schedule).  The
 // probes leave only state that the solve's init launch resets.
-std::string tune_key(const Plan& P, int bf16, int method, double bulk_bytes) {
-  char buf[96];
-  snprintf(buf, sizeof buf, "d%d;h%d;o%d;b%d;n%d", bf16, (int)P.hflow, method,
-           (int)std::floor(2.0 * std::log2(std::max(bulk_bytes, 1.0))),
-           (int)std::floor(std::log2((double)std::max(P.nbig, 1))));
+// Size class of a batch for the autotuner: device architecture, bulk dtype,
+// method, schedule, and the octaves of the largest m, the largest n and the
+// number of iterated signals.
+std::string tune_key(const Plan& P, int bf16, int method, const std::string& arch) {
+  int mmax = 1, nmax = 1;
+  for (int q = 0; q < P.nbig; ++q) {
+    mmax = std::max(mmax, P.insts[q].m);
+    nmax = std::max(nmax, P.insts[q].n);
+  }
+  auto octave = [](int v) {
+    int o = 0;
+    while ((2LL << o) <= v) ++o;
+    return o;
+  };
+  static const char* kMethod[] = {"clomp", "omp", "iht", "paper"};
+  char buf[160];
+  snprintf(buf, sizeof buf, "%s/%s/%s/%s/m%d/n%d/c%d", arch.c_str(), bf16 ? "bf16" : "f32",
+           (method >= 0 && method < 4) ? kMethod[method] : "other", P.hflow ? "corr" : "resid",
+           octave(mmax), octave(nmax), octave(std::max(P.nbig, 1)));
   return buf;
+}
+
+// The process-wide autotune table: every handle's results, and the entries a
+// caller imported (a saved table from an earlier process).  A handle looks in
+// its own table, then here, and only then times the candidates.
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+thread_local std::string g_table_error;   // last error of a handle-free call
+
+clomp_status_t table_fail(const char* fmt, ...) {
+  char buf[256];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_table_error = buf;
+  return CLOMP_INVALID_ARGUMENT;
+}
+
+constexpr const char* kTableHeader = "clomp-tuning 1";
+
+bool key_char_ok(char c) {
+  return (c >= 'a' && c <= 'z') || (c >= 'A' && c <= 'Z') || (c >= '0' && c <= '9') ||
+         c == '_' || c == '.' || c == '/' || c == ':' || c == '+' || c == '-';
 }
 
 clomp_status_t probe_launch(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st, bool timed) {
@@ -1408,8 +1448,75 @@ const char* clomp_status_string(clomp_status_t s) {
 }
 
 const char* clomp_last_error(clomp_handle_t h) {
-  if (!h) return "no handle";
+  if (!h) return g_table_error.empty() ? "no handle" : g_table_error.c_str();
   return h->last_error.c_str();
+}
+
+clomp_status_t clomp_tuning_table_import(const char* text, int32_t* n_entries) {
+  g_table_error.clear();
+  if (!text) return table_fail("text is NULL");
+  std::map<std::string, int> add;
+  const char* p = text;
+  int line = 0;
+  bool header = false;
+  while (*p) {
+    const char* e = p;
+    while (*e && *e != '\n') ++e;
+    std::string ln(p, e);
+    p = *e ? e + 1 : e;
+    ++line;
+    if (!ln.empty() && ln.back() == '\r') ln.pop_back();
+    if (!header) {
+      if (ln != kTableHeader)
+        return table_fail("line 1: expected the header '%s'", kTableHeader);
+      header = true;
+      continue;
+    }
+    if (ln.empty() || ln[0] == '#') continue;
+    const size_t sp = ln.find(' ');
+    if (sp == std::string::npos || sp == 0 || sp > 127)
+      return table_fail("line %d: expected '<key> <tile KB>'", line);
+    const std::string key = ln.substr(0, sp);
+    for (char c : key)
+      if (!key_char_ok(c)) return table_fail("line %d: key has a character outside [A-Za-z0-9_./:+-]", line);
+    const std::string val = ln.substr(sp + 1);
+    if (val.empty() || val.size() > 5) return table_fail("line %d: tile KB must be 1 .. 65536", line);
+    long v = 0;
+    for (char c : val) {
+      if (c < '0' || c > '9') return table_fail("line %d: tile KB must be 1 .. 65536", line);
+      v = v * 10 + (c - '0');
+    }
+    if (v < 1 || v > 65536) return table_fail("line %d: tile KB must be 1 .. 65536", line);
+    if (!add.emplace(key, (int)v).second) return table_fail("line %d: key repeated", line);
+  }
+  if (!header) return table_fail("line 1: expected the header '%s'", kTableHeader);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& kv : add) g_tune[kv.first] = kv.second;
+  if (n_entries) *n_entries = (int32_t)add.size();
+  return CLOMP_OK;
+}
+
+clomp_status_t clomp_tuning_table_export(char* buf, size_t cap, size_t* len) {
+  g_table_error.clear();
+  if (!len) return table_fail("len is NULL");
+  std::string out = std::string(kTableHeader) + "\n";
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& kv : g_tune) out += kv.first + " " + std::to_string(kv.second) + "\n";
+  }
+  *len = out.size();
+  if (!buf) return CLOMP_OK;
+  if (cap < out.size() + 1)
+    return table_fail("buffer of %zu bytes; the table needs %zu", cap, out.size() + 1);
+  memcpy(buf, out.c_str(), out.size() + 1);
+  return CLOMP_OK;
+}
+
+clomp_status_t clomp_tuning_table_clear(void) {
+  g_table_error.clear();
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+  return CLOMP_OK;
 }
 
 clomp_status_t clomp_create(clomp_handle_t* out, int device, const clomp_params_t* params) {
@@ -1441,6 +1548,18 @@ clomp_status_t clomp_create(clomp_handle_t* out, int device, const clomp_params_
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
   h->lds_limit = lds;
   h->num_cu = ncu;
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+      std::string a(prop.gcnArchName);
+      a = a.substr(0, a.find(':'));
+      bool ok = !a.empty();
+      for (char c : a) ok = ok && key_char_ok(c) && c != '/';
+      if (ok) h->arch = a;
+    } else {
+      (void)hipGetLastError();
+    }
+  }
   if (lds > 65536 && set_max_lds((size_t)lds) != hipSuccess) {
     (void)hipGetLastError();
     h->lds_limit = 65536;
@@ -1527,18 +1646,23 @@ clomp_status_t clomp_solve_batch(clomp_handle_t h, const clomp_instance_t* inst,
     build_plan(h, inst, count, bf16, P, scan_kb, pass_kb);
   }
   if (!cached && (h->params.flags & CLOMP_FLAG_AUTOTUNE) && P.nbig > 0) {
-    double bulk = 0.0;
-    for (int q = 0; q < P.nbig; ++q)
-      bulk += (double)P.insts[q].m * P.insts[q].n * (bf16 ? 2.0 : 4.0);
-    const std::string key = tune_key(P, bf16, h->params.method, bulk);
+    const std::string key = tune_key(P, bf16, h->params.method, h->arch);
     auto it = h->tuned.find(key);
     int kb = 0;
     if (it != h->tuned.end()) {
       kb = it->second;
     } else {
-      if ((s = autotune(h, inst, count, bf16, st, P.hflow, scan_kb, pass_kb, &kb)) != CLOMP_OK)
+      {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto g = g_tune.find(key);
+        if (g != g_tune.end()) kb = g->second;
+      }
+      if (kb == 0 &&
+          (s = autotune(h, inst, count, bf16, st, P.hflow, scan_kb, pass_kb, &kb)) != CLOMP_OK)
         return s;
       h->tuned[key] = kb;
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune[key] = kb;
     }
     if (P.hflow) pass_kb = kb; else scan_kb = kb;
     build_plan(h, inst, count, bf16, P, scan_kb, pass_kb);
