@@ -2385,6 +2385,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_loop_kernel(
         wave_sync();
         const float bb = (lane < t1) ? bsh[lane] : 0.f;
         const float* grow = Gq + (size_t)(lane < ke ? lane : 0) * ldq;
+        const int t1r = (t1 + 3) & ~3;   // columns read: whole chunks of 4 (within ldq)
         int bufi = cur;
         for (int it = 0; it < T; ++it) {
           b1p *= beta1;
@@ -2393,7 +2394,43 @@ __global__ __launch_bounds__(kSmallThreads) void small_loop_kernel(
           const float ibc2 = __builtin_amdgcn_rcpf((float)(1.0 - b2p));
           const float* sc = sbuf[bufi];
           float acc[4] = {0.f, 0.f, 0.f, 0.f};
-          for (int c = 0; c < t1; c += 4) {
+          // the row of G times s in 4-float chunks, in chunk order; groups of
+          // four (then two, then one) chunks issue their LDS reads before the
+          // first FMA, so a step waits for one LDS round trip per 16 columns
+          // (plus at most two for the tail), not one per 4
+          int c = 0;
+          for (; c + 16 <= t1r; c += 16) {
+            float4 g4[4], s4[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              g4[u] = *reinterpret_cast<const float4*>(grow + c + 4 * u);
+              s4[u] = *reinterpret_cast<const float4*>(sc + c + 4 * u);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              acc[0] = fmaf(g4[u].x, s4[u].x, acc[0]);
+              acc[1] = fmaf(g4[u].y, s4[u].y, acc[1]);
+              acc[2] = fmaf(g4[u].z, s4[u].z, acc[2]);
+              acc[3] = fmaf(g4[u].w, s4[u].w, acc[3]);
+            }
+          }
+          if (c + 8 <= t1r) {
+            float4 g4[2], s4[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+              g4[u] = *reinterpret_cast<const float4*>(grow + c + 4 * u);
+              s4[u] = *reinterpret_cast<const float4*>(sc + c + 4 * u);
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+              acc[0] = fmaf(g4[u].x, s4[u].x, acc[0]);
+              acc[1] = fmaf(g4[u].y, s4[u].y, acc[1]);
+              acc[2] = fmaf(g4[u].z, s4[u].z, acc[2]);
+              acc[3] = fmaf(g4[u].w, s4[u].w, acc[3]);
+            }
+            c += 8;
+          }
+          if (c < t1r) {   // at most one chunk left
             const float4 g4 = *reinterpret_cast<const float4*>(grow + c);
             const float4 s4 = *reinterpret_cast<const float4*>(sc + c);
             acc[0] = fmaf(g4.x, s4.x, acc[0]);
