@@ -1067,32 +1067,81 @@ constexpr int kQrSteps = 2;
 // Apply the stored reflectors H_0 .. H_{t1-1} to v (length mr) and solve
 // R d = (Q^T v)[0 .. t1), d into out.  Reflector c is column c of M from
 // row c on, with squared norm vn[c] (0: skipped).
+// Back substitution R d = v[0 .. t1) by wave 0 alone (the other waves pass
+// through); R has diagonal Rd and strictly-upper entries M[c + cc mr].  The
+// caller synchronises the workgroup afterwards.
+__device__ void qr_back_substitute(const float* M, const float* Rd, const float* v, float* out,
+                                   int mr, int t1) {
+  if ((threadIdx.x >> 6) != 0) return;
+  const int lane = threadIdx.x & 63;
+  for (int c = t1 - 1; c >= 0; --c) {
+    float sacc = 0.f;
+    for (int cc = c + 1 + lane; cc < t1; cc += 64) sacc = fmaf(M[c + (long long)cc * mr], out[cc], sacc);
+    sacc = wave_sum(sacc);
+    if (lane == 0) {
+      const float dd = Rd[c];
+      out[c] = (dd != 0.f) ? (v[c] - sacc) / dd : 0.f;
+    }
+    wave_sync();   // out[c] is read by every lane of the next rows
+  }
+}
+
+// Systems of up to kQrWaveRows rows apply the reflectors in wave 0 alone:
+// lane l keeps rows l, l + 64, ... of v for all of them, so only the wave's
+// own reduction orders the steps (no workgroup barrier per reflector).
+constexpr int kQrWaveRows = 256;
+
 __device__ void qr_apply_solve(const float* M, const float* Rd, const float* vn, float* v,
                                float* out, int mr, int t1, float* red) {
-  for (int c = 0; c < t1; ++c) {
-    const float* Mc = M + (long long)c * mr;
-    float p = 0.f;
-    for (int i = c + threadIdx.x; i < mr; i += kBlock) p = fmaf(Mc[i], v[i], p);
-    const float d = block_sum(p, red);
-    if (vn[c] > 0.f) {
-      const float f = 2.f * d / vn[c];
-      for (int i = c + threadIdx.x; i < mr; i += kBlock) v[i] = fmaf(-f, Mc[i], v[i]);
-    }
-    __syncthreads();
-  }
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  for (int c = t1 - 1; c >= 0; --c) {
-    if (wv == 0) {
-      float sacc = 0.f;
-      for (int cc = c + 1 + lane; cc < t1; cc += 64) sacc = fmaf(M[c + (long long)cc * mr], out[cc], sacc);
-      sacc = wave_sum(sacc);
-      if (lane == 0) {
-        const float dd = Rd[c];
-        out[c] = (dd != 0.f) ? (v[c] - sacc) / dd : 0.f;
+  if (mr <= kQrWaveRows) {
+    if ((threadIdx.x >> 6) == 0) {
+      const int lane = threadIdx.x & 63;
+      for (int c = 0; c < t1; ++c) {
+        const float* Mc = M + (long long)c * mr;
+        float p = 0.f;
+        for (int i = lane; i < mr; i += 64)
+          if (i >= c) p = fmaf(Mc[i], v[i], p);
+        const float d = wave_sum(p);
+        if (vn[c] > 0.f) {
+          const float f = 2.f * d / vn[c];
+          for (int i = lane; i < mr; i += 64)
+            if (i >= c) v[i] = fmaf(-f, Mc[i], v[i]);
+        }
       }
+      wave_sync();   // v[0 .. t1) is read across lanes below
     }
-    __syncthreads();
+  } else {
+    for (int c = 0; c < t1; ++c) {
+      const float* Mc = M + (long long)c * mr;
+      float p = 0.f;
+      for (int i = c + threadIdx.x; i < mr; i += kBlock) p = fmaf(Mc[i], v[i], p);
+      const float d = block_sum(p, red);
+      if (vn[c] > 0.f) {
+        const float f = 2.f * d / vn[c];
+        for (int i = c + threadIdx.x; i < mr; i += kBlock) v[i] = fmaf(-f, Mc[i], v[i]);
+      }
+      __syncthreads();
+    }
+  }
+  qr_back_substitute(M, Rd, v, out, mr, t1);
+  __syncthreads();
+}
+
+// Reflector c (Mc, rows c .. mr-1) applied to the targets c+1 .. t1 (columns
+// of M, then y as target t1): QG lanes share a target, so a wave takes 64/QG
+// targets at a time and each lane handles rows c + g, c + g + QG, ...
+template <int QG>
+__device__ void qr_apply_reflector(const float* Mc, float* M, float* yv, int c, int mr, int t1,
+                                   float inv) {
+  constexpr int kPerWave = 64 / QG;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int g = lane % QG, grp = lane / QG;
+  for (int cc = c + 1 + wv * kPerWave + grp; cc <= t1; cc += kWaves * kPerWave) {
+    float* tgt = (cc < t1) ? (M + (long long)cc * mr) : yv;
+    float d = 0.f;
+    for (int i = c + g; i < mr; i += QG) d = fmaf(Mc[i], tgt[i], d);
+    d = group_sum<QG>(d) * inv;
+    for (int i = c + g; i < mr; i += QG) tgt[i] = fmaf(-d, Mc[i], tgt[i]);
   }
 }
 
@@ -1114,16 +1163,27 @@ __global__ __launch_bounds__(kBlock) void qr_refine_kernel(const Inst* __restric
   float* xs = Rd + t1;             // t1 solution
   float* vn = xs + t1;             // t1 squared reflector norms
   float* dx = vn + t1;             // t1 refinement correction
-  for (int idx = threadIdx.x; idx < mr * t1; idx += kBlock) {
+  // (four entries per thread per round, their loads issued before the stores)
+  auto m_entry = [&](int idx) {
     const int c = idx / mr, i = idx - c * mr;
-    M[idx] = (i < m) ? I.Am[(long long)I.support[c] * I.ldam + i]
-                     : ((i - m == c) ? sqrtf(tv_diag(I, I.support[c])) : 0.f);
+    return (i < m) ? I.Am[(long long)I.support[c] * I.ldam + i]
+                   : ((i - m == c) ? sqrtf(tv_diag(I, I.support[c])) : 0.f);
+  };
+  {
+    const int tot = mr * t1;
+    int idx = threadIdx.x;
+    for (; idx + 3 * kBlock < tot; idx += 4 * kBlock) {
+      float e[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) e[u] = m_entry(idx + u * kBlock);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) M[idx + u * kBlock] = e[u];
+    }
+    for (; idx < tot; idx += kBlock) M[idx] = m_entry(idx);
   }
   const float* yw = I.r + I.m_pad;
   for (int i = threadIdx.x; i < mr; i += kBlock) yv[i] = (i < m) ? yw[i] : 0.f;
   __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
   bool rank_def = false;
   for (int c = 0; c < t1; ++c) {
     float* Mc = M + (long long)c * mr;
@@ -1151,39 +1211,37 @@ __global__ __launch_bounds__(kBlock) void qr_refine_kernel(const Inst* __restric
       continue;
     }
     const float inv = 2.f / vn2;
-    // apply H = I - 2 v v^T / (v^T v) to columns c+1..t1-1 and y: one wave per
-    // target, lanes over rows
-    for (int cc = c + 1 + wv; cc <= t1; cc += kWaves) {
-      float* tgt = (cc < t1) ? (M + (long long)cc * mr) : yv;
-      float d = 0.f;
-      for (int i = c + lane; i < mr; i += 64) d = fmaf(Mc[i], tgt[i], d);
-      d = wave_sum(d) * inv;
-      for (int i = c + lane; i < mr; i += 64) tgt[i] = fmaf(-d, Mc[i], tgt[i]);
-    }
+    // apply H = I - 2 v v^T / (v^T v) to columns c+1..t1-1 and y (target
+    // t1): a group of QG lanes per target, lanes over rows, 64 / QG targets
+    // per wave at a time
+    if (mr <= 128)
+      qr_apply_reflector<16>(Mc, M, yv, c, mr, t1, inv);
+    else if (mr <= 256)
+      qr_apply_reflector<32>(Mc, M, yv, c, mr, t1, inv);
+    else
+      qr_apply_reflector<64>(Mc, M, yv, c, mr, t1, inv);
     __syncthreads();
   }
-  // R has diagonal Rd[c] and strictly-upper entries M[c, cc] (cc > c).
-  // back substitution, one row at a time (wave 0 reduces)
-  for (int c = t1 - 1; c >= 0; --c) {
-    if (wv == 0) {
-      float sacc = 0.f;
-      for (int cc = c + 1 + lane; cc < t1; cc += 64) sacc = fmaf(M[c + (long long)cc * mr], xs[cc], sacc);
-      sacc = wave_sum(sacc);
-      if (lane == 0) {
-        const float d = Rd[c];
-        xs[c] = (d != 0.f) ? (yv[c] - sacc) / d : 0.f;
-      }
-    }
-    __syncthreads();
-  }
+  // R has diagonal Rd[c] and strictly-upper entries M[c, cc] (cc > c)
+  qr_back_substitute(M, Rd, yv, xs, mr, t1);
+  __syncthreads();
   // iterative refinement: r = y - A_S x in FP64 from the master columns
   // (stacked prior rows: r = -sqrt(lambda_c) x_c), correction from the factors
   for (int step = 0; step < kQrSteps && !rank_def; ++step) {
     for (int i = threadIdx.x; i < mr; i += kBlock) {
       double acc;
       if (i < m) {
+        // eight column loads in flight, subtracted in column order
         acc = (double)yw[i];
-        for (int c = 0; c < t1; ++c)
+        int c = 0;
+        for (; c + 8 <= t1; c += 8) {
+          float a[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) a[u] = I.Am[(long long)I.support[c + u] * I.ldam + i];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc -= (double)a[u] * (double)xs[c + u];
+        }
+        for (; c < t1; ++c)
           acc -= (double)I.Am[(long long)I.support[c] * I.ldam + i] * (double)xs[c];
       } else {
         const int c = i - m;
@@ -2228,12 +2286,6 @@ __global__ __launch_bounds__(kBlock) void shared_diag_kernel(const Inst* __restr
 constexpr int kSmallThreads = 512;
 constexpr int kSmallWaves = kSmallThreads / 64;
 constexpr int kSmallDots = (kSmallMaxK + 2 + kSmallWaves - 1) / kSmallWaves;   // per wave
-
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 template <typename TA, bool OMP>
 __global__ __launch_bounds__(kSmallThreads) void small_loop_kernel(
