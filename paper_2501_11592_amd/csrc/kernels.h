@@ -59,11 +59,11 @@ hipError_t launch_paper_select(const Inst* dc, int nact, int it, int last, float
                                float lr_rel, float beta1, float beta2, float bc1, float bc2,
                                float eps_rel, int nmax, hipStream_t s);
 
-// Fused greedy loop of the signals list[0..count): one 256-thread workgroup
-// per signal with its dictionary in LDS (k_eff <= kSmallMaxK, dynamic LDS of
-// small_lds_bytes for the largest signal).
-hipError_t launch_small(int bf16, int omp, const Inst* d, const int* list, int count, int T,
-                        float beta1, float beta2, float lr_rel, float eps_rel, size_t lds,
+// Fused greedy loop of the signals list[0..count): one workgroup per signal
+// with its dictionary in LDS (k_eff <= kSmallMaxK; kmax >= every k_eff of the
+// list; dynamic LDS of small_lds_bytes for the largest signal).
+hipError_t launch_small(int bf16, int omp, const Inst* d, const int* list, int count, int kmax,
+                        int T, float beta1, float beta2, float lr_rel, float eps_rel, size_t lds,
                         hipStream_t s);
 
 // correlation-update schedule (few large signals)

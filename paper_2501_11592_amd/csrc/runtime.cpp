@@ -1090,7 +1090,9 @@ clomp_status_t launch_all(clomp_ctx* h, const Plan& P, int bf16, hipStream_t st)
   if (!P.small_list.empty()) {
     const int* d_small = reinterpret_cast<const int*>(tb + P.off_small);
     PhaseScope ps(h, PH_FUSED, st);
-    HIP_TRY(launch_small(bf16, omp, d_insts, d_small, (int)P.small_list.size(),
+    int kmax = 1;
+    for (int q : P.small_list) kmax = std::max(kmax, P.insts[q].k_eff);
+    HIP_TRY(launch_small(bf16, omp, d_insts, d_small, (int)P.small_list.size(), kmax,
                          prm.inner_steps, prm.beta1, prm.beta2, prm.lr_rel, prm.eps_rel,
                          P.small_lds, st),
             "small");

@@ -2287,7 +2287,28 @@ constexpr int kSmallThreads = 512;
 constexpr int kSmallWaves = kSmallThreads / 64;
 constexpr int kSmallDots = (kSmallMaxK + 2 + kSmallWaves - 1) / kSmallWaves;   // per wave
 
-template <typename TA, bool OMP>
+// Row r of G times s in one Adam step of the fused loop: lane r holds its row
+// in registers (grow_r, zero beyond t+1) and takes s_c from lane c, in
+// blocks of eight columns up to t+1, summed in column order into acc[c % 4].
+template <int KR>
+__device__ inline void small_row_times_s(const float (&grow_r)[KR], float sv, int t1,
+                                         float (&acc)[4]) {
+#pragma unroll
+  for (int b = 0; b < KR / 8; ++b) {
+    if (8 * b < t1) {
+      float sc[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        sc[u] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sv), 8 * b + u));
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u & 3] = fmaf(grow_r[8 * b + u], sc[u], acc[u & 3]);
+    }
+  }
+}
+
+// KR: register row length of the Adam step (8, 16, 32 or 64, at least the
+// batch's largest k_eff; OMP ignores it)
+template <typename TA, bool OMP, int KR>
 __global__ __launch_bounds__(kSmallThreads) void small_loop_kernel(
     const Inst* __restrict__ insts, const int* __restrict__ list, int T, float beta1,
     float beta2, float lr_rel, float eps_rel) {
@@ -2437,59 +2458,18 @@ __global__ __launch_bounds__(kSmallThreads) void small_loop_kernel(
         wave_sync();
         const float bb = (lane < t1) ? bsh[lane] : 0.f;
         const float* grow = Gq + (size_t)(lane < ke ? lane : 0) * ldq;
-        const int t1r = (t1 + 3) & ~3;   // columns read: whole chunks of 4 (within ldq)
-        int bufi = cur;
+        // the row of G in registers for the T steps (columns < t+1; the
+        // rest zero), so a step reads no LDS: s_c comes from lane c
+        float grow_r[KR];
+#pragma unroll
+        for (int c = 0; c < KR; ++c) grow_r[c] = (c < t1) ? grow[c] : 0.f;
         for (int it = 0; it < T; ++it) {
           b1p *= beta1;
           b2p *= beta2;
           const float ibc1 = __builtin_amdgcn_rcpf((float)(1.0 - b1p));
           const float ibc2 = __builtin_amdgcn_rcpf((float)(1.0 - b2p));
-          const float* sc = sbuf[bufi];
           float acc[4] = {0.f, 0.f, 0.f, 0.f};
-          // the row of G times s in 4-float chunks, in chunk order; groups of
-          // four (then two, then one) chunks issue their LDS reads before the
-          // first FMA, so a step waits for one LDS round trip per 16 columns
-          // (plus at most two for the tail), not one per 4
-          int c = 0;
-          for (; c + 16 <= t1r; c += 16) {
-            float4 g4[4], s4[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              g4[u] = *reinterpret_cast<const float4*>(grow + c + 4 * u);
-              s4[u] = *reinterpret_cast<const float4*>(sc + c + 4 * u);
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              acc[0] = fmaf(g4[u].x, s4[u].x, acc[0]);
-              acc[1] = fmaf(g4[u].y, s4[u].y, acc[1]);
-              acc[2] = fmaf(g4[u].z, s4[u].z, acc[2]);
-              acc[3] = fmaf(g4[u].w, s4[u].w, acc[3]);
-            }
-          }
-          if (c + 8 <= t1r) {
-            float4 g4[2], s4[2];
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-              g4[u] = *reinterpret_cast<const float4*>(grow + c + 4 * u);
-              s4[u] = *reinterpret_cast<const float4*>(sc + c + 4 * u);
-            }
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-              acc[0] = fmaf(g4[u].x, s4[u].x, acc[0]);
-              acc[1] = fmaf(g4[u].y, s4[u].y, acc[1]);
-              acc[2] = fmaf(g4[u].z, s4[u].z, acc[2]);
-              acc[3] = fmaf(g4[u].w, s4[u].w, acc[3]);
-            }
-            c += 8;
-          }
-          if (c < t1r) {   // at most one chunk left
-            const float4 g4 = *reinterpret_cast<const float4*>(grow + c);
-            const float4 s4 = *reinterpret_cast<const float4*>(sc + c);
-            acc[0] = fmaf(g4.x, s4.x, acc[0]);
-            acc[1] = fmaf(g4.y, s4.y, acc[1]);
-            acc[2] = fmaf(g4.z, s4.z, acc[2]);
-            acc[3] = fmaf(g4.w, s4.w, acc[3]);
-          }
+          small_row_times_s<KR>(grow_r, sv, t1, acc);
           if (lane < t1) {
             const float gr = ((acc[0] + acc[1]) + (acc[2] + acc[3])) - bb;
             mo = beta1 * mo + (1.f - beta1) * gr;
@@ -2497,11 +2477,11 @@ __global__ __launch_bounds__(kSmallThreads) void small_loop_kernel(
             const float mh = mo * ibc1;
             const float vh = ve * ibc2;
             sv = sv - lr * mh * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(vh) + eps);
-            sbuf[bufi ^ 1][lane] = sv;
           }
-          wave_sync();
-          bufi ^= 1;
         }
+        // s for the residual and the next iteration: the buffer that every
+        // thread selects below (cur ^ (T & 1))
+        if (lane < t1) sbuf[cur ^ (T & 1)][lane] = sv;
       } else {
         // bordered inverse: v = Ginv g, delta = gamma - g.v,
         // alpha = (b_t - g.x) / delta, x <- [x - alpha v; alpha]
@@ -3595,26 +3575,41 @@ static hipError_t raise_dynamic_lds(const void* const* fns, size_t nf, size_t by
   return hipSuccess;
 }
 
-hipError_t launch_small(int bf16, int omp, const Inst* d, const int* list, int count, int T,
-                        float beta1, float beta2, float lr_rel, float eps_rel, size_t lds,
+template <typename TA, int KR>
+static void small_clomp(dim3 g, dim3 b, size_t lds, hipStream_t s, const Inst* d,
+                        const int* list, int T, float beta1, float beta2, float lr_rel,
+                        float eps_rel) {
+  CLOMP_LAUNCH((small_loop_kernel<TA, false, KR>), g, b, lds, s, d, list, T, beta1, beta2,
+               lr_rel, eps_rel);
+}
+
+template <typename TA>
+static void small_dispatch(int omp, int kmax, dim3 g, dim3 b, size_t lds, hipStream_t s,
+                           const Inst* d, const int* list, int T, float beta1, float beta2,
+                           float lr_rel, float eps_rel) {
+  if (omp)
+    CLOMP_LAUNCH((small_loop_kernel<TA, true, 8>), g, b, lds, s, d, list, T, beta1, beta2,
+                 lr_rel, eps_rel);
+  else if (kmax <= 8)
+    small_clomp<TA, 8>(g, b, lds, s, d, list, T, beta1, beta2, lr_rel, eps_rel);
+  else if (kmax <= 16)
+    small_clomp<TA, 16>(g, b, lds, s, d, list, T, beta1, beta2, lr_rel, eps_rel);
+  else if (kmax <= 32)
+    small_clomp<TA, 32>(g, b, lds, s, d, list, T, beta1, beta2, lr_rel, eps_rel);
+  else
+    small_clomp<TA, 64>(g, b, lds, s, d, list, T, beta1, beta2, lr_rel, eps_rel);
+}
+
+hipError_t launch_small(int bf16, int omp, const Inst* d, const int* list, int count, int kmax,
+                        int T, float beta1, float beta2, float lr_rel, float eps_rel, size_t lds,
                         hipStream_t s) {
   if (count <= 0) return nothing_to_launch(s);
+  if (kmax < 1 || kmax > kSmallMaxK) return hipErrorInvalidValue;
   const dim3 g(count), b(kSmallThreads);
-  if (bf16) {
-    if (omp)
-      CLOMP_LAUNCH((small_loop_kernel<uint16_t, true>), g, b, lds, s, d, list, T, beta1, beta2,
-                   lr_rel, eps_rel);
-    else
-      CLOMP_LAUNCH((small_loop_kernel<uint16_t, false>), g, b, lds, s, d, list, T, beta1, beta2,
-                   lr_rel, eps_rel);
-  } else {
-    if (omp)
-      CLOMP_LAUNCH((small_loop_kernel<float, true>), g, b, lds, s, d, list, T, beta1, beta2,
-                   lr_rel, eps_rel);
-    else
-      CLOMP_LAUNCH((small_loop_kernel<float, false>), g, b, lds, s, d, list, T, beta1, beta2,
-                   lr_rel, eps_rel);
-  }
+  if (bf16)
+    small_dispatch<uint16_t>(omp, kmax, g, b, lds, s, d, list, T, beta1, beta2, lr_rel, eps_rel);
+  else
+    small_dispatch<float>(omp, kmax, g, b, lds, s, d, list, T, beta1, beta2, lr_rel, eps_rel);
   return hipGetLastError();
 }
 
@@ -3725,9 +3720,16 @@ hipError_t launch_iht_select(const Inst* dc, int nact, int mode, int nmax, hipSt
 hipError_t set_max_lds(size_t bytes) {
   // Raise the dynamic-LDS ceiling of the kernels that stage vectors.
   const void* fns[] = {
-      (const void*)small_loop_kernel<float, false>, (const void*)small_loop_kernel<float, true>,
-      (const void*)small_loop_kernel<uint16_t, false>,
-      (const void*)small_loop_kernel<uint16_t, true>,
+      (const void*)small_loop_kernel<float, true, 8>,
+      (const void*)small_loop_kernel<float, false, 8>,
+      (const void*)small_loop_kernel<float, false, 16>,
+      (const void*)small_loop_kernel<float, false, 32>,
+      (const void*)small_loop_kernel<float, false, 64>,
+      (const void*)small_loop_kernel<uint16_t, true, 8>,
+      (const void*)small_loop_kernel<uint16_t, false, 8>,
+      (const void*)small_loop_kernel<uint16_t, false, 16>,
+      (const void*)small_loop_kernel<uint16_t, false, 32>,
+      (const void*)small_loop_kernel<uint16_t, false, 64>,
       (const void*)iht_grad_kernel<float, 4>, (const void*)iht_grad_kernel<float, 8>,
       (const void*)iht_grad_kernel<float, 16>, (const void*)iht_grad_kernel<float, 32>,
       (const void*)iht_grad_kernel<float, 64>, (const void*)iht_grad_kernel<uint16_t, 4>,
