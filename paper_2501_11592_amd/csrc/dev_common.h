@@ -24,6 +24,9 @@ namespace clomp {
 
 constexpr int kBlock = 256;     // threads per workgroup for every solver kernel
 constexpr int kTeamRows = 16;   // coefficient rows per team member
+// dynamic LDS of the split-row Adam (256 < t+1 <= 1024): s padded to 4, and
+// P * ceil((t+1)/4) <= 1024 partial float4s
+constexpr int kSplitLdsFloats = 1024 + 4 * 1024;
 constexpr int kTeamMax = 128;   // team members per signal (2048 rows)
 // IHT gradient scan: at most this many floats of r are staged in LDS per
 // workgroup; longer columns are split into slices of m whose partial dots

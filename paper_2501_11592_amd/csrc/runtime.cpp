@@ -621,7 +621,7 @@ void build_plan(clomp_ctx* h, const clomp_instance_t* inst, int count, int bf16,
       const bool omp = prm.method == CLOMP_METHOD_OMP;
       const size_t t1 = (size_t)c.kmax;
       size_t tl = std::max((size_t)c.m_pad_max, (omp ? 6 : 1) * t1);
-      if (!omp && t1 > 256) tl = std::max(tl, (size_t)2048);
+      if (!omp && t1 > 256) tl = std::max(tl, (size_t)kSplitLdsFloats);
       tl = std::max(tl, t1 + 4 + 32);
       c.team_occ = team_occupancy(h, bf16, c.lpa, omp ? 1 : 0, tl * sizeof(float));
     }
@@ -819,8 +819,9 @@ clomp_status_t launch_hflow(clomp_ctx* h, const Plan& P, int bf16, hipStream_t s
         // while the teams stay far below the CU count (all resident at once)
         size_t lds = (size_t)c.m_pad_max * sizeof(float);
         lds = std::max(lds, (omp ? 6 : 1) * t1 * sizeof(float));
-        // split-row Adam (256 < t+1 <= 1024): s[R] and partials [1024/R][R]
-        if (!omp && t1 > 256 && t1 <= 1024) lds = std::max(lds, (size_t)2048 * sizeof(float));
+        // split-row Adam (256 < t+1 <= 1024): s and the partial sums
+        if (!omp && t1 > 256 && t1 <= 1024)
+          lds = std::max(lds, (size_t)kSplitLdsFloats * sizeof(float));
         int W = 1;
         if (t1 > (size_t)h->team_min_rows) {
           const int want = (int)((t1 + 15) / 16);

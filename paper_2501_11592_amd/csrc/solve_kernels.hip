@@ -540,71 +540,117 @@ __device__ void adam_global_body(const Inst& I, int t, int T, float beta1, float
   }
 }
 
-// Fused-launch variant for 256 < t+1 <= 1024 on one 1024-thread workgroup:
-// P = 1024 / R threads per row (R = t+1 rounded up to a power of two), thread
-// (p, r) streaming the columns c = p, p+P, ... of row r from L2 (coalesced
-// along rows); the P partials of a row are added in LDS in a fixed order.
-// `lds` holds s[R] and the partials [P][R].
+// Fused-launch variant for 256 < t+1 <= 1024 on one 1024-thread workgroup.
+// The rows are taken four at a time: thread (p, q) streams rows 4q .. 4q+3 of
+// the columns c = p, p+P, ... (one 16-byte load per column; G is column-major,
+// so a column's rows are contiguous, and ldg is a multiple of 4), with P =
+// the most column partitions that keep P * ceil((t+1)/4) <= 1024 threads.
+// Eight loads per thread are in flight, so a step waits for a few memory
+// round trips instead of one per four columns.  The P partial float4s of a
+// row group are added in LDS in a fixed order by thread (0, q), which owns
+// the Adam state of its four rows.  `lds` holds s (t+1 rounded up to 4) and
+// the partials [P][ceil((t+1)/4)] as float4: at most kSplitLdsFloats.
 __device__ void adam_split_body(const Inst& I, int t, int T, float beta1, float beta2,
                                 float* lds) {
   constexpr int NT = 1024;   // the fused launch's workgroup size
   const int t1 = t + 1;
-  int R = 256;
-  while (R < t1) R <<= 1;
-  const int P = NT / R;
+  const int g4 = (t1 + 3) >> 2;        // row groups (<= 256)
+  const int t4 = 4 * g4;
+  int P = 1;
+  while (2 * P * g4 <= NT) P <<= 1;
   const int tid = threadIdx.x;
-  const int p = tid / R, r = tid - p * R;
-  const bool own = p == 0 && r < t1;
+  const int p = tid / g4, q = tid - p * g4;
+  const bool active = p < P;
+  const bool own = p == 0;             // owner of rows 4q .. 4q+3 (those < t1)
   const long long ldg = I.ldg;
   const float* __restrict__ G = I.G;
-  float* ssh = lds;            // [R]
-  float* part = lds + R;       // [P][R]
-  float mo = 0.f, ve = 0.f, bb = 0.f;
-  if (tid < R) ssh[tid] = (tid < t1) ? I.s[tid] : 0.f;
-  if (own) {
-    mo = I.mo[r];
-    ve = I.ve[r];
-    bb = I.b[r];
+  float* ssh = lds;                                     // [t4]
+  float4* part = reinterpret_cast<float4*>(lds + t4);   // [P][g4]
+  float mo[4], ve[4], bb[4];
+  for (int c = tid; c < t4; c += NT) ssh[c] = (c < t1) ? I.s[c] : 0.f;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int r = 4 * q + e;
+    const bool ok = own && r < t1;
+    mo[e] = ok ? I.mo[r] : 0.f;
+    ve[e] = ok ? I.ve[r] : 0.f;
+    bb[e] = ok ? I.b[r] : 0.f;
   }
   const float lr = I.st->lr, eps = I.st->eps;
   const int step0 = I.st->step;
   double b1p = pow((double)beta1, (double)step0);
   double b2p = pow((double)beta2, (double)step0);
+  const float* gcol = G + 4 * q;       // rows 4q .. 4q+3 of column 0
   __syncthreads();
   for (int it = 0; it < T; ++it) {
     b1p *= beta1;
     b2p *= beta2;
     const float ibc1 = __builtin_amdgcn_rcpf((float)(1.0 - b1p));
     const float ibc2 = __builtin_amdgcn_rcpf((float)(1.0 - b2p));
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-    if (r < t1) {
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
+    if (active) {
       int c = p;
-      for (; c + 3 * P < t1; c += 4 * P) {
-        a0 = fmaf(G[(long long)c * ldg + r], ssh[c], a0);
-        a1 = fmaf(G[(long long)(c + P) * ldg + r], ssh[c + P], a1);
-        a2 = fmaf(G[(long long)(c + 2 * P) * ldg + r], ssh[c + 2 * P], a2);
-        a3 = fmaf(G[(long long)(c + 3 * P) * ldg + r], ssh[c + 3 * P], a3);
+      for (; c + 7 * P < t1; c += 8 * P) {
+        float4 gv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          gv[u] = *reinterpret_cast<const float4*>(gcol + (long long)(c + u * P) * ldg);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const float sc = ssh[c + u * P];
+          float4& acc = (u & 1) ? b : a;
+          acc.x = fmaf(gv[u].x, sc, acc.x);
+          acc.y = fmaf(gv[u].y, sc, acc.y);
+          acc.z = fmaf(gv[u].z, sc, acc.z);
+          acc.w = fmaf(gv[u].w, sc, acc.w);
+        }
       }
-      for (; c < t1; c += P) a0 = fmaf(G[(long long)c * ldg + r], ssh[c], a0);
+      for (; c < t1; c += P) {
+        const float4 gv = *reinterpret_cast<const float4*>(gcol + (long long)c * ldg);
+        const float sc = ssh[c];
+        a.x = fmaf(gv.x, sc, a.x);
+        a.y = fmaf(gv.y, sc, a.y);
+        a.z = fmaf(gv.z, sc, a.z);
+        a.w = fmaf(gv.w, sc, a.w);
+      }
+      part[p * g4 + q] = make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
     }
-    part[p * R + r] = (a0 + a1) + (a2 + a3);
     __syncthreads();
     if (own) {
-      float gs = 0.f;
-      for (int q = 0; q < P; ++q) gs += part[q * R + r];
-      const float gr = gs - bb;
-      mo = beta1 * mo + (1.f - beta1) * gr;
-      ve = beta2 * ve + (1.f - beta2) * (gr * gr);
-      const float mh = mo * ibc1;
-      const float vh = ve * ibc2;
-      ssh[r] = ssh[r] - lr * mh * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(vh) + eps);
+      float4 gs = part[q];
+      for (int pp = 1; pp < P; ++pp) {
+        const float4 v = part[pp * g4 + q];
+        gs.x += v.x;
+        gs.y += v.y;
+        gs.z += v.z;
+        gs.w += v.w;
+      }
+      const float g[4] = {gs.x, gs.y, gs.z, gs.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = 4 * q + e;
+        if (r < t1) {
+          const float gr = g[e] - bb[e];
+          mo[e] = beta1 * mo[e] + (1.f - beta1) * gr;
+          ve[e] = beta2 * ve[e] + (1.f - beta2) * (gr * gr);
+          const float mh = mo[e] * ibc1;
+          const float vh = ve[e] * ibc2;
+          ssh[r] = ssh[r] - lr * mh * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(vh) + eps);
+        }
+      }
     }
     __syncthreads();
   }
   if (own) {
-    I.s[r] = ssh[r];
-    I.mo[r] = mo;
-    I.ve[r] = ve;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = 4 * q + e;
+      if (r < t1) {
+        I.s[r] = ssh[r];
+        I.mo[r] = mo[e];
+        I.ve[r] = ve[e];
+      }
+    }
   }
   if (tid == 0) I.st->step = step0 + T;
 }
