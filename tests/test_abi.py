@@ -6,7 +6,6 @@ import ctypes
 import os
 import re
 
-import numpy as np
 import pytest
 
 from paper_2501_11592_amd import clomp as C

@@ -12,11 +12,11 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import clomp_fp64, omp_fp64, lstsq_support
+from oracle import clomp_fp64, omp_fp64
 from paper_2501_11592_amd import clomp as C
 from paper_2501_11592_amd import workloads as W
 from tests.gpu_helpers import (PARAMS, FP32_DELTA, FP32_U, BF16_DELTA, BF16_U, dev,
-                               oracle_final_x, compare, rel_err, fp64_resid)
+                               oracle_final_x, compare, rel_err)
 
 pytestmark = pytest.mark.gpu
 

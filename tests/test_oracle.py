@@ -6,7 +6,6 @@ library routine (LAPACK SVD least squares, scikit-learn's OMP, torch autograd
 and torch.optim.Adam) or brute force.
 """
 
-import itertools
 import math
 import os
 
